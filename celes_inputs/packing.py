@@ -1,0 +1,97 @@
+"""Seeded sphere packings (random sequential addition) in a box.
+
+Lengths are in nanometres throughout.  All randomness comes from numpy's PCG64
+generator seeded explicitly, so a (seed, parameters) tuple always yields the
+same packing on any machine.
+"""
+import numpy as np
+
+
+def lognormal_radii(rng, n, mean, rel_sigma):
+    """Radii with E[R] = mean and log-standard-deviation rel_sigma.
+
+    The log-mean is shifted by -sigma^2/2 so that the arithmetic mean of the
+    distribution equals `mean`.
+    """
+    s = float(rel_sigma)
+    mu = np.log(mean) - 0.5 * s * s
+    return rng.lognormal(mean=mu, sigma=s, size=n)
+
+
+def slab_side_for_fraction(n, volume_fraction, thickness, mean, rel_sigma):
+    """Lateral side of a square slab holding n lognormal spheres at a given
+    volume fraction: side = sqrt(n <V> / (vf * t)), with
+    <R^3> = mean^3 exp(3 sigma^2) for the shifted lognormal law."""
+    r3 = mean ** 3 * np.exp(3.0 * rel_sigma ** 2)
+    v = 4.0 / 3.0 * np.pi * r3
+    return float(np.sqrt(n * v / (volume_fraction * thickness)))
+
+
+def _cell_key(c):
+    return (int(c[0]), int(c[1]), int(c[2]))
+
+
+def rsa_box(seed, radii, box, max_attempts_per_sphere=1000, gap=0.0, inside=True):
+    """Random sequential addition of spheres with the given radii into the
+    axis-aligned box [0,bx] x [0,by] x [0,bz].  With inside=True every sphere
+    lies fully inside the box; with inside=False only the centres do (spheres
+    may protrude by up to their radius, so the box volume fraction can reach
+    the bulk RSA range).
+
+    Spheres are placed in the given order.  A candidate centre is drawn
+    uniformly in the shrunken box and rejected if it comes within
+    R_i + R_j + gap of an already placed sphere.  Raises RuntimeError after
+    max_attempts_per_sphere * n total rejections.
+    Returns positions [n, 3] (float64).
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    radii = np.asarray(radii, dtype=np.float64)
+    n = radii.size
+    box = np.asarray(box, dtype=np.float64)
+    rmax = float(radii.max())
+    cell = 2.0 * rmax + gap
+    grid = {}
+    pos = np.zeros((n, 3))
+    budget = max_attempts_per_sphere * n
+    tries = 0
+    for i in range(n):
+        r = radii[i]
+        lo = np.full(3, r) if inside else np.zeros(3)
+        hi = box - r if inside else box.copy()
+        if np.any(hi < lo):
+            raise ValueError("sphere does not fit into the box")
+        while True:
+            tries += 1
+            if tries > budget:
+                raise RuntimeError("random sequential addition did not finish")
+            c = lo + (hi - lo) * rng.random(3)
+            ck = np.floor(c / cell).astype(np.int64)
+            ok = True
+            for dx in (-1, 0, 1):
+                for dy in (-1, 0, 1):
+                    for dz in (-1, 0, 1):
+                        lst = grid.get((ck[0] + dx, ck[1] + dy, ck[2] + dz))
+                        if not lst:
+                            continue
+                        for j in lst:
+                            d = c - pos[j]
+                            if d @ d <= (r + radii[j] + gap) ** 2:
+                                ok = False
+                                break
+                        if not ok:
+                            break
+                    if not ok:
+                        break
+                if not ok:
+                    break
+            if ok:
+                pos[i] = c
+                grid.setdefault(_cell_key(ck), []).append(i)
+                break
+    return pos
+
+
+def uniform_box(seed, n, radius, side, gap=0.0):
+    """n equal spheres of the given radius, centres uniform with each sphere
+    fully inside a cube of the given side, non-overlapping (by rejection)."""
+    return rsa_box(seed, np.full(n, float(radius)), (side, side, side), gap=gap)
