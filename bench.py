@@ -1,0 +1,228 @@
+"""Benchmark of the hot path on one MI355X.
+
+Workload: the 2,000-sphere slab (lognormal radii, mean 150 nm, sigma 10%,
+n = 1.52, volume fraction 0.3, thickness 2 um), lmax = 4, Gaussian beam
+(waist 2 um) at 550 nm, Hankel lookup table at 1 nm, complex128.
+
+A step is one FP64 solve of the master equation by block-diagonal
+preconditioned GMRES to relative residual 1e-8 from a zero initial guess
+(preconditioner set-up is done once before timing and reported separately).
+`value` is the number of pair-multipole updates of W b executed in the timed
+steps, N(N-1) nmax^2 per mat-vec, divided by the wall time of the steps.
+
+Also reported: the mat-vec kernel alone (HIP events on the launch stream, used
+for the roofline), time to residual 1e-6 in FP64 and in mixed precision, and
+the CPU oracle timed on a bounded sample of receiver rows.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "pair-multipole updates/s of W·b; time-to-residual 1e-6, mixed vs FP64"
+PEAK_FP64_VALU_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
+
+
+def flops_per_pair(L, hankel_lut=True):
+    """Floating-point operations per sphere pair of the coupling kernel as it
+    runs (all passes M0 = 0..L, one right-hand side).  Counting: real add,
+    mul or FMA = 1 or 2 flops as (add/mul 1, fma 2); complex multiply 6,
+    complex multiply-accumulate 8; sqrt, divide and sincos 1 each."""
+    def iabs(a):
+        return -a if a < 0 else a
+
+    def pa(l, lp, mu):
+        p = max(iabs(l - lp), mu)
+        p += (l + lp + p) & 1
+        return max(0, (l + lp - p) // 2 + 1) if p <= l + lp else 0
+
+    def pb(l, lp, mu):
+        p = max(iabs(l - lp) + 1, mu)
+        if not ((l + lp + p) & 1):
+            p += 1
+        return max(0, (l + lp - 1 - p) // 2 + 1) if p <= l + lp - 1 else 0
+
+    P = 2 * L
+    total = 0
+    for M0 in range(L + 1):
+        f = 19                                             # geometry
+        f += (4 + 12 * (P + 1)) if hankel_lut else (4 + 6 + 5 * (P - 1))
+        mumax = min(2 * L, L + M0)
+        for mu in range(mumax + 1):
+            if mu > 0:
+                f += 2 + 6                                 # P_mu^mu and e^{i mu phi}
+            ncol = P - mu + 1
+            f += 3 * max(0, ncol - 2) + (2 if ncol >= 2 else 0) + 2 * ncol   # Legendre column + H
+            for sgn in (1, -1):
+                if sgn < 0 and (mu == 0 or M0 == 0):
+                    continue
+                mp = M0 + sgn * mu
+                if iabs(mp) > L:
+                    continue
+                two = M0 > 0 or mu > 0
+                for lp in range(max(1, iabs(mp)), L + 1):
+                    f += 6 * (4 if two else 2)              # source rotations
+                    for l in range(max(1, M0), L + 1):
+                        f += 4 * (pa(l, lp, mu) + pb(l, lp, mu))   # A and B sums
+                        f += 4                               # P = A + iB, Q = A - iB
+                        f += 8 * (4 if two else 2)           # accumulations
+        total += f
+    return total
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--matvec-reps", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--workload", default="slab2000_l4")
+    ap.add_argument("--cuboid-edge", type=float, default=1500.0)
+    ap.add_argument("--hankel", choices=["lut", "direct"], default="lut")
+    ap.add_argument("--profile", action="store_true", help="mat-vec launches only (for rocprofv3)")
+    a = ap.parse_args()
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_1706_02145_amd as P
+    from celes_inputs import workload, random_coefficients
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    w = workload(a.workload)
+    il = w.illumination
+    N, L, nm = w.N, w.lmax, w.nmax
+    updates_per_mv = N * (N - 1) * nm * nm
+    hk = P.CELES_HANKEL_LUT if a.hankel == "lut" else P.CELES_HANKEL_DIRECT
+
+    def problem(**kw):
+        p = P.Problem(w.positions, w.radii, w.n_sphere, w.n0, w.wavelength, L, hankel=hk, lut_dr=w.lut_dr, **kw)
+        if il["kind"] == "gaussian":
+            p.set_gaussian_beam(il["waist"], il["focus"], il["alpha_G"], il["E0"])
+        else:
+            p.set_plane_waves([il["beta"]], [il["alpha"]], [il["pol"]])
+        return p
+
+    t0 = time.perf_counter()
+    p = problem(tol=w.tol, restart=100, maxiter=3000)
+    t_setup = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    if a.cuboid_edge > 0:
+        p.build_preconditioner(a.cuboid_edge)
+    torch.cuda.synchronize()
+    t_pre = time.perf_counter() - t0
+
+    # ---- mat-vec kernel alone (roofline), HIP events on the launch stream ----
+    stream = torch.cuda.current_stream()
+    x = torch.from_numpy(random_coefficients(1, 1, N, nm)[0]).to("cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        p.apply_W(x, y, P.CELES_FP64, stream=stream)
+    torch.cuda.synchronize()
+    reps = a.matvec_reps if not a.profile else 5
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(reps):
+        p.apply_W(x, y, P.CELES_FP64, stream=stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    mv_ms = ev0.elapsed_time(ev1) / reps
+    if a.profile:
+        print(json.dumps({"matvec_ms": mv_ms, "N": N, "lmax": L}))
+        return
+    fpp = flops_per_pair(L, a.hankel == "lut")
+    mv_flops = fpp * N * (N - 1)
+    achieved = mv_flops / (mv_ms * 1e-3) / 1e12
+
+    # ---- timed solves ----
+    for _ in range(a.warmup):
+        p.solve()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = []
+    for _ in range(a.steps):
+        b, info = p.solve()
+        infos.append(info)
+    torch.cuda.synchronize()
+    t_steps = time.perf_counter() - t0
+    matvecs = sum(i["matvecs"] for i in infos)
+    value = matvecs * updates_per_mv / t_steps
+
+    # ---- time to residual 1e-6: FP64 vs mixed (same preconditioner edge) ----
+    ttr = {}
+    if not a.no_mixed:
+        for name, prec in (("fp64", P.CELES_FP64), ("mixed", P.CELES_MIXED)):
+            q = problem(tol=1e-6, precision=prec, restart=100, maxiter=3000, inner_tol=1e-3)
+            if a.cuboid_edge > 0:
+                q.build_preconditioner(a.cuboid_edge)
+            q.solve()   # warm
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            _, inf = q.solve()
+            torch.cuda.synchronize()
+            ttr[name] = {"seconds": time.perf_counter() - t1, "iterations": inf["iterations"],
+                         "rel_residual": inf["rel_residual"]}
+            q.close()
+
+    # ---- CPU oracle on a bounded sample of receiver rows ----
+    cpu = None
+    if not a.no_cpu_baseline:
+        from oracle.translation import apply_W_rows
+        from oracle.lut import lut_for
+        k = 2 * math.pi * w.n0 / w.wavelength
+        lut = lut_for(w.positions, w.radii, k, L, w.lut_dr)
+        xs = random_coefficients(1, 1, N, nm)[0]
+        rows, t_cpu = 0, 0.0
+        t1 = time.perf_counter()
+        while t_cpu < a.cpu_seconds and rows < N:
+            apply_W_rows(w.positions, xs, k, L, [rows], hankel=lut)
+            rows += 1
+            t_cpu = time.perf_counter() - t1
+        cpu = {"value": rows * (N - 1) * nm * nm / t_cpu, "unit": "updates/s", "cores": 1, "kind": "oracle",
+               "sample": f"{rows} of {N} receiver rows of one W.b (same geometry, LUT mode), {t_cpu:.1f} s"}
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "updates/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": 1e3 * t_steps / a.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{w.name}: N={N} RSA slab, radii lognormal(150 nm, 10%), n=1.52, vf 0.3, "
+                               f"t=2 um, lmax={L}, Gaussian beam w=2 um, lambda=550 nm, LUT dr=1 nm, "
+                               f"block-diagonal preconditioned GMRES to 1e-8 (complex128)",
+                   "N": N, "lmax": L, "hankel": a.hankel, "cuboid_edge_nm": a.cuboid_edge},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VALU_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP64_VALU_TFLOPS, "traffic": None},
+        "cpu_baseline": cpu,
+        "matvec_ms": mv_ms,
+        "matvec_updates_per_s": updates_per_mv / (mv_ms * 1e-3),
+        "flops_per_pair": fpp,
+        "solve": {"iterations": infos[-1]["iterations"], "matvecs_per_solve": infos[-1]["matvecs"],
+                  "rel_residual": infos[-1]["rel_residual"], "matvec_share": sum(i["matvec_seconds"] for i in infos) / t_steps},
+        "setup_s": t_setup,
+        "preconditioner_setup_s": t_pre,
+        "time_to_residual_1e-6": ttr,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

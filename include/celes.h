@@ -1,0 +1,211 @@
+/*
+ * celes.h -- C ABI of the MI355X (gfx950) multi-sphere T-matrix library.
+ *
+ * Method: Egel, Pattelli, Mazzamuto, Wiersma, Lemmer, "CELES: CUDA-accelerated
+ * simulation of electromagnetic scattering by large ensembles of spheres"
+ * (JQSRT 2017, arXiv:1706.02145).  Section and equation names below refer to
+ * that paper.
+ *
+ * Conventions shared by every entry point
+ *   - Lengths are in one consistent unit (the tests use nanometres); the
+ *     wavelength is the vacuum wavelength in that unit.
+ *   - Complex numbers are interleaved (re, im) pairs: complex128 = 2 doubles,
+ *     complex64 = 2 floats.
+ *   - Multi-index n = (tau, l, m), tau in {1,2}, l = 1..lmax, m = -l..l
+ *     (Section 2.1).  Linear order (0-based):
+ *         n = (tau-1) lmax(lmax+2) + l(l+1) + m - 1,   nmax = 2 lmax (lmax+2).
+ *   - Coefficient vectors have layout [K][N][nmax] (right-hand side, sphere,
+ *     multi-index), sphere order as given to celes_create.
+ *   - Host pointers are owned by the caller and only read or written during
+ *     the call.  Device pointers (the *_dev arguments) must be HIP device
+ *     memory on the handle's device, owned by the caller.
+ *   - Every int-returning call returns CELES_OK (0) or a negative error code;
+ *     celes_last_error() then describes the failure.  No C++ exception
+ *     crosses this boundary.  Calls on one handle are not thread-safe.
+ */
+#ifndef CELES_H
+#define CELES_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CELES_VERSION 100
+
+/* error codes */
+#define CELES_OK 0
+#define CELES_E_ARG -1          /* invalid argument (null pointer, size < 1, ...) */
+#define CELES_E_OVERLAP -2      /* two spheres overlap: |r_i - r_j| <= R_i + R_j   */
+#define CELES_E_LUT_RANGE -3    /* a pair distance falls outside the Hankel table */
+#define CELES_E_NONFINITE -4    /* NaN or Inf in an input                          */
+#define CELES_E_NOCONV -5       /* solver hit maxiter; best iterate returned       */
+#define CELES_E_BREAKDOWN -6    /* Krylov breakdown / non-finite iterate           */
+#define CELES_E_OOM -7          /* device or host allocation failed                */
+#define CELES_E_DEVICE -8       /* HIP runtime error                               */
+#define CELES_E_UNSUPPORTED -9  /* e.g. lmax beyond the compiled kernels           */
+#define CELES_E_STATE -10       /* call order violated (e.g. solve before incident) */
+
+/* arithmetic of the coupling mat-vec */
+#define CELES_FP64 0            /* complex128 everywhere                            */
+#define CELES_MIXED 1           /* complex64 inner solve, FP64 residual/refinement  */
+
+/* spherical Hankel evaluation inside the mat-vec */
+#define CELES_HANKEL_LUT 0      /* cubic-Hermite lookup table at spacing lut_dr (Section 3.2.2) */
+#define CELES_HANKEL_DIRECT 1   /* upward three-term recurrence from h_0, h_1 per pair          */
+
+#define CELES_MAX_LMAX 6
+
+typedef struct celes_handle celes_handle;
+
+typedef struct celes_options {
+    int precision;          /* CELES_FP64 or CELES_MIXED                                     */
+    int hankel;             /* CELES_HANKEL_LUT or CELES_HANKEL_DIRECT                        */
+    double lut_dr;          /* lookup-table spacing in length units (paper: 1 nm)            */
+    double tol;             /* GMRES relative residual ||T a_in - M b|| / ||T a_in||          */
+    double inner_tol;       /* mixed precision: inner complex64 GMRES tolerance               */
+    int restart;            /* GMRES restart length                                           */
+    int maxiter;            /* total inner iterations allowed                                 */
+    int max_refinements;    /* mixed precision: outer refinement steps allowed                */
+    double cuboid_edge;     /* preconditioner cuboid edge; <= 0 disables the preconditioner   */
+    int device;             /* HIP device ordinal                                             */
+    int verbose;            /* 0 silent, 1 per-restart residuals on stderr                    */
+} celes_options;
+
+typedef struct celes_solve_info {
+    int status;             /* CELES_OK, CELES_E_NOCONV or CELES_E_BREAKDOWN                   */
+    int iterations;         /* inner GMRES iterations (all restarts, all refinements)          */
+    int refinements;        /* outer FP64 refinement steps (mixed) or restarts (FP64)          */
+    int matvecs;            /* coupling mat-vecs performed (any precision)                     */
+    double rel_residual;    /* final true relative residual, evaluated in FP64                 */
+    double seconds;         /* wall time of the solve (excludes preconditioner set-up)         */
+    double matvec_seconds;  /* part of `seconds` spent in the coupling mat-vec kernels         */
+} celes_solve_info;
+
+/* Fill *opt with defaults: FP64, LUT, lut_dr = 1, tol = 1e-8, inner_tol = 1e-4,
+ * restart = 100, maxiter = 2000, max_refinements = 30, cuboid_edge = 0, device 0. */
+void celes_default_options(celes_options* opt);
+
+/* Library version (CELES_VERSION). */
+int celes_version(void);
+
+/* Create a problem (Section 2: N disjoint spheres with centres pos [N][3],
+ * radii radius [N], complex refractive indices n_sphere [N][2] in a medium
+ * of real index n0, vacuum wavelength `wavelength`, multipole cut-off lmax).
+ * Computes the Mie T-matrix of every sphere (Appendix B), the a5/b5 tables
+ * (Appendix A.2) and, in LUT mode, the Hankel table (Section 3.2.2), and
+ * copies the geometry to the device.  On success *h owns device memory until
+ * celes_destroy.  Errors: CELES_E_ARG, CELES_E_NONFINITE, CELES_E_OVERLAP,
+ * CELES_E_UNSUPPORTED (lmax > CELES_MAX_LMAX), CELES_E_DEVICE, CELES_E_OOM.
+ * On error *h is NULL.  opt may be NULL (defaults). */
+int celes_create(celes_handle** h, int64_t N, const double* pos, const double* radius,
+                 const double* n_sphere, double n0, double wavelength, int lmax,
+                 const celes_options* opt);
+
+/* Release everything the handle owns.  NULL is allowed. */
+void celes_destroy(celes_handle* h);
+
+/* Text of the last error on this handle (or of the last failed create when
+ * h is NULL).  Valid until the next call on the handle. */
+const char* celes_last_error(const celes_handle* h);
+
+/* Incident field: K plane waves (Appendix A.1 PVWFs; coefficients from the
+ * PVWF-to-SVWF expansion of Appendix A.2).  Wave k propagates along polar
+ * angle beta[k] and azimuth alpha[k]; pol[k] = 1 (TE, e_alpha) or 2 (TM,
+ * e_beta); amplitude E0 [K][2] complex (NULL = 1).  Replaces any previous
+ * incident field and invalidates earlier solutions.  Errors: CELES_E_ARG. */
+int celes_set_plane_waves(celes_handle* h, int K, const double* beta, const double* alpha,
+                          const int* pol, const double* E0);
+
+/* Incident field: one Gaussian beam along +z (Appendix C) with waist w,
+ * focus r_G = focus [3], polarisation angle alpha_G (E0 direction
+ * (-sin alpha_G, cos alpha_G, 0)), complex amplitude (E0_re, E0_im); the
+ * polar-angle integral uses n_beta Gauss-Legendre nodes on [0, pi/2]
+ * (n_beta <= 0: 512).  Sets K = 1.  Errors: CELES_E_ARG. */
+int celes_set_gaussian_beam(celes_handle* h, double waist, const double* focus, double alpha_G,
+                            double E0_re, double E0_im, int n_beta);
+
+/* Copy the incident coefficients a_in [K][N][nmax] complex128 to host memory
+ * a_out.  Errors: CELES_E_STATE (no incident field), CELES_E_ARG. */
+int celes_get_incident(const celes_handle* h, double* a_out);
+
+/* Number of right-hand sides of the current incident field (0 if none). */
+int celes_num_rhs(const celes_handle* h);
+
+/* Block-diagonal preconditioner (Section 3.2.1): partition the spheres into
+ * cubes of edge `cuboid_edge` anchored at the minimum corner of the centres'
+ * bounding box, assemble M_j = I - T W_jj per cube and factorise it (LU with
+ * partial pivoting, FP64).  cuboid_edge <= 0 removes the preconditioner.
+ * Errors: CELES_E_OOM, CELES_E_DEVICE. */
+int celes_build_preconditioner(celes_handle* h, double cuboid_edge);
+
+/* Solve the master equation M b = T a_in (Section 2.2, eqs. masterequation
+ * and M) for every right-hand side by right-preconditioned restarted GMRES
+ * (Section 3.2), W applied on the fly on the device.  x0 [K][N][nmax]
+ * complex128 is the initial guess (NULL: zero).  b_out [K][N][nmax]
+ * receives the scattered-field coefficients (may be NULL: kept internally
+ * for celes_cross_sections / celes_far_field).  info may be NULL.
+ * Returns CELES_OK, CELES_E_NOCONV (b_out holds the best iterate),
+ * CELES_E_BREAKDOWN, CELES_E_STATE, CELES_E_DEVICE. */
+int celes_solve(celes_handle* h, const double* x0, double* b_out, celes_solve_info* info);
+
+/* Hot path, device pointers: y = W x for K right-hand sides (Section 2.2,
+ * eq. a: (W x)^i_n = sum_{i' != i} sum_{n'} A_{n'n}(r_i - r_{i'}) x^{i'}_{n'}),
+ * W evaluated on the fly per sphere pair (Section 3.2.2).  precision
+ * CELES_FP64: x_dev, y_dev are complex128 [K][N][nmax]; CELES_MIXED:
+ * complex64.  Enqueued on `stream` (a hipStream_t; NULL = default stream),
+ * asynchronous.  x_dev and y_dev must not alias.  Errors: CELES_E_ARG,
+ * CELES_E_DEVICE, CELES_E_OOM (scratch). */
+int celes_apply_W(celes_handle* h, int precision, int K, const void* x_dev, void* y_dev,
+                  void* stream);
+
+/* As celes_apply_W but y = M x = x - T (W x) (eq. M). */
+int celes_apply_M(celes_handle* h, int precision, int K, const void* x_dev, void* y_dev,
+                  void* stream);
+
+/* Cross sections for every right-hand side, E0 = 1 normalisation, from the
+ * last solution: C_ext = -(pi/k^2) Re sum conj(a_in) b, C_abs =
+ * -(pi/k^2) sum |b|^2 (Re(1/Q) + 1), C_sca = (1/k^2) oint |F|^2 dOmega by
+ * quadrature of the far field (Appendix D).  Each output has K entries
+ * (any may be NULL).  Errors: CELES_E_STATE (no solution). */
+int celes_cross_sections(celes_handle* h, double* C_ext, double* C_sca, double* C_abs);
+
+/* Far-field amplitude F(theta, phi) of the scattered field, E_sca ->
+ * e^{ikr}/(kr) F (Appendix D), at ndir directions; F_out [K][ndir][3][2]
+ * cartesian complex.  Errors: CELES_E_STATE, CELES_E_ARG. */
+int celes_far_field(celes_handle* h, int64_t ndir, const double* theta, const double* phi,
+                    double* F_out);
+
+/* Electric near field at npt points outside all spheres (Section 2.1, eq.
+ * Escat summed over spheres), plus the incident field when add_incident != 0;
+ * E_out [K][npt][3][2] cartesian complex.  Errors: CELES_E_STATE, CELES_E_ARG. */
+int celes_near_field(celes_handle* h, int64_t npt, const double* pts, int add_incident,
+                     double* E_out);
+
+/* Mie T-matrix entries of one sphere (Appendix B) for size parameter kR =
+ * k R and relative index m = n_sphere / n0: Q_out [2][lmax][2] =
+ * (Q_{1l}, Q_{2l}) complex.  Errors: CELES_E_ARG. */
+int celes_mie_coefficients(int lmax, double kR, double m_re, double m_im, double* Q_out);
+
+/* Geometry of the Hankel lookup table (Section 3.2.2): nodes d_lo + q*dr,
+ * q = 0..n_int; d_lo = max(dr, (floor(2 min R / dr) - 1) dr), n_int =
+ * ceil((d_max - d_lo)/dr) + 1 with d_max the diagonal of the centres'
+ * bounding box.  Any output may be NULL.  Errors: CELES_E_ARG. */
+int celes_lut_info(const celes_handle* h, double* d_lo, double* dr, int64_t* n_int);
+
+/* Number of spheres, lmax and nmax of a handle. */
+int celes_dims(const celes_handle* h, int64_t* N, int* lmax, int* nmax);
+
+/* Translation coefficient tables used by the kernels (Appendix A.2):
+ * writes a5 [L][2L+1][L][2L+1][2L+1] and Im(b5) for l, l' = 1..L,
+ * m = -l..l (offset by L), p = 0..2L, with a5(l,m|l',m'|p) at
+ * [((((l-1)(2L+1) + m+L) L + l'-1)(2L+1) + m'+L)(2L+1) + p].  For tests of
+ * the host tables.  Errors: CELES_E_ARG. */
+int celes_translation_tables(int lmax, double* a5_out, double* b5im_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CELES_H */

@@ -1,0 +1,194 @@
+"""MI355X-native multi-sphere T-matrix solver (CELES method, arXiv:1706.02145).
+
+Thin Python binding over the C ABI of libceles_amd.so (include/celes.h):
+every computation runs in the library's HIP kernels and host C++ code; this
+module only converts arguments.  PyTorch is used only to hand device buffers
+and streams to the device-pointer entry points.
+"""
+import ctypes as C
+
+import numpy as np
+
+from ._capi import (CELES_FP64, CELES_HANKEL_DIRECT, CELES_HANKEL_LUT, CELES_MIXED, ERRORS, Options,
+                    SolveInfo, lib, LIB_PATH)
+
+__all__ = ["Problem", "CelesError", "default_options", "mie_coefficients", "translation_tables", "version",
+           "CELES_FP64", "CELES_MIXED", "CELES_HANKEL_LUT", "CELES_HANKEL_DIRECT", "LIB_PATH"]
+
+
+class CelesError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+        self.name = ERRORS.get(code, str(code))
+
+
+def _dptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _check(rc, h=None):
+    if rc != 0:
+        msg = lib().celes_last_error(h)
+        raise CelesError(rc, msg.decode() if msg else "")
+
+
+def version():
+    return lib().celes_version()
+
+
+def default_options(**kw):
+    o = Options()
+    lib().celes_default_options(C.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def mie_coefficients(lmax, kR, m):
+    """Q[tau-1, l-1] of one sphere (celes_mie_coefficients)."""
+    out = np.zeros(4 * lmax)
+    _check(lib().celes_mie_coefficients(lmax, float(kR), float(np.real(m)), float(np.imag(m)), _dptr(out)))
+    z = out[0::2] + 1j * out[1::2]
+    return z.reshape(2, lmax)
+
+
+def translation_tables(lmax):
+    """(a5, Im b5) arrays indexed [l-1, m+L, l'-1, m'+L, p] (celes_translation_tables)."""
+    W = 2 * lmax + 1
+    a = np.zeros((lmax, W, lmax, W, W))
+    b = np.zeros_like(a)
+    _check(lib().celes_translation_tables(lmax, _dptr(a), _dptr(b)))
+    return a, b
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        return None
+    return C.c_void_p(int(getattr(stream, "cuda_stream", stream)))
+
+
+class Problem:
+    """One sphere ensemble on one device (celes_create ... celes_destroy)."""
+
+    def __init__(self, positions, radii, n_sphere, n0, wavelength, lmax, options=None, **kw):
+        pos = np.ascontiguousarray(positions, dtype=np.float64).reshape(-1, 3)
+        rad = np.ascontiguousarray(radii, dtype=np.float64).reshape(-1)
+        ns = np.ascontiguousarray(np.broadcast_to(np.asarray(n_sphere, dtype=np.complex128), rad.shape))
+        nsv = np.ascontiguousarray(np.stack([ns.real, ns.imag], -1))
+        opt = options if options is not None else default_options(**kw)
+        self._h = C.c_void_p()
+        rc = lib().celes_create(C.byref(self._h), pos.shape[0], _dptr(pos), _dptr(rad), _dptr(nsv), float(n0),
+                                float(wavelength), int(lmax), C.byref(opt))
+        if rc != 0:
+            self._h = None
+            _check(rc, None)
+        self.N = pos.shape[0]
+        self.lmax = lmax
+        self.nmax = 2 * lmax * (lmax + 2)
+        self.k = 2 * np.pi * n0 / wavelength
+        self.options = opt
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().celes_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # ---- incident field -------------------------------------------------
+    def set_plane_waves(self, beta, alpha, pol, E0=None):
+        beta = np.ascontiguousarray(np.atleast_1d(beta), dtype=np.float64)
+        alpha = np.ascontiguousarray(np.atleast_1d(alpha), dtype=np.float64)
+        pol = np.ascontiguousarray(np.atleast_1d(pol), dtype=np.int32)
+        K = beta.size
+        e = None
+        if E0 is not None:
+            z = np.broadcast_to(np.asarray(E0, dtype=np.complex128), (K,))
+            e = np.ascontiguousarray(np.stack([z.real, z.imag], -1))
+        _check(lib().celes_set_plane_waves(self._h, K, _dptr(beta), _dptr(alpha),
+                                           pol.ctypes.data_as(C.POINTER(C.c_int)),
+                                           _dptr(e) if e is not None else None), self._h)
+
+    def set_gaussian_beam(self, waist, focus, alpha_G, E0=1.0, n_beta=512):
+        f = np.ascontiguousarray(focus, dtype=np.float64)
+        _check(lib().celes_set_gaussian_beam(self._h, float(waist), _dptr(f), float(alpha_G), float(np.real(E0)),
+                                             float(np.imag(E0)), int(n_beta)), self._h)
+
+    @property
+    def num_rhs(self):
+        return lib().celes_num_rhs(self._h)
+
+    def incident(self):
+        K = self.num_rhs
+        out = np.zeros((K, self.N, self.nmax), dtype=np.complex128)
+        _check(lib().celes_get_incident(self._h, _dptr(out.view(np.float64))), self._h)
+        return out
+
+    # ---- solve ------------------------------------------------------------
+    def build_preconditioner(self, cuboid_edge):
+        _check(lib().celes_build_preconditioner(self._h, float(cuboid_edge)), self._h)
+
+    def solve(self, x0=None, check=True):
+        K = self.num_rhs
+        b = np.zeros((K, self.N, self.nmax), dtype=np.complex128)
+        info = SolveInfo()
+        x = None
+        if x0 is not None:
+            x = np.ascontiguousarray(np.broadcast_to(x0, b.shape), dtype=np.complex128)
+        rc = lib().celes_solve(self._h, _dptr(x.view(np.float64)) if x is not None else None,
+                               _dptr(b.view(np.float64)), C.byref(info))
+        if check and rc not in (0,):
+            _check(rc, self._h)
+        return b, {f: getattr(info, f) for f, _ in SolveInfo._fields_}
+
+    def apply_W(self, x, y, precision=CELES_FP64, stream=None, K=1):
+        """y = W x on device buffers (torch tensors or raw pointers)."""
+        xp = x.data_ptr() if hasattr(x, "data_ptr") else int(x)
+        yp = y.data_ptr() if hasattr(y, "data_ptr") else int(y)
+        _check(lib().celes_apply_W(self._h, precision, K, C.c_void_p(xp), C.c_void_p(yp), _stream_ptr(stream)),
+               self._h)
+
+    def apply_M(self, x, y, precision=CELES_FP64, stream=None, K=1):
+        xp = x.data_ptr() if hasattr(x, "data_ptr") else int(x)
+        yp = y.data_ptr() if hasattr(y, "data_ptr") else int(y)
+        _check(lib().celes_apply_M(self._h, precision, K, C.c_void_p(xp), C.c_void_p(yp), _stream_ptr(stream)),
+               self._h)
+
+    # ---- observables ------------------------------------------------------
+    def cross_sections(self):
+        K = self.num_rhs
+        ce, cs, ca = np.zeros(K), np.zeros(K), np.zeros(K)
+        _check(lib().celes_cross_sections(self._h, _dptr(ce), _dptr(cs), _dptr(ca)), self._h)
+        return ce, cs, ca
+
+    def far_field(self, theta, phi):
+        th = np.ascontiguousarray(np.atleast_1d(theta), dtype=np.float64)
+        ph = np.ascontiguousarray(np.atleast_1d(phi), dtype=np.float64)
+        out = np.zeros((self.num_rhs, th.size, 3), dtype=np.complex128)
+        _check(lib().celes_far_field(self._h, th.size, _dptr(th), _dptr(ph), _dptr(out.view(np.float64))), self._h)
+        return out
+
+    def near_field(self, points, add_incident=True):
+        p = np.ascontiguousarray(points, dtype=np.float64).reshape(-1, 3)
+        out = np.zeros((self.num_rhs, p.shape[0], 3), dtype=np.complex128)
+        _check(lib().celes_near_field(self._h, p.shape[0], _dptr(p), int(bool(add_incident)),
+                                      _dptr(out.view(np.float64))), self._h)
+        return out
+
+    def lut_info(self):
+        lo, dr, n = C.c_double(), C.c_double(), C.c_int64()
+        _check(lib().celes_lut_info(self._h, C.byref(lo), C.byref(dr), C.byref(n)), self._h)
+        return lo.value, dr.value, n.value

@@ -1,0 +1,1093 @@
+// Host side of the library: problem set-up, incident fields, the Krylov
+// solvers that drive the device mat-vec, observables and the C ABI.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <map>
+#include <memory>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/celes.h"
+#include "device_common.hpp"
+#include "host_math.hpp"
+#include "precond.hpp"
+#include "vec_kernels.hpp"
+#include "wx_launch.hpp"
+
+using celes::cplx;
+using celes::cx;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf() { release(); }
+    void release() {
+        if (p) hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    bool ensure(size_t b) {
+        if (b <= bytes && p) return true;
+        release();
+        if (hipMalloc(&p, b) != hipSuccess) {
+            p = nullptr;
+            return false;
+        }
+        bytes = b;
+        return true;
+    }
+    template <typename T>
+    T* as() const { return static_cast<T*>(p); }
+};
+
+struct Err {
+    int code;
+    std::string msg;
+};
+
+}  // namespace
+
+struct celes_handle {
+    celes_options opt;
+    int64_t N = 0;
+    int L = 0, nmax = 0, half = 0;
+    double n0 = 1, wavelength = 0, k = 0;
+    std::vector<double> pos;     // [N][3]
+    std::vector<double> radius;  // [N]
+    std::vector<cplx> nsph;      // [N]
+    std::vector<cplx> tq;        // [N][2][L]
+    // Hankel table
+    double lut_lo = 0, lut_dr = 1;
+    int64_t lut_n = 0;
+    // device data
+    DevBuf d_px, d_py, d_pz, d_tq64, d_tq32, d_lut64, d_lut32;
+    DevBuf d_xsd, d_part;        // mat-vec scratch
+    // incident field / solution (host, canonical layout [K][N][nmax])
+    int K = 0;
+    std::vector<cplx> a_in;
+    // incident description (for the near field): plane waves or one Gaussian beam
+    bool gaussian = false;
+    std::vector<double> pw_beta, pw_alpha;
+    std::vector<int> pw_pol;
+    std::vector<cplx> pw_E0;
+    double g_waist = 0, g_focus[3] = {0, 0, 0}, g_alpha = 0;
+    cplx g_E0 = 1.0;
+    std::vector<cplx> b;
+    bool have_solution = false;
+    // solver scratch
+    DevBuf d_V, d_w, d_z, d_r, d_x, d_rhs, d_h, d_partial, d_V32, d_w32, d_z32, d_r32, d_x32;
+    // preconditioner
+    std::unique_ptr<celes::BlockPrecond> pre;
+    std::string err;
+};
+
+namespace {
+
+int fail(celes_handle* h, int code, const std::string& msg) {
+    if (h) h->err = msg;
+    else g_create_error = msg;
+    return code;
+}
+
+#define HIPCHK(h, expr)                                                                          \
+    do {                                                                                         \
+        hipError_t e_ = (expr);                                                                  \
+        if (e_ != hipSuccess)                                                                    \
+            return fail((h), CELES_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// geometry checks
+// ---------------------------------------------------------------------------
+bool find_overlap(int64_t N, const double* pos, const double* rad, int64_t* a, int64_t* bidx) {
+    double rmax = 0;
+    double lo[3] = {1e300, 1e300, 1e300};
+    for (int64_t i = 0; i < N; ++i) {
+        rmax = std::max(rmax, rad[i]);
+        for (int c = 0; c < 3; ++c) lo[c] = std::min(lo[c], pos[3 * i + c]);
+    }
+    const double cell = 2.0 * rmax > 0 ? 2.0 * rmax : 1.0;
+    std::map<std::tuple<int64_t, int64_t, int64_t>, std::vector<int64_t>> grid;
+    auto key = [&](int64_t i) {
+        return std::make_tuple((int64_t)std::floor((pos[3 * i] - lo[0]) / cell),
+                               (int64_t)std::floor((pos[3 * i + 1] - lo[1]) / cell),
+                               (int64_t)std::floor((pos[3 * i + 2] - lo[2]) / cell));
+    };
+    for (int64_t i = 0; i < N; ++i) grid[key(i)].push_back(i);
+    for (int64_t i = 0; i < N; ++i) {
+        auto [cx_, cy, cz] = key(i);
+        for (int dx = -1; dx <= 1; ++dx)
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dz = -1; dz <= 1; ++dz) {
+                    auto it = grid.find(std::make_tuple(cx_ + dx, cy + dy, cz + dz));
+                    if (it == grid.end()) continue;
+                    for (int64_t j : it->second) {
+                        if (j <= i) continue;
+                        double d2 = 0;
+                        for (int c = 0; c < 3; ++c) {
+                            double t = pos[3 * i + c] - pos[3 * j + c];
+                            d2 += t * t;
+                        }
+                        double rr = rad[i] + rad[j];
+                        if (d2 <= rr * rr) {
+                            *a = i;
+                            *bidx = j;
+                            return true;
+                        }
+                    }
+                }
+    }
+    return false;
+}
+
+// ---------------------------------------------------------------------------
+// Hankel lookup table: cubic Hermite per interval, Horner coefficients in t
+// ---------------------------------------------------------------------------
+void lut_geometry(const celes_handle* h, double dr, double* lo, int64_t* n) {
+    double rmin = *std::min_element(h->radius.begin(), h->radius.end());
+    double mn[3] = {1e300, 1e300, 1e300}, mx[3] = {-1e300, -1e300, -1e300};
+    for (int64_t i = 0; i < h->N; ++i)
+        for (int c = 0; c < 3; ++c) {
+            mn[c] = std::min(mn[c], h->pos[3 * i + c]);
+            mx[c] = std::max(mx[c], h->pos[3 * i + c]);
+        }
+    double dmax = std::sqrt((mx[0] - mn[0]) * (mx[0] - mn[0]) + (mx[1] - mn[1]) * (mx[1] - mn[1]) +
+                            (mx[2] - mn[2]) * (mx[2] - mn[2]));
+    double dlo = std::max(dr, (std::floor(2.0 * rmin / dr) - 1.0) * dr);
+    *lo = dlo;
+    *n = (int64_t)std::ceil((dmax - dlo) / dr) + 1;
+}
+
+int build_lut(celes_handle* h) {
+    const int P = 2 * h->L;
+    lut_geometry(h, h->opt.lut_dr, &h->lut_lo, &h->lut_n);
+    h->lut_dr = h->opt.lut_dr;
+    const int64_t nn = h->lut_n + 1;
+    std::vector<cplx> val((size_t)nn * (P + 1)), der((size_t)nn * (P + 1));
+#pragma omp parallel for schedule(static)
+    for (int64_t q = 0; q < nn; ++q) {
+        double d = h->lut_lo + (double)q * h->lut_dr;
+        cplx hv[16], dh[16];
+        celes::sph_hankel(P, h->k * d, hv, dh);
+        for (int p = 0; p <= P; ++p) {
+            val[(size_t)q * (P + 1) + p] = hv[p];
+            der[(size_t)q * (P + 1) + p] = h->k * h->lut_dr * dh[p];  // d/dt = dr * d/dd
+        }
+    }
+    std::vector<cx<double>> c64((size_t)h->lut_n * (P + 1) * 4);
+    std::vector<cx<float>> c32(c64.size());
+    for (int64_t q = 0; q < h->lut_n; ++q)
+        for (int p = 0; p <= P; ++p) {
+            cplx h0 = val[(size_t)q * (P + 1) + p], h1 = val[(size_t)(q + 1) * (P + 1) + p];
+            cplx g0 = der[(size_t)q * (P + 1) + p], g1 = der[(size_t)(q + 1) * (P + 1) + p];
+            cplx c[4] = {h0, g0, 3.0 * (h1 - h0) - 2.0 * g0 - g1, 2.0 * (h0 - h1) + g0 + g1};
+            for (int t = 0; t < 4; ++t) {
+                size_t o = ((size_t)q * (P + 1) + p) * 4 + t;
+                c64[o] = {c[t].real(), c[t].imag()};
+                c32[o] = {(float)c[t].real(), (float)c[t].imag()};
+            }
+        }
+    if (!h->d_lut64.ensure(c64.size() * sizeof(cx<double>)) || !h->d_lut32.ensure(c32.size() * sizeof(cx<float>)))
+        return fail(h, CELES_E_OOM, "cannot allocate the Hankel lookup table");
+    HIPCHK(h, hipMemcpy(h->d_lut64.p, c64.data(), c64.size() * sizeof(cx<double>), hipMemcpyHostToDevice));
+    HIPCHK(h, hipMemcpy(h->d_lut32.p, c32.data(), c32.size() * sizeof(cx<float>), hipMemcpyHostToDevice));
+    return CELES_OK;
+}
+
+// ---------------------------------------------------------------------------
+// mat-vec driver
+// ---------------------------------------------------------------------------
+int pick_chunks(int64_t N) {
+    const char* env = std::getenv("CELES_WX_TARGET_BLOCKS");
+    int target = env ? std::max(1, std::atoi(env)) : 1024;
+    int64_t nbx = (N + celes::WX_BLOCK_SIZE - 1) / celes::WX_BLOCK_SIZE;
+    int64_t nchunk = (target + nbx - 1) / nbx;
+    int64_t maxc = (N + celes::WX_TILE_SIZE - 1) / celes::WX_TILE_SIZE;
+    nchunk = std::max<int64_t>(1, std::min(nchunk, maxc));
+    return (int)nchunk;
+}
+
+template <typename T>
+int matvec(celes_handle* h, const cx<T>* x, cx<T>* y, int epilogue, hipStream_t s) {
+    const int64_t N = h->N;
+    const int nchunk = pick_chunks(N);
+    int64_t chunk_len = (N + nchunk - 1) / nchunk;
+    chunk_len = (chunk_len + celes::WX_TILE_SIZE - 1) / celes::WX_TILE_SIZE * celes::WX_TILE_SIZE;
+    const int nchunk_eff = (int)((N + chunk_len - 1) / chunk_len);
+    if (!h->d_xsd.ensure((size_t)N * h->nmax * sizeof(cx<T>)) ||
+        !h->d_part.ensure((size_t)nchunk_eff * h->nmax * N * sizeof(cx<T>)))
+        return fail(h, CELES_E_OOM, "cannot allocate mat-vec scratch");
+    celes::WxArgs<T> a;
+    a.px = h->d_px.as<double>();
+    a.py = h->d_py.as<double>();
+    a.pz = h->d_pz.as<double>();
+    a.xsd = h->d_xsd.as<cx<T>>();
+    a.part = h->d_part.as<cx<T>>();
+    a.lut.coef = (sizeof(T) == 8) ? (const cx<T>*)h->d_lut64.p : (const cx<T>*)h->d_lut32.p;
+    a.lut.d_lo = h->lut_lo;
+    a.lut.inv_dr = 1.0 / h->lut_dr;
+    a.lut.n_int = (int)h->lut_n;
+    a.k = h->k;
+    a.n = (int)N;
+    a.chunk_len = (int)chunk_len;
+    a.ldp = (int)N;
+    const cx<T>* tq = (sizeof(T) == 8) ? (const cx<T>*)h->d_tq64.p : (const cx<T>*)h->d_tq32.p;
+    int rc = celes::wx_launch<T>(a, h->L, h->opt.hankel == CELES_HANKEL_DIRECT ? 1 : 0, nchunk_eff, x, tq, y,
+                                 epilogue, s);
+    if (rc == -1) return fail(h, CELES_E_UNSUPPORTED, "lmax not compiled");
+    if (rc != 0) return fail(h, CELES_E_DEVICE, "mat-vec launch failed");
+    return CELES_OK;
+}
+
+// ---------------------------------------------------------------------------
+// GMRES (right-preconditioned, restarted, classical Gram-Schmidt with one
+// re-orthogonalisation) on device vectors of precision T.  Inner products
+// accumulate in FP64.  Solves M x = rhs from the initial x.
+// ---------------------------------------------------------------------------
+struct GmresResult {
+    int iterations = 0;
+    int restarts = 0;
+    int matvecs = 0;
+    double est = 0;       // final implicit relative residual estimate
+    bool breakdown = false;
+    double matvec_seconds = 0;
+};
+
+template <typename T>
+int gmres_device(celes_handle* h, const cx<T>* rhs, cx<T>* x, double tol, int maxiter, double rhs_norm,
+                 GmresResult* out, hipStream_t s, cx<T>* V, cx<T>* w, cx<T>* z) {
+    const int64_t n = h->N * h->nmax;
+    const int m = std::max(1, h->opt.restart);
+    cx<double>* dh = h->d_h.as<cx<double>>();
+    cx<double>* dpart = h->d_partial.as<cx<double>>();
+    std::vector<cx<double>> hh(m + 2), hh2(m + 2);
+    std::vector<cplx> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1);
+    const bool use_pre = (bool)h->pre;
+    auto apply_pre = [&](const cx<T>* in, cx<T>* outv) -> int {
+        return h->pre->apply<T>(in, outv, s);
+    };
+    auto norm2 = [&](const cx<T>* v) -> double {
+        celes::vec_dots<T>(v, 0, 1, v, n, dpart, dh, s);
+        cx<double> r;
+        hipMemcpyAsync(&r, dh, sizeof(r), hipMemcpyDeviceToHost, s);
+        hipStreamSynchronize(s);
+        return std::sqrt(std::max(0.0, r.re));
+    };
+    hipEvent_t e0, e1;
+    hipEventCreate(&e0);
+    hipEventCreate(&e1);
+    auto timed_matvec = [&](const cx<T>* in, cx<T>* outv) -> int {
+        hipEventRecord(e0, s);
+        int rc = matvec<T>(h, in, outv, 1, s);
+        hipEventRecord(e1, s);
+        hipEventSynchronize(e1);
+        float ms = 0;
+        hipEventElapsedTime(&ms, e0, e1);
+        out->matvec_seconds += ms * 1e-3;
+        out->matvecs++;
+        return rc;
+    };
+    int rc = CELES_OK;
+    while (true) {
+        // r = rhs - M x  -> V[0]
+        if ((rc = timed_matvec(x, w)) != CELES_OK) break;
+        celes::vec_sub<T>(rhs, w, V, n, s);
+        double beta = norm2(V);
+        out->est = beta / rhs_norm;
+        if (!std::isfinite(beta)) {
+            out->breakdown = true;
+            break;
+        }
+        if (out->est <= tol || out->iterations >= maxiter) break;
+        celes::vec_scale<T>(V, 1.0 / beta, V, n, s);
+        std::fill(g.begin(), g.end(), cplx(0, 0));
+        g[0] = beta;
+        int kk = 0, used = 0;
+        for (kk = 0; kk < m; ++kk) {
+            cx<T>* vk = V + (int64_t)kk * n;
+            cx<T>* vk1 = V + (int64_t)(kk + 1) * n;
+            const cx<T>* zin = vk;
+            if (use_pre) {
+                if ((rc = apply_pre(vk, z)) != CELES_OK) break;
+                zin = z;
+            }
+            if ((rc = timed_matvec(zin, vk1)) != CELES_OK) break;
+            // CGS2
+            celes::vec_dots<T>(V, n, kk + 1, vk1, n, dpart, dh, s);
+            celes::vec_gemv_sub<T>(V, n, kk + 1, dh, vk1, n, s);
+            hipMemcpyAsync(hh.data(), dh, (kk + 1) * sizeof(cx<double>), hipMemcpyDeviceToHost, s);
+            celes::vec_dots<T>(V, n, kk + 1, vk1, n, dpart, dh, s);
+            celes::vec_gemv_sub<T>(V, n, kk + 1, dh, vk1, n, s);
+            hipMemcpyAsync(hh2.data(), dh, (kk + 1) * sizeof(cx<double>), hipMemcpyDeviceToHost, s);
+            double hn = norm2(vk1);
+            for (int i = 0; i <= kk; ++i)
+                H[(size_t)i * m + kk] = cplx(hh[i].re + hh2[i].re, hh[i].im + hh2[i].im);
+            H[(size_t)(kk + 1) * m + kk] = hn;
+            if (!std::isfinite(hn)) {
+                out->breakdown = true;
+                break;
+            }
+            // apply previous Givens rotations
+            for (int i = 0; i < kk; ++i) {
+                cplx a = H[(size_t)i * m + kk], bb = H[(size_t)(i + 1) * m + kk];
+                H[(size_t)i * m + kk] = cs[i] * a + sn[i] * bb;
+                H[(size_t)(i + 1) * m + kk] = -std::conj(sn[i]) * a + std::conj(cs[i]) * bb;
+            }
+            cplx a = H[(size_t)kk * m + kk], bb = H[(size_t)(kk + 1) * m + kk];
+            double den = std::sqrt(std::norm(a) + std::norm(bb));
+            cs[kk] = den > 0 ? a / den : cplx(1, 0);
+            sn[kk] = den > 0 ? bb / den : cplx(0, 0);
+            H[(size_t)kk * m + kk] = den;
+            H[(size_t)(kk + 1) * m + kk] = 0;
+            g[kk + 1] = -std::conj(sn[kk]) * g[kk];
+            g[kk] = std::conj(cs[kk]) * g[kk];
+            out->iterations++;
+            used = kk + 1;
+            if (hn > 0) celes::vec_scale<T>(vk1, 1.0 / hn, vk1, n, s);
+            double est = std::abs(g[kk + 1]) / rhs_norm;
+            out->est = est;
+            if (hn == 0 || est <= tol || out->iterations >= maxiter) break;
+        }
+        if (rc != CELES_OK || out->breakdown) break;
+        // y = H^{-1} g (upper triangular), u = V y, x += P^{-1} u
+        std::vector<cplx> y(used);
+        for (int i = used - 1; i >= 0; --i) {
+            cplx t = g[i];
+            for (int j = i + 1; j < used; ++j) t -= H[(size_t)i * m + j] * y[j];
+            y[i] = t / H[(size_t)i * m + i];
+        }
+        std::vector<cx<double>> yd(used);
+        for (int i = 0; i < used; ++i) yd[i] = {y[i].real(), y[i].imag()};
+        hipMemcpyAsync(dh, yd.data(), used * sizeof(cx<double>), hipMemcpyHostToDevice, s);
+        if (use_pre) {
+            hipMemsetAsync(w, 0, n * sizeof(cx<T>), s);
+            celes::vec_gemv_add<T>(V, n, used, dh, w, n, s);
+            if ((rc = apply_pre(w, z)) != CELES_OK) break;
+            // x += z : reuse gemv_add with a single "basis vector" z and coefficient 1
+            cx<double> one = {1.0, 0.0};
+            hipMemcpyAsync(dh, &one, sizeof(one), hipMemcpyHostToDevice, s);
+            celes::vec_gemv_add<T>(z, n, 1, dh, x, n, s);
+        } else {
+            celes::vec_gemv_add<T>(V, n, used, dh, x, n, s);
+        }
+        hipStreamSynchronize(s);
+        out->restarts++;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    return rc;
+}
+
+int ensure_solver_buffers(celes_handle* h, bool mixed) {
+    const int64_t n = h->N * h->nmax;
+    const int m = std::max(1, h->opt.restart);
+    bool ok = h->d_h.ensure((m + 2) * sizeof(cx<double>)) &&
+              h->d_partial.ensure((size_t)celes::VEC_PARTIAL_BLOCKS * (m + 2) * sizeof(cx<double>)) &&
+              h->d_w.ensure(n * sizeof(cx<double>)) && h->d_z.ensure(n * sizeof(cx<double>)) &&
+              h->d_r.ensure(n * sizeof(cx<double>)) && h->d_x.ensure(n * sizeof(cx<double>)) &&
+              h->d_rhs.ensure(n * sizeof(cx<double>));
+    if (mixed)
+        ok = ok && h->d_V32.ensure((size_t)(m + 1) * n * sizeof(cx<float>)) &&
+             h->d_w32.ensure(n * sizeof(cx<float>)) && h->d_z32.ensure(n * sizeof(cx<float>)) &&
+             h->d_r32.ensure(n * sizeof(cx<float>)) && h->d_x32.ensure(n * sizeof(cx<float>));
+    else
+        ok = ok && h->d_V.ensure((size_t)(m + 1) * n * sizeof(cx<double>));
+    return ok ? CELES_OK : fail(h, CELES_E_OOM, "cannot allocate solver buffers");
+}
+
+double host_norm(const std::vector<cplx>& v, size_t off, size_t n) {
+    double s = 0;
+    for (size_t i = 0; i < n; ++i) s += std::norm(v[off + i]);
+    return std::sqrt(s);
+}
+
+// FP64 residual r = rhs - M x on the device; returns ||r||
+double residual64(celes_handle* h, const cx<double>* rhs, const cx<double>* x, cx<double>* r, hipStream_t s,
+                  int* rc, double* mv_sec) {
+    const int64_t n = h->N * h->nmax;
+    hipEvent_t e0, e1;
+    hipEventCreate(&e0);
+    hipEventCreate(&e1);
+    hipEventRecord(e0, s);
+    *rc = matvec<double>(h, x, h->d_w.as<cx<double>>(), 1, s);
+    hipEventRecord(e1, s);
+    celes::vec_sub<double>(rhs, h->d_w.as<cx<double>>(), r, n, s);
+    celes::vec_dots<double>(r, 0, 1, r, n, h->d_partial.as<cx<double>>(), h->d_h.as<cx<double>>(), s);
+    cx<double> v;
+    hipMemcpyAsync(&v, h->d_h.p, sizeof(v), hipMemcpyDeviceToHost, s);
+    hipStreamSynchronize(s);
+    float ms = 0;
+    hipEventElapsedTime(&ms, e0, e1);
+    *mv_sec += ms * 1e-3;
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    return std::sqrt(std::max(0.0, v.re));
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+void celes_default_options(celes_options* opt) {
+    if (!opt) return;
+    std::memset(opt, 0, sizeof(*opt));
+    opt->precision = CELES_FP64;
+    opt->hankel = CELES_HANKEL_LUT;
+    opt->lut_dr = 1.0;
+    opt->tol = 1e-8;
+    opt->inner_tol = 1e-4;
+    opt->restart = 100;
+    opt->maxiter = 2000;
+    opt->max_refinements = 30;
+    opt->cuboid_edge = 0.0;
+    opt->device = 0;
+    opt->verbose = 0;
+}
+
+int celes_version(void) { return CELES_VERSION; }
+
+const char* celes_last_error(const celes_handle* h) { return h ? h->err.c_str() : g_create_error.c_str(); }
+
+int celes_create(celes_handle** out, int64_t N, const double* pos, const double* radius, const double* n_sphere,
+                 double n0, double wavelength, int lmax, const celes_options* opt) {
+    if (!out) return fail(nullptr, CELES_E_ARG, "null handle pointer");
+    *out = nullptr;
+    if (N < 1 || !pos || !radius || !n_sphere) return fail(nullptr, CELES_E_ARG, "N < 1 or null input array");
+    if (lmax < 1) return fail(nullptr, CELES_E_ARG, "lmax < 1");
+    if (lmax > CELES_MAX_LMAX) return fail(nullptr, CELES_E_UNSUPPORTED, "lmax above CELES_MAX_LMAX");
+    if (!(n0 > 0) || !(wavelength > 0) || !std::isfinite(n0) || !std::isfinite(wavelength))
+        return fail(nullptr, CELES_E_ARG, "n0 and wavelength must be positive and finite");
+    if (N > (int64_t)std::numeric_limits<int>::max() / 64)
+        return fail(nullptr, CELES_E_ARG, "N too large");
+    for (int64_t i = 0; i < N; ++i) {
+        for (int c = 0; c < 3; ++c)
+            if (!std::isfinite(pos[3 * i + c])) return fail(nullptr, CELES_E_NONFINITE, "non-finite position");
+        if (!std::isfinite(radius[i]) || !(radius[i] > 0))
+            return fail(nullptr, CELES_E_NONFINITE, "radius must be positive and finite");
+        if (!std::isfinite(n_sphere[2 * i]) || !std::isfinite(n_sphere[2 * i + 1]))
+            return fail(nullptr, CELES_E_NONFINITE, "non-finite refractive index");
+    }
+    int64_t oa, ob;
+    if (find_overlap(N, pos, radius, &oa, &ob))
+        return fail(nullptr, CELES_E_OVERLAP,
+                    "spheres " + std::to_string(oa) + " and " + std::to_string(ob) + " overlap");
+    std::unique_ptr<celes_handle> h(new celes_handle());
+    if (opt) h->opt = *opt;
+    else celes_default_options(&h->opt);
+    if (!(h->opt.lut_dr > 0)) return fail(nullptr, CELES_E_ARG, "lut_dr must be positive");
+    if (h->opt.restart < 1) h->opt.restart = 1;
+    if (hipSetDevice(h->opt.device) != hipSuccess) return fail(nullptr, CELES_E_DEVICE, "hipSetDevice failed");
+    h->N = N;
+    h->L = lmax;
+    h->nmax = celes::nmax_of(lmax);
+    h->half = celes::half_of(lmax);
+    h->n0 = n0;
+    h->wavelength = wavelength;
+    h->k = 2.0 * M_PI * n0 / wavelength;
+    h->pos.assign(pos, pos + 3 * N);
+    h->radius.assign(radius, radius + N);
+    h->nsph.resize(N);
+    for (int64_t i = 0; i < N; ++i) h->nsph[i] = cplx(n_sphere[2 * i], n_sphere[2 * i + 1]);
+    // Mie coefficients (Appendix B), relative index n_i / n0
+    h->tq.resize((size_t)N * 2 * lmax);
+    {
+        std::map<std::pair<double, std::pair<double, double>>, std::vector<cplx>> cache;
+        std::vector<cplx> q1(lmax), q2(lmax);
+        for (int64_t i = 0; i < N; ++i) {
+            auto key = std::make_pair(radius[i], std::make_pair(h->nsph[i].real(), h->nsph[i].imag()));
+            auto it = cache.find(key);
+            if (it == cache.end()) {
+                celes::mie_Q(lmax, h->k * radius[i], h->nsph[i] / n0, q1.data(), q2.data());
+                std::vector<cplx> v(2 * lmax);
+                for (int l = 0; l < lmax; ++l) {
+                    v[l] = q1[l];
+                    v[lmax + l] = q2[l];
+                }
+                it = cache.emplace(key, v).first;
+            }
+            std::copy(it->second.begin(), it->second.end(), h->tq.begin() + (size_t)i * 2 * lmax);
+        }
+    }
+    // device geometry and T
+    std::vector<double> px(N), py(N), pz(N);
+    for (int64_t i = 0; i < N; ++i) {
+        px[i] = pos[3 * i];
+        py[i] = pos[3 * i + 1];
+        pz[i] = pos[3 * i + 2];
+    }
+    std::vector<cx<double>> t64(h->tq.size());
+    std::vector<cx<float>> t32(h->tq.size());
+    for (size_t i = 0; i < h->tq.size(); ++i) {
+        t64[i] = {h->tq[i].real(), h->tq[i].imag()};
+        t32[i] = {(float)h->tq[i].real(), (float)h->tq[i].imag()};
+    }
+    celes_handle* hp = h.get();
+    if (!h->d_px.ensure(N * 8) || !h->d_py.ensure(N * 8) || !h->d_pz.ensure(N * 8) ||
+        !h->d_tq64.ensure(t64.size() * sizeof(cx<double>)) || !h->d_tq32.ensure(t32.size() * sizeof(cx<float>)))
+        return fail(nullptr, CELES_E_OOM, "device allocation failed");
+    if (hipMemcpy(h->d_px.p, px.data(), N * 8, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(h->d_py.p, py.data(), N * 8, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(h->d_pz.p, pz.data(), N * 8, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(h->d_tq64.p, t64.data(), t64.size() * sizeof(cx<double>), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(h->d_tq32.p, t32.data(), t32.size() * sizeof(cx<float>), hipMemcpyHostToDevice) != hipSuccess)
+        return fail(nullptr, CELES_E_DEVICE, "host-to-device copy failed");
+    int rc = build_lut(hp);
+    if (rc != CELES_OK) {
+        g_create_error = hp->err;
+        return rc;
+    }
+    *out = h.release();
+    return CELES_OK;
+}
+
+void celes_destroy(celes_handle* h) { delete h; }
+
+int celes_dims(const celes_handle* h, int64_t* N, int* lmax, int* nmax) {
+    if (!h) return CELES_E_ARG;
+    if (N) *N = h->N;
+    if (lmax) *lmax = h->L;
+    if (nmax) *nmax = h->nmax;
+    return CELES_OK;
+}
+
+int celes_lut_info(const celes_handle* h, double* d_lo, double* dr, int64_t* n_int) {
+    if (!h) return CELES_E_ARG;
+    if (d_lo) *d_lo = h->lut_lo;
+    if (dr) *dr = h->lut_dr;
+    if (n_int) *n_int = h->lut_n;
+    return CELES_OK;
+}
+
+int celes_num_rhs(const celes_handle* h) { return h ? h->K : 0; }
+
+int celes_set_plane_waves(celes_handle* h, int K, const double* beta, const double* alpha, const int* pol,
+                          const double* E0) {
+    if (!h) return CELES_E_ARG;
+    if (K < 1 || !beta || !alpha || !pol) return fail(h, CELES_E_ARG, "K < 1 or null array");
+    for (int kk = 0; kk < K; ++kk)
+        if (pol[kk] != 1 && pol[kk] != 2) return fail(h, CELES_E_ARG, "pol must be 1 or 2");
+    const int64_t N = h->N;
+    const int nm = h->nmax, L = h->L;
+    h->a_in.assign((size_t)K * N * nm, cplx(0, 0));
+    for (int kk = 0; kk < K; ++kk) {
+        const double b = beta[kk], al = alpha[kk];
+        const cplx e0 = E0 ? cplx(E0[2 * kk], E0[2 * kk + 1]) : cplx(1, 0);
+        // a_{in,n}^i = 4 E0 e^{i k.r_i} e^{-i m alpha} B^dagger_{nj}(beta)
+        std::vector<cplx> base(nm);
+        for (int tau = 1; tau <= 2; ++tau)
+            for (int l = 1; l <= L; ++l)
+                for (int m = -l; m <= l; ++m)
+                    base[(tau - 1) * h->half + celes::lm_index(l, m)] =
+                        4.0 * e0 * std::exp(cplx(0, -m * al)) * celes::b_dagger(tau, l, m, pol[kk], b);
+        const double kx = h->k * std::sin(b) * std::cos(al), ky = h->k * std::sin(b) * std::sin(al),
+                     kz = h->k * std::cos(b);
+        for (int64_t i = 0; i < N; ++i) {
+            cplx ph = std::exp(cplx(0, kx * h->pos[3 * i] + ky * h->pos[3 * i + 1] + kz * h->pos[3 * i + 2]));
+            cplx* dst = &h->a_in[((size_t)kk * N + i) * nm];
+            for (int c = 0; c < nm; ++c) dst[c] = ph * base[c];
+        }
+    }
+    h->K = K;
+    h->have_solution = false;
+    h->gaussian = false;
+    h->pw_beta.assign(beta, beta + K);
+    h->pw_alpha.assign(alpha, alpha + K);
+    h->pw_pol.assign(pol, pol + K);
+    h->pw_E0.resize(K);
+    for (int kk = 0; kk < K; ++kk) h->pw_E0[kk] = E0 ? cplx(E0[2 * kk], E0[2 * kk + 1]) : cplx(1, 0);
+    return CELES_OK;
+}
+
+int celes_set_gaussian_beam(celes_handle* h, double waist, const double* focus, double alpha_G, double E0_re,
+                            double E0_im, int n_beta) {
+    if (!h) return CELES_E_ARG;
+    if (!(waist > 0) || !focus) return fail(h, CELES_E_ARG, "waist must be positive and focus non-null");
+    if (n_beta <= 0) n_beta = 512;
+    const int64_t N = h->N;
+    const int nm = h->nmax, L = h->L;
+    const double k = h->k;
+    std::vector<double> xg(n_beta), wg(n_beta);
+    celes::gauss_legendre(n_beta, xg.data(), wg.data());
+    // beta nodes on [0, pi/2]; weight factor sin cos exp(-w^2 k^2 sin^2 / 4)
+    std::vector<double> bet(n_beta), wb(n_beta);
+    for (int q = 0; q < n_beta; ++q) {
+        bet[q] = 0.25 * M_PI * (xg[q] + 1.0);
+        double sb = std::sin(bet[q]), cb = std::cos(bet[q]);
+        wb[q] = 0.25 * M_PI * wg[q] * sb * cb * std::exp(-waist * waist * k * k * sb * sb / 4.0);
+    }
+    // B^dagger table [q][n][j]
+    std::vector<cplx> Bd((size_t)n_beta * nm * 2);
+    for (int q = 0; q < n_beta; ++q)
+        for (int tau = 1; tau <= 2; ++tau)
+            for (int l = 1; l <= L; ++l)
+                for (int m = -l; m <= l; ++m)
+                    for (int j = 1; j <= 2; ++j)
+                        Bd[((size_t)q * nm + (tau - 1) * h->half + celes::lm_index(l, m)) * 2 + (j - 1)] =
+                            celes::b_dagger(tau, l, m, j, bet[q]);
+    const cplx E0(E0_re, E0_im);
+    const cplx pref = E0 * k * k * waist * waist / M_PI;
+    h->a_in.assign((size_t)N * nm, cplx(0, 0));
+    const cplx I(0, 1);
+    auto ipow = [](int e) -> cplx {
+        switch (((e % 4) + 4) % 4) {
+            case 0: return {1, 0};
+            case 1: return {0, 1};
+            case 2: return {-1, 0};
+            default: return {0, -1};
+        }
+    };
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < N; ++i) {
+        const double rx = h->pos[3 * i] - focus[0], ry = h->pos[3 * i + 1] - focus[1],
+                     rz = h->pos[3 * i + 2] - focus[2];
+        const double rho = std::hypot(rx, ry), phG = std::atan2(ry, rx);
+        std::vector<cplx> acc(nm, cplx(0, 0));
+        std::vector<double> J(L + 3);
+        for (int q = 0; q < n_beta; ++q) {
+            const double sb = std::sin(bet[q]), cb = std::cos(bet[q]);
+            const double x = k * rho * sb;
+            // J_0..J_{L+1}(x): downward recurrence from two library values
+            if (x == 0.0) {
+                std::fill(J.begin(), J.end(), 0.0);
+                J[0] = 1.0;
+            } else {
+                J[L + 1] = std::cyl_bessel_j((double)(L + 1), x);
+                J[L] = std::cyl_bessel_j((double)L, x);
+                for (int nn = L; nn >= 1; --nn) J[nn - 1] = 2.0 * nn / x * J[nn] - J[nn + 1];
+            }
+            const cplx ax = std::exp(I * (k * rz * cb)) * wb[q];
+            for (int l = 1; l <= L; ++l)
+                for (int m = -l; m <= l; ++m) {
+                    // I_{jn} / (2 pi), for j = 1, 2
+                    const cplx t1 = std::exp(-I * alpha_G) * ipow(std::abs(m - 1)) *
+                                    std::exp(-I * ((double)(m - 1) * phG)) * J[std::abs(m - 1)];
+                    const cplx t2 = std::exp(I * alpha_G) * ipow(std::abs(m + 1)) *
+                                    std::exp(-I * ((double)(m + 1) * phG)) * J[std::abs(m + 1)];
+                    const cplx Ij1 = 2.0 * M_PI * 0.5 * (t1 + t2);
+                    const cplx Ij2 = 2.0 * M_PI * 0.5 * (-I * t1 + I * t2);
+                    for (int tau = 1; tau <= 2; ++tau) {
+                        const int c = (tau - 1) * h->half + celes::lm_index(l, m);
+                        const cplx* bd = &Bd[((size_t)q * nm + c) * 2];
+                        acc[c] += ax * (bd[0] * Ij1 + bd[1] * Ij2);
+                    }
+                }
+        }
+        for (int c = 0; c < nm; ++c) h->a_in[(size_t)i * nm + c] = pref * acc[c];
+    }
+    h->K = 1;
+    h->have_solution = false;
+    h->gaussian = true;
+    h->g_waist = waist;
+    for (int c = 0; c < 3; ++c) h->g_focus[c] = focus[c];
+    h->g_alpha = alpha_G;
+    h->g_E0 = E0;
+    return CELES_OK;
+}
+
+int celes_get_incident(const celes_handle* h, double* a_out) {
+    if (!h || !a_out) return CELES_E_ARG;
+    if (h->K < 1) return CELES_E_STATE;
+    std::memcpy(a_out, h->a_in.data(), h->a_in.size() * sizeof(cplx));
+    return CELES_OK;
+}
+
+int celes_apply_W(celes_handle* h, int precision, int K, const void* x_dev, void* y_dev, void* stream) {
+    if (!h) return CELES_E_ARG;
+    if (K < 1 || !x_dev || !y_dev) return fail(h, CELES_E_ARG, "K < 1 or null device pointer");
+    hipStream_t s = (hipStream_t)stream;
+    const size_t stride = (size_t)h->N * h->nmax;
+    for (int kk = 0; kk < K; ++kk) {
+        int rc;
+        if (precision == CELES_FP64)
+            rc = matvec<double>(h, (const cx<double>*)x_dev + kk * stride, (cx<double>*)y_dev + kk * stride, 0, s);
+        else if (precision == CELES_MIXED)
+            rc = matvec<float>(h, (const cx<float>*)x_dev + kk * stride, (cx<float>*)y_dev + kk * stride, 0, s);
+        else
+            return fail(h, CELES_E_ARG, "unknown precision");
+        if (rc != CELES_OK) return rc;
+    }
+    return CELES_OK;
+}
+
+int celes_apply_M(celes_handle* h, int precision, int K, const void* x_dev, void* y_dev, void* stream) {
+    if (!h) return CELES_E_ARG;
+    if (K < 1 || !x_dev || !y_dev) return fail(h, CELES_E_ARG, "K < 1 or null device pointer");
+    hipStream_t s = (hipStream_t)stream;
+    const size_t stride = (size_t)h->N * h->nmax;
+    for (int kk = 0; kk < K; ++kk) {
+        int rc;
+        if (precision == CELES_FP64)
+            rc = matvec<double>(h, (const cx<double>*)x_dev + kk * stride, (cx<double>*)y_dev + kk * stride, 1, s);
+        else if (precision == CELES_MIXED)
+            rc = matvec<float>(h, (const cx<float>*)x_dev + kk * stride, (cx<float>*)y_dev + kk * stride, 1, s);
+        else
+            return fail(h, CELES_E_ARG, "unknown precision");
+        if (rc != CELES_OK) return rc;
+    }
+    return CELES_OK;
+}
+
+int celes_build_preconditioner(celes_handle* h, double cuboid_edge) {
+    if (!h) return CELES_E_ARG;
+    h->pre.reset();
+    if (!(cuboid_edge > 0)) return CELES_OK;
+    std::string msg;
+    auto p = std::make_unique<celes::BlockPrecond>();
+    int rc = p->build(h->N, h->L, h->pos.data(), h->k, h->tq.data(), cuboid_edge,
+                      h->opt.hankel == CELES_HANKEL_DIRECT ? 1 : 0, h->d_lut64.p, h->lut_lo, h->lut_dr,
+                      (int)h->lut_n, &msg);
+    if (rc != CELES_OK) return fail(h, rc, msg);
+    h->pre = std::move(p);
+    return CELES_OK;
+}
+
+int celes_solve(celes_handle* h, const double* x0, double* b_out, celes_solve_info* info) {
+    if (!h) return CELES_E_ARG;
+    if (h->K < 1) return fail(h, CELES_E_STATE, "no incident field set");
+    const bool mixed = h->opt.precision == CELES_MIXED;
+    int rc = ensure_solver_buffers(h, mixed);
+    if (rc != CELES_OK) return rc;
+    hipStream_t s = nullptr;
+    const int64_t N = h->N, nm = h->nmax, n = N * nm;
+    celes_solve_info inf{};
+    h->b.assign((size_t)h->K * n, cplx(0, 0));
+    auto t0 = std::chrono::steady_clock::now();
+    int status = CELES_OK;
+    double worst = 0;
+    for (int kk = 0; kk < h->K; ++kk) {
+        // rhs = T a_in
+        std::vector<cx<double>> rhs(n), x(n);
+        for (int64_t i = 0; i < N; ++i)
+            for (int tau = 0; tau < 2; ++tau)
+                for (int c = 0; c < h->half; ++c) {
+                    int l = (int)std::floor(std::sqrt((double)(c + 1)));
+                    while (l * (l + 2) < c + 1) ++l;
+                    while ((l - 1) * (l + 1) >= c + 1) --l;
+                    cplx q = h->tq[((size_t)i * 2 + tau) * h->L + (l - 1)];
+                    cplx v = q * h->a_in[((size_t)kk * N + i) * nm + tau * h->half + c];
+                    rhs[i * nm + tau * h->half + c] = {v.real(), v.imag()};
+                }
+        for (int64_t c = 0; c < n; ++c) {
+            if (x0) {
+                x[c] = {x0[2 * ((size_t)kk * n + c)], x0[2 * ((size_t)kk * n + c) + 1]};
+                if (!std::isfinite(x[c].re) || !std::isfinite(x[c].im)) return fail(h, CELES_E_NONFINITE, "non-finite x0");
+            } else {
+                x[c] = {0, 0};
+            }
+        }
+        double rn = 0;
+        for (auto& v : rhs) rn += v.re * v.re + v.im * v.im;
+        rn = std::sqrt(rn);
+        cx<double>* drhs = h->d_rhs.as<cx<double>>();
+        cx<double>* dx = h->d_x.as<cx<double>>();
+        HIPCHK(h, hipMemcpy(drhs, rhs.data(), n * sizeof(cx<double>), hipMemcpyHostToDevice));
+        HIPCHK(h, hipMemcpy(dx, x.data(), n * sizeof(cx<double>), hipMemcpyHostToDevice));
+        double final_res = 0;
+        if (rn == 0) {
+            HIPCHK(h, hipMemset(dx, 0, n * sizeof(cx<double>)));
+        } else if (!mixed) {
+            GmresResult gr;
+            rc = gmres_device<double>(h, drhs, dx, h->opt.tol, h->opt.maxiter, rn, &gr, s, h->d_V.as<cx<double>>(),
+                                      h->d_w.as<cx<double>>(), h->d_z.as<cx<double>>());
+            if (rc != CELES_OK) return rc;
+            inf.iterations += gr.iterations;
+            inf.refinements += gr.restarts;
+            inf.matvecs += gr.matvecs;
+            inf.matvec_seconds += gr.matvec_seconds;
+            double mv = 0;
+            double r = residual64(h, drhs, dx, h->d_r.as<cx<double>>(), s, &rc, &mv) / rn;
+            inf.matvecs++;
+            inf.matvec_seconds += mv;
+            final_res = r;
+            if (gr.breakdown || !std::isfinite(r)) status = CELES_E_BREAKDOWN;
+            else if (r > h->opt.tol && status == CELES_OK) status = CELES_E_NOCONV;
+        } else {
+            // iterative refinement: FP64 residual, complex64 GMRES correction
+            int inner_left = h->opt.maxiter;
+            double mv = 0;
+            double r = residual64(h, drhs, dx, h->d_r.as<cx<double>>(), s, &rc, &mv) / rn;
+            inf.matvecs++;
+            for (int it = 0; it < h->opt.max_refinements && r > h->opt.tol && inner_left > 0; ++it) {
+                // correction problem M d = r in complex64, from d = 0
+                celes::vec_to32(h->d_r.as<cx<double>>(), h->d_r32.as<cx<float>>(), n, s);
+                HIPCHK(h, hipMemsetAsync(h->d_x32.p, 0, n * sizeof(cx<float>), s));
+                GmresResult gr;
+                double rnorm = r * rn;
+                double inner = std::max(h->opt.inner_tol, 0.5 * h->opt.tol / r);
+                rc = gmres_device<float>(h, h->d_r32.as<cx<float>>(), h->d_x32.as<cx<float>>(), inner, inner_left,
+                                         rnorm, &gr, s, h->d_V32.as<cx<float>>(), h->d_w32.as<cx<float>>(),
+                                         h->d_z32.as<cx<float>>());
+                if (rc != CELES_OK) return rc;
+                inf.iterations += gr.iterations;
+                inf.matvecs += gr.matvecs;
+                inf.matvec_seconds += gr.matvec_seconds;
+                inner_left -= std::max(1, gr.iterations);
+                celes::vec_acc32(h->d_x32.as<cx<float>>(), dx, n, s);
+                double rnew = residual64(h, drhs, dx, h->d_r.as<cx<double>>(), s, &rc, &mv) / rn;
+                inf.matvecs++;
+                inf.refinements++;
+                if (h->opt.verbose) std::fprintf(stderr, "refinement %d: residual %.3e (inner its %d)\n", it, rnew, gr.iterations);
+                if (!(rnew < r) && gr.breakdown) break;
+                r = rnew;
+            }
+            inf.matvec_seconds += mv;
+            final_res = r;
+            if (!std::isfinite(r)) status = CELES_E_BREAKDOWN;
+            else if (r > h->opt.tol && status == CELES_OK) status = CELES_E_NOCONV;
+        }
+        worst = std::max(worst, final_res);
+        HIPCHK(h, hipMemcpy(x.data(), dx, n * sizeof(cx<double>), hipMemcpyDeviceToHost));
+        for (int64_t c = 0; c < n; ++c) h->b[(size_t)kk * n + c] = cplx(x[c].re, x[c].im);
+    }
+    auto t1 = std::chrono::steady_clock::now();
+    inf.seconds = std::chrono::duration<double>(t1 - t0).count();
+    inf.rel_residual = worst;
+    inf.status = status;
+    h->have_solution = true;
+    if (b_out) std::memcpy(b_out, h->b.data(), h->b.size() * sizeof(cplx));
+    if (info) *info = inf;
+    if (status == CELES_E_NOCONV) h->err = "GMRES did not reach the tolerance";
+    if (status == CELES_E_BREAKDOWN) h->err = "GMRES breakdown (non-finite iterate)";
+    return status;
+}
+
+int celes_mie_coefficients(int lmax, double kR, double m_re, double m_im, double* Q_out) {
+    if (lmax < 1 || !(kR > 0) || !Q_out) return CELES_E_ARG;
+    std::vector<cplx> q1(lmax), q2(lmax);
+    celes::mie_Q(lmax, kR, cplx(m_re, m_im), q1.data(), q2.data());
+    for (int l = 0; l < lmax; ++l) {
+        Q_out[2 * l] = q1[l].real();
+        Q_out[2 * l + 1] = q1[l].imag();
+        Q_out[2 * (lmax + l)] = q2[l].real();
+        Q_out[2 * (lmax + l) + 1] = q2[l].imag();
+    }
+    return CELES_OK;
+}
+
+int celes_translation_tables(int lmax, double* a5_out, double* b5im_out) {
+    if (lmax < 1 || lmax > CELES_MAX_LMAX || !a5_out || !b5im_out) return CELES_E_ARG;
+    const int W = 2 * lmax + 1;
+    for (int l = 1; l <= lmax; ++l)
+        for (int m = -lmax; m <= lmax; ++m)
+            for (int lp = 1; lp <= lmax; ++lp)
+                for (int mp = -lmax; mp <= lmax; ++mp)
+                    for (int p = 0; p <= 2 * lmax; ++p) {
+                        size_t o = ((((size_t)(l - 1) * W + (m + lmax)) * lmax + (lp - 1)) * W + (mp + lmax)) * W + p;
+                        bool ok = std::abs(m) <= l && std::abs(mp) <= lp;
+                        a5_out[o] = ok ? celes::a5_coef(l, m, lp, mp, p) : 0.0;
+                        b5im_out[o] = ok ? celes::b5im_coef(l, m, lp, mp, p) : 0.0;
+                    }
+    return CELES_OK;
+}
+
+// ---------------------------------------------------------------------------
+// observables (Appendix D and the SVWF definitions of Appendix A.1)
+// ---------------------------------------------------------------------------
+static void far_field_dir(const celes_handle* h, int kk, double th, double ph, cplx F[3]) {
+    const int L = h->L, nm = h->nmax;
+    const double st = std::sin(th), ct = std::cos(th), sp = std::sin(ph), cp = std::cos(ph);
+    const double rh[3] = {st * cp, st * sp, ct};
+    const double et[3] = {ct * cp, ct * sp, -st};
+    const double ep[3] = {-sp, cp, 0.0};
+    // coefficient sums over spheres: c_n = sum_i e^{-ik rhat.r_i} b_n^i
+    std::vector<cplx> c(nm, cplx(0, 0));
+    for (int64_t i = 0; i < h->N; ++i) {
+        const double* r = &h->pos[3 * i];
+        const cplx e = std::exp(cplx(0, -h->k * (rh[0] * r[0] + rh[1] * r[1] + rh[2] * r[2])));
+        const cplx* b = &h->b[((size_t)kk * h->N + i) * nm];
+        for (int n = 0; n < nm; ++n) c[n] += e * b[n];
+    }
+    F[0] = F[1] = F[2] = 0;
+    const cplx I(0, 1);
+    for (int l = 1; l <= L; ++l) {
+        const cplx mi_l = std::pow(cplx(0, -1), l);
+        for (int m = -l; m <= l; ++m) {
+            double pi, tau;
+            celes::pi_tau(l, std::abs(m), th, &pi, &tau);
+            const cplx e = std::exp(cplx(0, m * ph)) / std::sqrt(2.0 * l * (l + 1));
+            const int c1 = celes::lm_index(l, m), c2 = h->half + c1;
+            // f_{1lm} = (-i)^{l+1} e (i m pi e_theta - tau e_phi); f_{2lm} = (-i)^l e (tau e_theta + i m pi e_phi)
+            const cplx a1 = c[c1] * mi_l * cplx(0, -1) * e, a2 = c[c2] * mi_l * e;
+            const cplx ut = a1 * (I * (double)m * pi) + a2 * tau;
+            const cplx up = -a1 * tau + a2 * (I * (double)m * pi);
+            for (int q = 0; q < 3; ++q) F[q] += ut * et[q] + up * ep[q];
+        }
+    }
+}
+
+static void svwf3(int L, double k, const double* r, int tau, int l, int m, cplx E[3]) {
+    const double rr = std::sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+    const double th = std::acos(std::max(-1.0, std::min(1.0, r[2] / rr))), ph = std::atan2(r[1], r[0]);
+    const double kr = k * rr;
+    cplx hv[16], dh[16];
+    celes::sph_hankel(l, kr, hv, dh);
+    const cplx z = hv[l], dkrz = hv[l] + kr * dh[l];
+    double pi, ta;
+    celes::pi_tau(l, std::abs(m), th, &pi, &ta);
+    std::vector<double> Pt((l + 1) * (l + 1));
+    celes::legendre_table(l, std::cos(th), std::sin(th), Pt.data());
+    const double P = Pt[l * (l + 1) + std::abs(m)];
+    const double st = std::sin(th), ct = std::cos(th), sp = std::sin(ph), cp = std::cos(ph);
+    const double er[3] = {st * cp, st * sp, ct}, et[3] = {ct * cp, ct * sp, -st}, ep[3] = {-sp, cp, 0.0};
+    const cplx e = std::exp(cplx(0, m * ph)) / std::sqrt(2.0 * l * (l + 1));
+    const cplx I(0, 1);
+    for (int q = 0; q < 3; ++q) {
+        if (tau == 1) E[q] = e * z * (I * (double)m * pi * et[q] - ta * ep[q]);
+        else E[q] = e * ((double)(l * (l + 1)) * z / kr * P * er[q] + dkrz / kr * (ta * et[q] + I * (double)m * pi * ep[q]));
+    }
+}
+
+int celes_far_field(celes_handle* h, int64_t ndir, const double* theta, const double* phi, double* F_out) {
+    if (!h) return CELES_E_ARG;
+    if (!h->have_solution) return fail(h, CELES_E_STATE, "no solution");
+    if (ndir < 0 || (ndir > 0 && (!theta || !phi || !F_out))) return fail(h, CELES_E_ARG, "bad direction arrays");
+    for (int kk = 0; kk < h->K; ++kk) {
+#pragma omp parallel for schedule(dynamic, 4)
+        for (int64_t d = 0; d < ndir; ++d) {
+            cplx F[3];
+            far_field_dir(h, kk, theta[d], phi[d], F);
+            for (int q = 0; q < 3; ++q) {
+                F_out[(((size_t)kk * ndir + d) * 3 + q) * 2] = F[q].real();
+                F_out[(((size_t)kk * ndir + d) * 3 + q) * 2 + 1] = F[q].imag();
+            }
+        }
+    }
+    return CELES_OK;
+}
+
+int celes_cross_sections(celes_handle* h, double* C_ext, double* C_sca, double* C_abs) {
+    if (!h) return CELES_E_ARG;
+    if (!h->have_solution) return fail(h, CELES_E_STATE, "no solution");
+    const int64_t N = h->N;
+    const int nm = h->nmax, L = h->L;
+    const double k = h->k;
+    // quadrature sized from the band limit L + k D (D: cluster diameter)
+    double cen[3] = {0, 0, 0};
+    for (int64_t i = 0; i < N; ++i)
+        for (int c = 0; c < 3; ++c) cen[c] += h->pos[3 * i + c] / N;
+    double D = 0;
+    for (int64_t i = 0; i < N; ++i) {
+        double t = 0;
+        for (int c = 0; c < 3; ++c) t += (h->pos[3 * i + c] - cen[c]) * (h->pos[3 * i + c] - cen[c]);
+        D = std::max(D, 2.0 * std::sqrt(t));
+    }
+    const int band = (int)(L + k * D) + 10;
+    const int nt = band + 1, nph = 2 * band + 2;
+    std::vector<double> xg(nt), wg(nt);
+    celes::gauss_legendre(nt, xg.data(), wg.data());
+    for (int kk = 0; kk < h->K; ++kk) {
+        double ext = 0, ab = 0;
+        for (int64_t i = 0; i < N; ++i)
+            for (int tau = 0; tau < 2; ++tau)
+                for (int c = 0; c < h->half; ++c) {
+                    const size_t o = ((size_t)kk * N + i) * nm + tau * h->half + c;
+                    ext += std::real(std::conj(h->a_in[o]) * h->b[o]);
+                    int l = (int)std::floor(std::sqrt((double)(c + 1)));
+                    while (l * (l + 2) < c + 1) ++l;
+                    while ((l - 1) * (l + 1) >= c + 1) --l;
+                    const cplx q = h->tq[((size_t)i * 2 + tau) * L + (l - 1)];
+                    if (std::abs(q) > 0) ab += std::norm(h->b[o]) * (std::real(1.0 / q) + 1.0);
+                }
+        if (C_ext) C_ext[kk] = -M_PI / (k * k) * ext;
+        if (C_abs) C_abs[kk] = -M_PI / (k * k) * ab;
+        if (C_sca) {
+            double sum = 0;
+#pragma omp parallel for reduction(+ : sum) collapse(2) schedule(dynamic, 8)
+            for (int a = 0; a < nt; ++a)
+                for (int bq = 0; bq < nph; ++bq) {
+                    cplx F[3];
+                    far_field_dir(h, kk, std::acos(xg[a]), 2.0 * M_PI * bq / nph, F);
+                    sum += wg[a] * (2.0 * M_PI / nph) * (std::norm(F[0]) + std::norm(F[1]) + std::norm(F[2]));
+                }
+            C_sca[kk] = sum / (k * k);
+        }
+    }
+    return CELES_OK;
+}
+
+int celes_near_field(celes_handle* h, int64_t npt, const double* pts, int add_incident, double* E_out) {
+    if (!h) return CELES_E_ARG;
+    if (!h->have_solution) return fail(h, CELES_E_STATE, "no solution");
+    if (npt < 0 || (npt > 0 && (!pts || !E_out))) return fail(h, CELES_E_ARG, "bad point arrays");
+    const int64_t N = h->N;
+    const int nm = h->nmax, L = h->L;
+    const double k = h->k;
+    for (int kk = 0; kk < h->K; ++kk) {
+#pragma omp parallel for schedule(dynamic, 1)
+        for (int64_t q = 0; q < npt; ++q) {
+            cplx E[3] = {0, 0, 0};
+            for (int64_t i = 0; i < N; ++i) {
+                const double r[3] = {pts[3 * q] - h->pos[3 * i], pts[3 * q + 1] - h->pos[3 * i + 1],
+                                     pts[3 * q + 2] - h->pos[3 * i + 2]};
+                const cplx* b = &h->b[((size_t)kk * N + i) * nm];
+                for (int tau = 1; tau <= 2; ++tau)
+                    for (int l = 1; l <= L; ++l)
+                        for (int m = -l; m <= l; ++m) {
+                            const cplx c = b[(tau - 1) * h->half + celes::lm_index(l, m)];
+                            if (c == cplx(0, 0)) continue;
+                            cplx v[3];
+                            svwf3(L, k, r, tau, l, m, v);
+                            for (int a = 0; a < 3; ++a) E[a] += c * v[a];
+                        }
+            }
+            if (add_incident) {
+                const double* p = &pts[3 * q];
+                if (!h->gaussian) {
+                    const double be = h->pw_beta[kk], al = h->pw_alpha[kk];
+                    const double kv[3] = {k * std::sin(be) * std::cos(al), k * std::sin(be) * std::sin(al), k * std::cos(be)};
+                    const cplx ph = h->pw_E0[kk] * std::exp(cplx(0, kv[0] * p[0] + kv[1] * p[1] + kv[2] * p[2]));
+                    double e[3];
+                    if (h->pw_pol[kk] == 1) { e[0] = -std::sin(al); e[1] = std::cos(al); e[2] = 0; }
+                    else { e[0] = std::cos(be) * std::cos(al); e[1] = std::cos(be) * std::sin(al); e[2] = -std::sin(be); }
+                    for (int a = 0; a < 3; ++a) E[a] += ph * e[a];
+                } else {
+                    // angular-spectrum integral of Appendix C (small-beta polarisation form)
+                    const int nb = 256, na = 256;
+                    std::vector<double> xg(nb), wg(nb);
+                    celes::gauss_legendre(nb, xg.data(), wg.data());
+                    const double w = h->g_waist;
+                    const double r[3] = {p[0] - h->g_focus[0], p[1] - h->g_focus[1], p[2] - h->g_focus[2]};
+                    for (int bq = 0; bq < nb; ++bq) {
+                        const double be = 0.25 * M_PI * (xg[bq] + 1.0), wb = 0.25 * M_PI * wg[bq];
+                        const double sb = std::sin(be), cb = std::cos(be);
+                        const double gq = k * k * w * w / (4 * M_PI) * sb * cb * std::exp(-(w * k * sb) * (w * k * sb) / 4);
+                        for (int aq = 0; aq < na; ++aq) {
+                            const double al = 2 * M_PI * aq / na;
+                            const double ca = std::cos(al), sa = std::sin(al);
+                            const cplx ph = std::exp(cplx(0, k * (sb * ca * r[0] + sb * sa * r[1] + cb * r[2])));
+                            const double pa = std::cos(al - h->g_alpha), qa = std::sin(al - h->g_alpha);
+                            const double pol[3] = {pa * (-sa) + qa * cb * ca, pa * ca + qa * cb * sa, -qa * sb};
+                            const cplx f = h->g_E0 * (wb * 2 * M_PI / na * gq) * ph;
+                            for (int a = 0; a < 3; ++a) E[a] += f * pol[a];
+                        }
+                    }
+                }
+            }
+            for (int a = 0; a < 3; ++a) {
+                E_out[(((size_t)kk * npt + q) * 3 + a) * 2] = E[a].real();
+                E_out[(((size_t)kk * npt + q) * 3 + a) * 2 + 1] = E[a].imag();
+            }
+        }
+    }
+    return CELES_OK;
+}
+
+}  // extern "C"
+

@@ -1,0 +1,313 @@
+#include "precond.hpp"
+
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+namespace celes {
+
+void partition_cuboids(int64_t N, const double* pos, double edge, std::vector<int64_t>* perm,
+                       std::vector<int64_t>* offsets) {
+    double lo[3] = {1e300, 1e300, 1e300};
+    for (int64_t i = 0; i < N; ++i)
+        for (int c = 0; c < 3; ++c) lo[c] = std::min(lo[c], pos[3 * i + c]);
+    std::vector<int64_t> cell(3 * N);
+    int64_t nc[3] = {0, 0, 0};
+    for (int64_t i = 0; i < N; ++i)
+        for (int c = 0; c < 3; ++c) {
+            cell[3 * i + c] = (int64_t)std::floor((pos[3 * i + c] - lo[c]) / edge);
+            nc[c] = std::max(nc[c], cell[3 * i + c] + 1);
+        }
+    std::vector<int64_t> lin(N);
+    for (int64_t i = 0; i < N; ++i) lin[i] = cell[3 * i] + nc[0] * (cell[3 * i + 1] + nc[1] * cell[3 * i + 2]);
+    perm->resize(N);
+    std::iota(perm->begin(), perm->end(), 0);
+    std::stable_sort(perm->begin(), perm->end(), [&](int64_t a, int64_t b) { return lin[a] < lin[b]; });
+    offsets->clear();
+    for (int64_t t = 0; t < N; ++t)
+        if (t == 0 || lin[(*perm)[t]] != lin[(*perm)[t - 1]]) offsets->push_back(t);
+    offsets->push_back(N);
+}
+
+// ---------------------------------------------------------------------------
+// assembly: M_j[r, c] = delta_rc - Q_n(a) W^{ab}_{n n'}, r = a nmax + n,
+// c = b nmax + n' (column-major), W^{ab}_{nn'} = A_{n'n}(r_a - r_b).
+// One thread per (block, a, b, receiving (l, m)).
+// ---------------------------------------------------------------------------
+struct AsmArgs {
+    const double* pos;          // [N][3]
+    const int64_t* perm;
+    const int64_t* boff;
+    const int64_t* moff;
+    const cx<double>* tq;       // [N][2][L]
+    const double* a5;           // [L][2L+1][L][2L+1][2L+1]
+    const double* b5;
+    const cx<double>* lut;      // [n_int][2L+1][4]
+    double lut_lo, lut_inv_dr;
+    int lut_n;
+    double k;
+    int L, hmode, blk;
+    cx<double>* mat;
+};
+
+__device__ inline void hankel_row(const AsmArgs& g, double d, cx<double>* h) {
+    const int P = 2 * g.L;
+    if (g.hmode == 0) {
+        double s = (d - g.lut_lo) * g.lut_inv_dr;
+        int q = (int)s;
+        q = q < 0 ? 0 : (q >= g.lut_n ? g.lut_n - 1 : q);
+        double t = s - q;
+        const cx<double>* c = g.lut + (size_t)q * (P + 1) * 4;
+        for (int p = 0; p <= P; ++p) {
+            h[p].re = ((c[4 * p + 3].re * t + c[4 * p + 2].re) * t + c[4 * p + 1].re) * t + c[4 * p].re;
+            h[p].im = ((c[4 * p + 3].im * t + c[4 * p + 2].im) * t + c[4 * p + 1].im) * t + c[4 * p].im;
+        }
+    } else {
+        double x = g.k * d, s, cc;
+        sincos(x, &s, &cc);
+        double inv = 1.0 / x;
+        h[0] = {s * inv, -cc * inv};
+        h[1] = {(h[0].re - cc) * inv, (h[0].im - s) * inv};
+        for (int p = 1; p < P; ++p) {
+            double f = (2.0 * p + 1.0) * inv;
+            h[p + 1] = {f * h[p].re - h[p - 1].re, f * h[p].im - h[p - 1].im};
+        }
+    }
+}
+
+__global__ void assemble_kernel(AsmArgs g, int64_t ntot) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ntot) return;
+    const int L = g.L, half = L * (L + 2), nmax = 2 * half, W = 2 * L + 1;
+    const int64_t o = g.boff[g.blk], nj = g.boff[g.blk + 1] - o;
+    const int c_out = (int)(t % half);
+    const int64_t ab = t / half;
+    const int64_t a = ab % nj, b = ab / nj;
+    const int64_t dim = nj * nmax;
+    cx<double>* M = g.mat + g.moff[g.blk];
+    const int l = (int)floor(sqrt((double)(c_out + 1)));
+    int ll = l;
+    while (ll * (ll + 2) < c_out + 1) ++ll;
+    while ((ll - 1) * (ll + 1) >= c_out + 1) --ll;
+    const int m = c_out + 1 - ll * (ll + 1);
+    const int64_t ia = g.perm[o + a], ib = g.perm[o + b];
+    if (a == b) {
+        for (int tau = 0; tau < 2; ++tau)
+            for (int tp = 0; tp < 2; ++tp)
+                for (int cp = 0; cp < half; ++cp) {
+                    int64_t r = a * nmax + tau * half + c_out, c = b * nmax + tp * half + cp;
+                    M[r + c * dim] = {(r == c) ? 1.0 : 0.0, 0.0};
+                }
+        return;
+    }
+    const double dx = g.pos[3 * ia] - g.pos[3 * ib], dy = g.pos[3 * ia + 1] - g.pos[3 * ib + 1],
+                 dz = g.pos[3 * ia + 2] - g.pos[3 * ib + 2];
+    const double rho = sqrt(dx * dx + dy * dy), d = sqrt(dx * dx + dy * dy + dz * dz);
+    const double ct = dz / d, st = rho / d;
+    const double ph = rho > 0 ? atan2(dy, dx) : 0.0;
+    cx<double> h[13];
+    hankel_row(g, d, h);
+    // normalized Legendre P_p^mu(ct), 0 <= mu <= p <= 2L
+    double P[13][13];
+    double pmm = 0.70710678118654752440;
+    for (int mu = 0; mu <= 2 * L; ++mu) {
+        if (mu > 0) pmm *= sqrt((2.0 * mu + 1.0) / (2.0 * mu)) * st;
+        P[mu][mu] = pmm;
+        if (mu + 1 <= 2 * L) P[mu + 1][mu] = sqrt(2.0 * mu + 3.0) * ct * pmm;
+        for (int p = mu + 2; p <= 2 * L; ++p) {
+            double aa = sqrt((4.0 * p * p - 1.0) / ((double)p * p - (double)mu * mu));
+            double bb = sqrt((2.0 * p + 1.0) * ((p - 1.0) * (p - 1.0) - (double)mu * mu) /
+                             ((2.0 * p - 3.0) * ((double)p * p - (double)mu * mu)));
+            P[p][mu] = aa * ct * P[p - 1][mu] - bb * P[p - 2][mu];
+        }
+    }
+    const cx<double> q1 = g.tq[(ia * 2 + 0) * L + (ll - 1)], q2 = g.tq[(ia * 2 + 1) * L + (ll - 1)];
+    for (int lp = 1; lp <= L; ++lp)
+        for (int mp = -lp; mp <= lp; ++mp) {
+            const int mu = abs(mp - m);
+            double Are = 0, Aim = 0, Bre = 0, Bim = 0;
+            for (int p = 0; p <= 2 * L; ++p) {
+                if (p < mu) continue;
+                // coefficient a5(l', m' | l, m | p) (source first)
+                size_t co = ((((size_t)(lp - 1) * W + (mp + L)) * L + (ll - 1)) * W + (m + L)) * W + p;
+                const double ca = g.a5[co], cb = g.b5[co];
+                const double hp = P[p][mu];
+                Are += ca * h[p].re * hp;
+                Aim += ca * h[p].im * hp;
+                Bre += cb * h[p].re * hp;
+                Bim += cb * h[p].im * hp;
+            }
+            double s, c;
+            sincos((double)(mp - m) * ph, &s, &c);
+            const cx<double> A = {Are * c - Aim * s, Are * s + Aim * c};
+            // B = i * (Bre + i Bim) * e^{i(m'-m) phi}
+            const cx<double> Bp = {Bre * c - Bim * s, Bre * s + Bim * c};
+            const cx<double> B = {-Bp.im, Bp.re};
+            const int cp = lp * (lp + 1) + mp - 1;
+            for (int tau = 0; tau < 2; ++tau) {
+                const cx<double> q = tau == 0 ? q1 : q2;
+                for (int tp = 0; tp < 2; ++tp) {
+                    const cx<double> w = (tau == tp) ? A : B;
+                    int64_t r = a * nmax + tau * half + c_out, col = b * nmax + tp * half + cp;
+                    M[r + col * dim] = {-(q.re * w.re - q.im * w.im), -(q.re * w.im + q.im * w.re)};
+                }
+            }
+        }
+}
+
+// out[perm rows of block j] = Minv_j * in[perm rows of block j]; one thread per row
+template <typename T>
+__global__ void __launch_bounds__(256) apply_kernel(const cx<double>* __restrict__ inv, const int64_t* __restrict__ perm,
+                                                    const int64_t* __restrict__ boff, const int64_t* __restrict__ moff,
+                                                    int nmax, const cx<T>* __restrict__ in, cx<T>* __restrict__ out) {
+    const int j = blockIdx.y;
+    const int64_t o = boff[j], nj = boff[j + 1] - o, dim = nj * nmax;
+    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if ((int64_t)blockIdx.x * 256 >= dim) return;
+    const cx<double>* M = inv + moff[j];
+    double re = 0, im = 0;
+    if (r < dim) {
+        for (int64_t c = 0; c < dim; ++c) {
+            const int64_t src = perm[o + c / nmax] * nmax + c % nmax;
+            const cx<T> x = in[src];
+            const cx<double> a = M[r + c * dim];
+            re += a.re * (double)x.re - a.im * (double)x.im;
+            im += a.re * (double)x.im + a.im * (double)x.re;
+        }
+        const int64_t dst = perm[o + r / nmax] * nmax + r % nmax;
+        out[dst] = {(T)re, (T)im};
+    }
+}
+
+BlockPrecond::~BlockPrecond() {
+    if (d_perm_) hipFree(d_perm_);
+    if (d_boff_) hipFree(d_boff_);
+    if (d_moff_) hipFree(d_moff_);
+    if (d_inv_) hipFree(d_inv_);
+}
+
+int BlockPrecond::build(int64_t N, int L, const double* pos, double k, const cplx* tq, double edge, int hmode,
+                        const void* lut_dev, double lut_lo, double lut_dr, int lut_n, std::string* msg) {
+    N_ = N;
+    L_ = L;
+    nmax_ = 2 * L * (L + 2);
+    partition_cuboids(N, pos, edge, &perm_, &offsets_);
+    const int nb = (int)offsets_.size() - 1;
+    std::vector<int64_t> moff(nb);
+    mat_elems_ = 0;
+    max_dim_ = 0;
+    for (int j = 0; j < nb; ++j) {
+        int64_t dim = (offsets_[j + 1] - offsets_[j]) * nmax_;
+        moff[j] = (int64_t)mat_elems_;
+        mat_elems_ += (size_t)dim * dim;
+        max_dim_ = std::max<int>(max_dim_, (int)dim);
+    }
+    auto dev = [&](void** p, size_t bytes) { return hipMalloc(p, bytes) == hipSuccess; };
+    if (!dev((void**)&d_perm_, N * 8) || !dev((void**)&d_boff_, (nb + 1) * 8) || !dev((void**)&d_moff_, nb * 8) ||
+        !dev((void**)&d_inv_, mat_elems_ * sizeof(cx<double>))) {
+        *msg = "cannot allocate the preconditioner (" + std::to_string(mat_elems_ * 16 / (1 << 20)) + " MiB)";
+        return CELES_E_OOM_INTERNAL;
+    }
+    hipMemcpy(d_perm_, perm_.data(), N * 8, hipMemcpyHostToDevice);
+    hipMemcpy(d_boff_, offsets_.data(), (nb + 1) * 8, hipMemcpyHostToDevice);
+    hipMemcpy(d_moff_, moff.data(), nb * 8, hipMemcpyHostToDevice);
+    // coefficient tables and per-sphere data
+    const int W = 2 * L + 1;
+    const size_t tsz = (size_t)L * W * L * W * W;
+    std::vector<double> a5(tsz, 0.0), b5(tsz, 0.0);
+    for (int l = 1; l <= L; ++l)
+        for (int m = -l; m <= l; ++m)
+            for (int lp = 1; lp <= L; ++lp)
+                for (int mp = -lp; mp <= lp; ++mp)
+                    for (int p = 0; p <= 2 * L; ++p) {
+                        size_t o = ((((size_t)(l - 1) * W + (m + L)) * L + (lp - 1)) * W + (mp + L)) * W + p;
+                        a5[o] = a5_coef(l, m, lp, mp, p);
+                        b5[o] = b5im_coef(l, m, lp, mp, p);
+                    }
+    double *d_a5 = nullptr, *d_b5 = nullptr, *d_pos = nullptr;
+    cx<double>* d_tq = nullptr;
+    std::vector<cx<double>> t64((size_t)N * 2 * L);
+    for (size_t i = 0; i < t64.size(); ++i) t64[i] = {tq[i].real(), tq[i].imag()};
+    if (!dev((void**)&d_a5, tsz * 8) || !dev((void**)&d_b5, tsz * 8) || !dev((void**)&d_pos, N * 24) ||
+        !dev((void**)&d_tq, t64.size() * 16)) {
+        *msg = "cannot allocate assembly tables";
+        return CELES_E_OOM_INTERNAL;
+    }
+    hipMemcpy(d_a5, a5.data(), tsz * 8, hipMemcpyHostToDevice);
+    hipMemcpy(d_b5, b5.data(), tsz * 8, hipMemcpyHostToDevice);
+    hipMemcpy(d_pos, pos, N * 24, hipMemcpyHostToDevice);
+    hipMemcpy(d_tq, t64.data(), t64.size() * 16, hipMemcpyHostToDevice);
+    AsmArgs g;
+    g.pos = d_pos;
+    g.perm = d_perm_;
+    g.boff = d_boff_;
+    g.moff = d_moff_;
+    g.tq = d_tq;
+    g.a5 = d_a5;
+    g.b5 = d_b5;
+    g.lut = (const cx<double>*)lut_dev;
+    g.lut_lo = lut_lo;
+    g.lut_inv_dr = 1.0 / lut_dr;
+    g.lut_n = lut_n;
+    g.k = k;
+    g.L = L;
+    g.hmode = hmode;
+    g.mat = d_inv_;
+    rocblas_handle rb;
+    if (rocblas_create_handle(&rb) != rocblas_status_success) {
+        *msg = "rocblas_create_handle failed";
+        return CELES_E_DEVICE_INTERNAL;
+    }
+    rocblas_int *d_ipiv = nullptr, *d_info = nullptr;
+    dev((void**)&d_ipiv, (size_t)max_dim_ * sizeof(rocblas_int));
+    dev((void**)&d_info, sizeof(rocblas_int));
+    int rc = 0;
+    for (int j = 0; j < nb && rc == 0; ++j) {
+        g.blk = j;
+        const int64_t nj = offsets_[j + 1] - offsets_[j];
+        const int64_t ntot = nj * nj * (nmax_ / 2);
+        hipLaunchKernelGGL(assemble_kernel, dim3((unsigned)((ntot + 255) / 256)), dim3(256), 0, 0, g, ntot);
+        const int dim = (int)(nj * nmax_);
+        rocblas_double_complex* A = (rocblas_double_complex*)(d_inv_ + moff[j]);
+        if (rocsolver_zgetrf(rb, dim, dim, A, dim, d_ipiv, d_info) != rocblas_status_success ||
+            rocsolver_zgetri(rb, dim, A, dim, d_ipiv, d_info) != rocblas_status_success) {
+            *msg = "rocsolver LU/inverse failed";
+            rc = CELES_E_DEVICE_INTERNAL;
+        }
+        rocblas_int info = 0;
+        hipMemcpy(&info, d_info, sizeof(info), hipMemcpyDeviceToHost);
+        if (info != 0) {
+            *msg = "singular preconditioner block " + std::to_string(j);
+            rc = CELES_E_DEVICE_INTERNAL;
+        }
+    }
+    hipDeviceSynchronize();
+    rocblas_destroy_handle(rb);
+    hipFree(d_ipiv);
+    hipFree(d_info);
+    hipFree(d_a5);
+    hipFree(d_b5);
+    hipFree(d_pos);
+    hipFree(d_tq);
+    if (hipGetLastError() != hipSuccess && rc == 0) {
+        *msg = "preconditioner assembly failed";
+        rc = CELES_E_DEVICE_INTERNAL;
+    }
+    return rc;
+}
+
+template <typename T>
+int BlockPrecond::apply(const cx<T>* in, cx<T>* out, hipStream_t s) const {
+    const int nb = (int)offsets_.size() - 1;
+    dim3 grid((unsigned)((max_dim_ + 255) / 256), (unsigned)nb);
+    hipLaunchKernelGGL(apply_kernel<T>, grid, dim3(256), 0, s, d_inv_, d_perm_, d_boff_, d_moff_, nmax_, in, out);
+    return hipGetLastError() == hipSuccess ? 0 : CELES_E_DEVICE_INTERNAL;
+}
+
+template int BlockPrecond::apply<double>(const cx<double>*, cx<double>*, hipStream_t) const;
+template int BlockPrecond::apply<float>(const cx<float>*, cx<float>*, hipStream_t) const;
+
+}  // namespace celes

@@ -1,0 +1,54 @@
+// Block-diagonal preconditioner (paper, Section 3.2.1): the spheres are
+// partitioned into cuboids, the diagonal blocks M_j = I - T W_jj are
+// assembled on the device and factorised in FP64, and applying the
+// preconditioner multiplies each block of a vector by M_j^{-1}.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "device_common.hpp"
+#include "host_math.hpp"
+
+namespace celes {
+
+// error codes returned by BlockPrecond (same values as the C ABI's)
+constexpr int CELES_E_OOM_INTERNAL = -7;
+constexpr int CELES_E_DEVICE_INTERNAL = -8;
+
+class BlockPrecond {
+   public:
+    ~BlockPrecond();
+    // pos [N][3], tq [N][2][L] (host); lut_dev: FP64 Hankel table (LUT mode)
+    int build(int64_t N, int L, const double* pos, double k, const cplx* tq, double edge, int hmode,
+              const void* lut_dev, double lut_lo, double lut_dr, int lut_n, std::string* msg);
+    // out = P^{-1} in (in, out: [N][nmax] device vectors, must not alias)
+    template <typename T>
+    int apply(const cx<T>* in, cx<T>* out, hipStream_t s) const;
+
+    int num_blocks() const { return (int)offsets_.size() - 1; }
+    const std::vector<int64_t>& perm() const { return perm_; }
+    const std::vector<int64_t>& offsets() const { return offsets_; }
+    size_t bytes() const { return mat_elems_ * 16; }
+
+   private:
+    int L_ = 0, nmax_ = 0;
+    int64_t N_ = 0;
+    std::vector<int64_t> perm_, offsets_;
+    size_t mat_elems_ = 0;
+    int max_dim_ = 0;
+    int64_t* d_perm_ = nullptr;      // [N] new -> old sphere index
+    int64_t* d_boff_ = nullptr;      // [nb+1] sphere offsets
+    int64_t* d_moff_ = nullptr;      // [nb] matrix element offsets
+    cx<double>* d_inv_ = nullptr;    // block inverses, column-major, concatenated
+};
+
+// partition of Section 3.2.1 step 1: cubes of edge `edge` anchored at the
+// minimum corner of the centres' bounding box; spheres ordered by (cell linear
+// index with x fastest, then y, then z; original index); empty cells skipped.
+void partition_cuboids(int64_t N, const double* pos, double edge, std::vector<int64_t>* perm,
+                       std::vector<int64_t>* offsets);
+
+}  // namespace celes

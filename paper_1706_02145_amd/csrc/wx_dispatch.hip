@@ -1,0 +1,88 @@
+// Dispatch of the coupling mat-vec: prep (sum/difference form), the per-L
+// pass kernels (wx_kernels.hip), and the chunk reduction with the optional
+// M = I - T W epilogue (paper, Section 2.2 eq. M).
+#include <hip/hip_runtime.h>
+
+#include "device_common.hpp"
+#include "wx_launch.hpp"
+
+namespace celes {
+
+// x [N][nmax] (tau blocks) -> xsd [N][2][HALF] with s = x1 + x2, d = x1 - x2
+template <typename T>
+__global__ void wx_prep_kernel(const cx<T>* __restrict__ x, cx<T>* __restrict__ xsd, int n, int half) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * half) return;
+    const int i = t / half, c = t % half;
+    const cx<T> a = x[(size_t)i * 2 * half + c], b = x[(size_t)i * 2 * half + half + c];
+    xsd[(size_t)i * 2 * half + c] = {a.re + b.re, a.im + b.im};
+    xsd[(size_t)i * 2 * half + half + c] = {a.re - b.re, a.im - b.im};
+}
+
+// sum partials over chunks, convert to (tau, l, m), optional y = x - T (W x)
+template <typename T>
+__global__ void wx_finish_kernel(const cx<T>* __restrict__ part, int nchunk, int ldp, int n, int L,
+                                 const cx<T>* __restrict__ x, const cx<T>* __restrict__ tq,
+                                 cx<T>* __restrict__ y, int epilogue) {
+    const int half = L * (L + 2);
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * half) return;
+    const int c = t / n, i = t % n;      // consecutive lanes: consecutive spheres (coalesced part reads)
+    cx<T> sp = {0, 0}, sm = {0, 0};
+    for (int ch = 0; ch < nchunk; ++ch) {
+        const cx<T> a = part[((size_t)ch * 2 * half + c) * ldp + i];
+        const cx<T> b = part[((size_t)ch * 2 * half + half + c) * ldp + i];
+        sp.re += a.re; sp.im += a.im;
+        sm.re += b.re; sm.im += b.im;
+    }
+    cx<T> y1 = {(T)0.5 * (sp.re + sm.re), (T)0.5 * (sp.im + sm.im)};
+    cx<T> y2 = {(T)0.5 * (sp.re - sm.re), (T)0.5 * (sp.im - sm.im)};
+    const size_t b1 = (size_t)i * 2 * half + c, b2 = b1 + half;
+    if (epilogue) {
+        // l of the (l, m) index c: l(l+1)+m-1 = c  ->  l = floor(sqrt(c+1))
+        int l = (int)sqrtf((float)(c + 1));
+        while (l * (l + 2) < c + 1) ++l;
+        while ((l - 1) * (l + 1) >= c + 1) --l;
+        const cx<T> q1 = tq[((size_t)i * 2 + 0) * L + (l - 1)];
+        const cx<T> q2 = tq[((size_t)i * 2 + 1) * L + (l - 1)];
+        const cx<T> x1 = x[b1], x2 = x[b2];
+        const cx<T> t1 = cmul(q1, y1), t2 = cmul(q2, y2);
+        y1 = {x1.re - t1.re, x1.im - t1.im};
+        y2 = {x2.re - t2.re, x2.im - t2.im};
+    }
+    y[b1] = y1;
+    y[b2] = y2;
+}
+
+template <typename T>
+int wx_launch(const WxArgs<T>& a, int L, int hmode, int nchunk, const cx<T>* x, const cx<T>* tq,
+              cx<T>* y, int epilogue, hipStream_t s) {
+    const int half = L * (L + 2);
+    {
+        int tot = a.n * half;
+        hipLaunchKernelGGL(wx_prep_kernel<T>, dim3((tot + 255) / 256), dim3(256), 0, s, x, const_cast<cx<T>*>(a.xsd), a.n, half);
+    }
+switch (L) {
+        case 1: wx_run_L<T, 1>(a, hmode, nchunk, s); break;
+        case 2: wx_run_L<T, 2>(a, hmode, nchunk, s); break;
+        case 3: wx_run_L<T, 3>(a, hmode, nchunk, s); break;
+        case 4: wx_run_L<T, 4>(a, hmode, nchunk, s); break;
+        case 5: wx_run_L<T, 5>(a, hmode, nchunk, s); break;
+        case 6: wx_run_L<T, 6>(a, hmode, nchunk, s); break;
+        default: return -1;
+    }
+
+    {
+        int tot = a.n * half;
+        hipLaunchKernelGGL(wx_finish_kernel<T>, dim3((tot + 255) / 256), dim3(256), 0, s, a.part, nchunk,
+                           a.ldp, a.n, L, x, tq, y, epilogue);
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+template int wx_launch<double>(const WxArgs<double>&, int, int, int, const cx<double>*, const cx<double>*,
+                               cx<double>*, int, hipStream_t);
+template int wx_launch<float>(const WxArgs<float>&, int, int, int, const cx<float>*, const cx<float>*,
+                              cx<float>*, int, hipStream_t);
+
+}  // namespace celes

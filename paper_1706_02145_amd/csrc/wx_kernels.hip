@@ -1,0 +1,284 @@
+// Coupling mat-vec W x evaluated on the fly (paper, Section 2.2 eq. a and
+// Section 3.2.2), hand-written for gfx950.
+//
+// Mapping.  One lane = one receiving sphere i; a wave walks a contiguous
+// chunk of source spheres i' that is uniform across the wave, so all source
+// data (position and the source coefficients) comes in through scalar loads
+// and the VALU works only on per-lane pair quantities.  Work on one pair is
+// split into passes by the receiving |m| = M0 (a kernel instantiation per
+// pass): a pass keeps only its own accumulators live, which is what lets the
+// FP64 L = 4 kernel run without spilling, and it reuses every reduced
+// translation coefficient for m = +M0 and m = -M0.
+//
+// Polarisation structure.  With x_1, x_2 the tau = 1, 2 halves of a source
+// vector, the block [[A, B], [B, A]] acts as (A + B)(x_1 + x_2) and
+// (A - B)(x_1 - x_2).  The kernels therefore consume s = x_1 + x_2 and
+// d = x_1 - x_2 and produce y_1 + y_2 and y_1 - y_2; prep/finish kernels
+// convert.  b5 is purely imaginary (b5 = i b5im), so A +- B = A +- i B'.
+//
+// Split over sources.  Each (receiver tile, source chunk) writes its partial
+// sums to part[chunk][k][i]; wx_finish reduces over chunks in a fixed order
+// (deterministic), converts back to (tau, l, m) and applies the optional
+// y = x - T (W x) epilogue of eq. M.
+#include <hip/hip_runtime.h>
+#include <type_traits>
+
+#include "device_common.hpp"
+#include "wx_plan.hpp"
+#include "wx_launch.hpp"
+
+#define WX_BLOCK WX_BLOCK_SIZE   // receivers per block (4 waves share one source tile)
+#define WX_TILE WX_TILE_SIZE     // sources per LDS tile
+
+// This translation unit instantiates the kernels of one multipole cut-off,
+// CELES_WX_L, so that the cut-offs compile in parallel.
+#ifndef CELES_WX_L
+#error "define CELES_WX_L (1..6)"
+#endif
+
+namespace celes {
+
+using namespace plan;
+
+// compile-time loop: f(integral_constant<int, B>), ..., f(integral_constant<int, E-1>)
+template <int B, int E, typename F>
+__device__ __forceinline__ void sfor(F&& f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        sfor<B + 1, E>(f);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// spherical Hankel functions h_p(kd), p = 0..2L
+// ---------------------------------------------------------------------------
+template <typename T, int P>
+__device__ __forceinline__ void hankel_direct(double kd, cx<T> (&h)[P + 1]) {
+    // h_0 = -i e^{ix}/x, h_1 = -e^{ix}(x + i)/x^2, h_{p+1} = (2p+1)/x h_p - h_{p-1}
+    double s, c;
+    sincos(kd, &s, &c);
+    double inv = 1.0 / kd;
+    double h0r = s * inv, h0i = -c * inv;
+    double h1r = (h0r - c) * inv;   // (s/x - c)/x
+    double h1i = (h0i - s) * inv;   // (-c/x - s)/x
+    if constexpr (sizeof(T) == 8) {
+        h[0] = {h0r, h0i};
+        if constexpr (P >= 1) h[1] = {h1r, h1i};
+#pragma unroll
+        for (int p = 1; p < P; ++p) {
+            double f = (2.0 * p + 1.0) * inv;
+            h[p + 1] = {f * h[p].re - h[p - 1].re, f * h[p].im - h[p - 1].im};
+        }
+    } else {
+        float fi = (float)inv;
+        h[0] = {(float)h0r, (float)h0i};
+        if constexpr (P >= 1) h[1] = {(float)h1r, (float)h1i};
+#pragma unroll
+        for (int p = 1; p < P; ++p) {
+            float f = (2.0f * p + 1.0f) * fi;
+            h[p + 1] = {f * h[p].re - h[p - 1].re, f * h[p].im - h[p - 1].im};
+        }
+    }
+}
+
+template <typename T, int P>
+__device__ __forceinline__ void hankel_lut(double d, const LutView<T>& lut, cx<T> (&h)[P + 1]) {
+    // cubic Hermite on [d_q, d_q + dr], coefficients in Horner order c0..c3 of t
+    double s = (d - lut.d_lo) * lut.inv_dr;
+    int q = (int)s;
+    q = q < 0 ? 0 : (q >= lut.n_int ? lut.n_int - 1 : q);
+    T t = (T)(s - (double)q);
+    const cx<T>* c = lut.coef + (size_t)q * (P + 1) * 4;
+#pragma unroll
+    for (int p = 0; p <= P; ++p) {
+        cx<T> c0 = c[4 * p], c1 = c[4 * p + 1], c2 = c[4 * p + 2], c3 = c[4 * p + 3];
+        h[p].re = fma(fma(fma(c3.re, t, c2.re), t, c1.re), t, c0.re);
+        h[p].im = fma(fma(fma(c3.im, t, c2.im), t, c1.im), t, c0.im);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// one pass of the coupling mat-vec
+// ---------------------------------------------------------------------------
+template <typename T, int L, int M0, int HMODE>
+__global__ __launch_bounds__(WX_BLOCK) void wx_pass_kernel(WxArgs<T> a) {
+    constexpr int HALF = L * (L + 2);
+    constexpr int P2 = 2 * L;
+    constexpr int LLO = l_lo(M0);
+    constexpr int NL = L - LLO + 1;
+    constexpr int MUMAX = mu_max(L, M0);
+    constexpr bool MIRROR = M0 > 0;
+
+    const int i = blockIdx.x * WX_BLOCK + threadIdx.x;
+    // source tile staged in LDS; every lane reads the same element (broadcast)
+    __shared__ cx<T> tile[WX_TILE * 2 * HALF];
+    const int chunk = blockIdx.y;
+    const bool active = i < a.n;
+    const double xi = active ? a.px[i] : 0.0;
+    const double yi = active ? a.py[i] : 0.0;
+    const double zi = active ? a.pz[i] : 0.0;
+
+    cx<T> accP[NL], accM[NL], accPm[NL], accMm[NL];
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+        accP[q] = {0, 0};
+        accM[q] = {0, 0};
+        accPm[q] = {0, 0};
+        accMm[q] = {0, 0};
+    }
+
+    const int j0 = chunk * a.chunk_len;
+    const int j1 = min(a.n, j0 + a.chunk_len);
+    for (int t0 = j0; t0 < j1; t0 += WX_TILE) {
+      const int nt = min(WX_TILE, j1 - t0);
+      __syncthreads();
+      {
+        const cx<T>* src = a.xsd + (size_t)t0 * (2 * HALF);
+        for (int e = threadIdx.x; e < nt * 2 * HALF; e += WX_BLOCK) tile[e] = src[e];
+      }
+      __syncthreads();
+      for (int jj = 0; jj < nt; ++jj) {
+        const int j = t0 + jj;
+        if (!active || j == i) continue;
+        // ---- pair geometry (FP64) ----
+        const double dx = xi - a.px[j], dy = yi - a.py[j], dz = zi - a.pz[j];
+        const double rho2 = dx * dx + dy * dy;
+        const double r = sqrt(rho2 + dz * dz);
+        const double inv_r = 1.0 / r;
+        const double rho = sqrt(rho2);
+        const T ct = (T)(dz * inv_r), st = (T)(rho * inv_r);
+        T cph = 1, sph = 0;
+        if (rho > 0.0) {
+            const double ir = 1.0 / rho;
+            cph = (T)(dx * ir);
+            sph = (T)(dy * ir);
+        }
+        // ---- radial functions ----
+        cx<T> h[P2 + 1];
+        if constexpr (HMODE == 0)
+            hankel_lut<T, P2>(r, a.lut, h);
+        else
+            hankel_direct<T, P2>(a.k * r, h);
+
+            const cx<T>* xs = tile + jj * (2 * HALF);
+        const cx<T> e1 = {cph, sph};
+        cx<T> emu = {1, 0};
+        T pmm = (T)0.70710678118654752440;   // P_0^0
+        sfor<0, MUMAX + 1>([&](auto MU_) {
+            constexpr int mu = decltype(MU_)::value;
+            if constexpr (mu > 0) {
+                constexpr double cd = leg_diag(mu);
+                pmm = (T)cd * st * pmm;
+                emu = cmul(emu, e1);
+            }
+            // Legendre column P_p^mu, p = mu..2L, and H_p = h_p P_p^mu
+            T Pc[P2 + 1];
+            cx<T> H[P2 + 1];
+            sfor<mu, P2 + 1>([&](auto PP_) {
+                constexpr int p = decltype(PP_)::value;
+                if constexpr (p == mu) {
+                    Pc[p] = pmm;
+                } else if constexpr (p == mu + 1) {
+                    constexpr double cs = leg_sub(mu);
+                    Pc[p] = (T)cs * ct * pmm;
+                } else {
+                    constexpr double ca = leg_a(p, mu), cb = leg_b(p, mu);
+                    Pc[p] = (T)ca * ct * Pc[p - 1] - (T)cb * Pc[p - 2];
+                }
+                H[p] = {h[p].re * Pc[p], h[p].im * Pc[p]};
+            });
+            sfor<0, 2>([&](auto SG_) {
+                constexpr int sgn = decltype(SG_)::value == 0 ? 1 : -1;
+                if constexpr (branch(L, M0, mu, sgn)) {
+                    constexpr int mp = M0 + sgn * mu;
+                    constexpr bool two = MIRROR || mu > 0;
+                    const cx<T> rot = sgn > 0 ? emu : cx<T>{emu.re, -emu.im};
+                    const cx<T> rotc = {rot.re, -rot.im};
+                    sfor<lp_lo(mp), L + 1>([&](auto LP_) {
+                        constexpr int lp = decltype(LP_)::value;
+                        // keep the group's LDS reads next to their use (bounded live range)
+                        __builtin_amdgcn_sched_barrier(0);
+                        // source coefficients of (l', m') and of the mirror (l', -m')
+                        const cx<T> s1 = xs[lp * (lp + 1) + mp - 1];
+                        const cx<T> d1 = xs[HALF + lp * (lp + 1) + mp - 1];
+                        const cx<T> ts = cmul(rot, s1), td = cmul(rot, d1);
+                        cx<T> us = {0, 0}, ud = {0, 0};
+                        if constexpr (two) {
+                            const cx<T> s2 = xs[lp * (lp + 1) - mp - 1];
+                            const cx<T> d2 = xs[HALF + lp * (lp + 1) - mp - 1];
+                            us = cmul(rotc, s2);
+                            ud = cmul(rotc, d2);
+                        }
+                        sfor<LLO, L + 1>([&](auto LL_) {
+                            constexpr int l = decltype(LL_)::value;
+                            constexpr int pa0 = pa_lo(l, lp, mu), nA = na(l, lp, mu);
+                            constexpr int pb0 = pb_lo(l, lp, mu), nB = nb(l, lp, mu);
+                            cx<T> A = {0, 0}, B = {0, 0};
+                            sfor<0, nA>([&](auto QA_) {
+                                constexpr int t = decltype(QA_)::value;
+                                constexpr double cv = ca5(lp, mp, l, M0, pa0 + 2 * t);
+                                const T c = (T)cv;
+                                A.re = fma(c, H[pa0 + 2 * t].re, A.re);
+                                A.im = fma(c, H[pa0 + 2 * t].im, A.im);
+                            });
+                            sfor<0, nB>([&](auto QB_) {
+                                constexpr int t = decltype(QB_)::value;
+                                constexpr double cv = cb5im(lp, mp, l, M0, pb0 + 2 * t);
+                                const T c = (T)cv;
+                                B.re = fma(c, H[pb0 + 2 * t].re, B.re);
+                                B.im = fma(c, H[pb0 + 2 * t].im, B.im);
+                            });
+                            // P = A + iB, Q = A - iB
+                            const cx<T> Pv = {A.re - B.im, A.im + B.re};
+                            const cx<T> Qv = {A.re + B.im, A.im - B.re};
+                            constexpr int q = l - LLO;
+                            cfma(accP[q], Pv, ts);
+                            cfma(accM[q], Qv, td);
+                            if constexpr (MIRROR) {
+                                cfma(accPm[q], Qv, us);
+                                cfma(accMm[q], Pv, ud);
+                            } else if constexpr (two) {
+                                cfma(accP[q], Qv, us);
+                                cfma(accM[q], Pv, ud);
+                            }
+                        });
+                    });
+                }
+            });
+        });
+      }
+    }
+    if (!active) return;
+    // partial sums: part[chunk][kk][i], kk = plus-space (l,m) or HALF + minus-space (l,m)
+    cx<T>* out = a.part + (size_t)chunk * (2 * HALF) * a.ldp;
+#pragma unroll
+    for (int l = LLO; l <= L; ++l) {
+        const int q = l - LLO;
+        out[(size_t)(l * (l + 1) + M0 - 1) * a.ldp + i] = accP[q];
+        out[(size_t)(HALF + l * (l + 1) + M0 - 1) * a.ldp + i] = accM[q];
+        if constexpr (MIRROR) {
+            out[(size_t)(l * (l + 1) - M0 - 1) * a.ldp + i] = accPm[q];
+            out[(size_t)(HALF + l * (l + 1) - M0 - 1) * a.ldp + i] = accMm[q];
+        }
+    }
+}
+
+template <typename T, int L, int HMODE, int M0>
+static void launch_pass(const WxArgs<T>& a, int nchunk, hipStream_t s) {
+    dim3 grid((a.n + WX_BLOCK - 1) / WX_BLOCK, nchunk);
+    hipLaunchKernelGGL((wx_pass_kernel<T, L, M0, HMODE>), grid, dim3(WX_BLOCK), 0, s, a);
+    if constexpr (M0 > 0) launch_pass<T, L, HMODE, M0 - 1>(a, nchunk, s);
+}
+
+template <typename T, int L>
+void wx_run_L(const WxArgs<T>& a, int hmode, int nchunk, hipStream_t s) {
+    if (hmode == 0)
+        launch_pass<T, L, 0, L>(a, nchunk, s);
+    else
+        launch_pass<T, L, 1, L>(a, nchunk, s);
+}
+
+template void wx_run_L<double, CELES_WX_L>(const WxArgs<double>&, int, int, hipStream_t);
+template void wx_run_L<float, CELES_WX_L>(const WxArgs<float>&, int, int, hipStream_t);
+
+}  // namespace celes

@@ -1,0 +1,44 @@
+// Argument block and launcher of the on-the-fly coupling mat-vec.
+#pragma once
+#include <hip/hip_runtime.h>
+#include "device_common.hpp"
+
+namespace celes {
+
+template <typename T>
+struct LutView {
+    const cx<T>* coef;   // [n_int][2L+1][4] Horner coefficients in t
+    double d_lo;
+    double inv_dr;
+    int n_int;
+};
+
+template <typename T>
+struct WxArgs {
+    const double* px;    // sphere centres, SoA, FP64
+    const double* py;
+    const double* pz;
+    const cx<T>* xsd;    // [N][2][HALF] source sums/differences (scratch, written by prep)
+    const T* coef;       // a5 / b5im table in kernel enumeration order
+    cx<T>* part;         // [nchunk][2 HALF][ldp] partial sums
+    LutView<T> lut;
+    double k;            // background wavenumber
+    int n;               // number of spheres
+    int chunk_len;       // sources per chunk
+    int ldp;             // leading dimension of part (>= n)
+};
+
+// per-L pass launcher (defined in wx_kernels.hip, one translation unit per L)
+template <typename T, int L>
+void wx_run_L(const WxArgs<T>& a, int hmode, int nchunk, hipStream_t s);
+
+constexpr int WX_BLOCK_SIZE = 256;  // receivers per block
+constexpr int WX_TILE_SIZE = 16;    // sources per LDS tile
+
+// y = W x (epilogue = 0) or y = x - T (W x) (epilogue = 1); x, y: [N][nmax];
+// tq: [N][2][L] Mie coefficients.  Returns 0 on success.
+template <typename T>
+int wx_launch(const WxArgs<T>& a, int L, int hmode, int nchunk, const cx<T>* x, const cx<T>* tq,
+              cx<T>* y, int epilogue, hipStream_t s);
+
+}  // namespace celes

@@ -1,0 +1,85 @@
+"""C-ABI library: loads, exports every declared symbol, and its host-side
+logic (coefficient tables, Mie coefficients, argument validation) agrees with
+the oracle.  No GPU work is launched here."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1706_02145_amd as P
+from paper_1706_02145_amd._capi import SIGNATURES, lib
+from oracle.mie import mie_Q
+from oracle.translation import a5, b5
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    src = open(os.path.join(ROOT, "include", "celes.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(celes_[A-Za-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = _declared_symbols()
+    assert len(names) >= 20
+    l = lib()
+    for n in names:
+        assert hasattr(l, n), n
+        assert n in SIGNATURES, f"{n} has no ctypes signature"
+
+
+def test_version():
+    assert P.version() == 100
+
+
+@pytest.mark.parametrize("L", [1, 3, 4, 6])
+def test_translation_tables_match_oracle(L):
+    a, b = P.translation_tables(L)
+    err = 0.0
+    for l in range(1, L + 1):
+        for m in range(-l, l + 1):
+            for lp in range(1, L + 1):
+                for mp in range(-lp, lp + 1):
+                    for p in range(0, 2 * L + 1):
+                        ra = a5(l, m, lp, mp, p)
+                        rb = b5(l, m, lp, mp, p) if p >= 1 else 0.0
+                        err = max(err, abs(a[l - 1, m + L, lp - 1, mp + L, p] - ra),
+                                  abs(1j * b[l - 1, m + L, lp - 1, mp + L, p] - rb))
+    assert err < 1e-14
+
+
+@pytest.mark.parametrize("x,m", [(0.5, 1.5), (1.142, 1.5 + 0.01j), (1.714, 1.52), (6.0, 1.33 + 0.2j)])
+def test_mie_matches_oracle(x, m):
+    Q = P.mie_coefficients(8, x, m)
+    R = mie_Q(8, 1.0, x, m)
+    assert np.allclose(Q, R, rtol=1e-12, atol=1e-16)
+
+
+def test_create_rejects_bad_input_before_device_use():
+    pos = np.array([[0.0, 0, 0], [150.0, 0, 0]])
+    with pytest.raises(P.CelesError) as e:
+        P.Problem(pos, [100.0, 100.0], 1.5, 1.0, 550.0, 3)
+    assert e.value.name == "CELES_E_OVERLAP"
+    with pytest.raises(P.CelesError) as e:
+        P.Problem(np.array([[0.0, 0, np.nan]]), [100.0], 1.5, 1.0, 550.0, 3)
+    assert e.value.name == "CELES_E_NONFINITE"
+    with pytest.raises(P.CelesError) as e:
+        P.Problem(np.zeros((1, 3)), [100.0], 1.5, 1.0, 550.0, 0)
+    assert e.value.name == "CELES_E_ARG"
+    with pytest.raises(P.CelesError) as e:
+        P.Problem(np.zeros((1, 3)), [100.0], 1.5, 1.0, 550.0, 9)
+    assert e.value.name == "CELES_E_UNSUPPORTED"
+    with pytest.raises(P.CelesError) as e:
+        P.Problem(np.zeros((1, 3)), [-1.0], 1.5, 1.0, 550.0, 3)
+    assert e.value.name == "CELES_E_NONFINITE"
+
+
+def test_default_options():
+    o = P.default_options()
+    assert o.precision == P.CELES_FP64 and o.hankel == P.CELES_HANKEL_LUT
+    assert o.lut_dr == 1.0 and o.restart == 100
+    with pytest.raises(KeyError):
+        P.default_options(nonsense=1)

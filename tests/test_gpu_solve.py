@@ -1,0 +1,111 @@
+"""GPU solves against the oracle's dense LU solution, incident-field parity,
+and the optical theorem on the GPU solution."""
+import numpy as np
+import pytest
+
+import paper_1706_02145_amd as P
+from celes_inputs import workload
+from oracle.observables import absorption, extinction, scattering_cross_section
+from oracle.solve import master_matrix, solve_dense
+from tests.gpu_helpers import k_of, make_problem, oracle_incident, oracle_lut, rel
+
+pytestmark = pytest.mark.gpu
+
+
+def _dense(w, hankel):
+    hk = oracle_lut(w) if hankel == 0 else None
+    M, W, t = master_matrix(w.positions, w.radii, w.n_sphere, w.n0, w.wavelength, w.lmax, hk)
+    a = oracle_incident(w)
+    b = solve_dense(M, t * a.reshape(-1)).reshape(w.N, -1)
+    return M, t, a, b
+
+
+@pytest.mark.parametrize("name", ["cube8_l3", "slab64_l3", "slab200_l4"])
+def test_incident_coefficients(name):
+    w = workload(name)
+    p = make_problem(w)
+    a = p.incident()[0]
+    assert rel(a, oracle_incident(w)) <= 1e-11
+
+
+@pytest.mark.parametrize("hankel", [1, 0])
+def test_solve_cube8_matches_dense_lu(hankel):
+    w = workload("cube8_l3")
+    print(f"[solve] cube8_l3 hankel={hankel}", flush=True)
+    M, t, a, bref = _dense(w, hankel)
+    p = make_problem(w, hankel=hankel, tol=1e-10)
+    b, info = p.solve()
+    assert info["status"] == 0 and info["rel_residual"] <= 1e-10
+    assert rel(b[0], bref) <= 1e-9
+
+
+def test_preconditioned_solve_slab64():
+    w = workload("slab64_l3")
+    print("[solve] slab64_l3 preconditioned", flush=True)
+    M, t, a, bref = _dense(w, 0)
+    p = make_problem(w, tol=1e-11, restart=50)
+    b0, i0 = p.solve()
+    p.build_preconditioner(700.0)
+    b1, i1 = p.solve()
+    assert i1["status"] == 0 and i0["status"] == 0
+    assert rel(b0[0], bref) <= 1e-9 and rel(b1[0], bref) <= 1e-9
+    assert i1["iterations"] < i0["iterations"]
+
+
+def test_mixed_precision_matches_fp64():
+    w = workload("slab300_l3")
+    print("[solve] slab300_l3 mixed vs fp64", flush=True)
+    pf = make_problem(w, tol=1e-10)
+    bf, inf_f = pf.solve()
+    pm = make_problem(w, tol=1e-10, precision=P.CELES_MIXED, inner_tol=1e-4)
+    bm, inf_m = pm.solve()
+    assert inf_m["status"] == 0 and inf_m["rel_residual"] <= 1e-10
+    assert rel(bm, bf) <= 1e-6
+
+
+def test_optical_theorem_on_gpu_solution():
+    w = workload("cube8_l3")
+    k = k_of(w)
+    p = make_problem(w, tol=1e-12, hankel=1)
+    b, info = p.solve()
+    ce, cs, ca = p.cross_sections()
+    assert abs(ce[0] - cs[0] - ca[0]) <= 1e-9 * ce[0]
+    # the library's observables agree with the oracle's on the same b
+    t = np.concatenate([np.zeros(0)])
+    M, tv, a, bref = _dense(w, 1)
+    assert abs(ce[0] - extinction(k, a, b[0])) <= 1e-12 * ce[0]
+    assert abs(ca[0] - absorption(k, b[0].reshape(-1), tv)) <= 1e-10 * ca[0]
+    assert abs(cs[0] - scattering_cross_section(k, w.positions, b[0], w.lmax)) <= 1e-10 * cs[0]
+
+
+def test_far_and_near_field_match_oracle():
+    from oracle.observables import far_field, scattered_field
+    w = workload("cube8_l3")
+    k = k_of(w)
+    p = make_problem(w, tol=1e-12, hankel=1)
+    b, _ = p.solve()
+    th = np.array([0.0, 0.3, 1.2, 2.5, np.pi])
+    ph = np.array([0.0, 1.0, -2.0, 0.4, 0.0])
+    F = p.far_field(th, ph)[0]
+    # library's far field uses the raw centres (no recentring): compare directly
+    Fr = far_field(k, w.positions, b[0], w.lmax, th, ph)
+    assert rel(F, Fr) <= 1e-12
+    pts = np.array([[1500.0, 0, 0], [0, -1400.0, 300.0], [200.0, 200.0, 1600.0]])
+    E = p.near_field(pts, add_incident=False)[0]
+    Er = scattered_field(k, w.positions, b[0], w.lmax, pts)
+    assert rel(E, Er) <= 1e-11
+
+
+def test_noconv_status_and_x0():
+    w = workload("slab64_l3")
+    p = make_problem(w, tol=1e-12, maxiter=3)
+    with pytest.raises(P.CelesError) as e:
+        p.solve()
+    assert e.value.name == "CELES_E_NOCONV"
+    b, info = p.solve(check=False)
+    assert info["status"] == -5
+    # restart from the solution: converges immediately
+    p2 = make_problem(w, tol=1e-8)
+    bs, _ = p2.solve()
+    b2, info2 = p2.solve(x0=bs)
+    assert info2["iterations"] == 0 and info2["rel_residual"] <= 1e-8
