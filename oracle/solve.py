@@ -104,9 +104,11 @@ def gmres(matvec, rhs, tol=1e-10, restart=100, maxiter=10000, precond=None, x0=N
                 H[i, kk] = np.vdot(V[i], w)
                 w = w - H[i, kk] * V[i]
             H[kk + 1, kk] = np.linalg.norm(w)
+            # complex Givens rotation [[conj(c), conj(s)], [-s, c]] with
+            # c = a/r, s = b/r, r = sqrt(|a|^2 + |b|^2), annihilating H[k+1, k]
             for i in range(kk):
-                t = cs[i] * H[i, kk] + sn[i] * H[i + 1, kk]
-                H[i + 1, kk] = -np.conj(sn[i]) * H[i, kk] + np.conj(cs[i]) * H[i + 1, kk]
+                t = np.conj(cs[i]) * H[i, kk] + np.conj(sn[i]) * H[i + 1, kk]
+                H[i + 1, kk] = -sn[i] * H[i, kk] + cs[i] * H[i + 1, kk]
                 H[i, kk] = t
             a, b = H[kk, kk], H[kk + 1, kk]
             den = np.sqrt(abs(a) ** 2 + abs(b) ** 2)
@@ -114,7 +116,7 @@ def gmres(matvec, rhs, tol=1e-10, restart=100, maxiter=10000, precond=None, x0=N
             sn[kk] = b / den if den != 0 else 0.0
             H[kk, kk] = den
             H[kk + 1, kk] = 0.0
-            g[kk + 1] = -np.conj(sn[kk]) * g[kk]
+            g[kk + 1] = -sn[kk] * g[kk]
             g[kk] = np.conj(cs[kk]) * g[kk]
             its += 1
             if H[kk + 1, kk] == 0 and den == 0:

@@ -93,3 +93,18 @@ def test_partition_blocks_are_cells():
         c = cells[perm[off[j]:off[j + 1]]]
         assert (c == c[0]).all()
         assert list(perm[off[j]:off[j + 1]]) == sorted(perm[off[j]:off[j + 1]])
+
+
+def test_gmres_exact_in_n_steps_and_monotone_restarts():
+    # GMRES minimises the residual over x0 + Krylov space: without restart it
+    # is exact after n steps (up to rounding), and across restarts the true
+    # residual can never increase (the previous iterate is in the search space).
+    rng = np.random.default_rng(11)
+    n = 40
+    A = np.eye(n) + 0.4 * (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))) / np.sqrt(n)
+    b = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    x, its, _ = gmres(lambda v: A @ v, b, tol=1e-13, restart=n + 5)
+    assert its <= n and np.linalg.norm(A @ x - b) <= 1e-12 * np.linalg.norm(b)
+    x, its, hist = gmres(lambda v: A @ v, b, tol=1e-12, restart=5, maxiter=2000)
+    assert all(h2 <= h1 * (1 + 1e-12) for h1, h2 in zip(hist, hist[1:]))
+    assert hist[-1] <= 1e-12
