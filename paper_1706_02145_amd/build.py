@@ -30,7 +30,9 @@ def _run(cmd):
     return err
 
 
-def build(lmax_compiled=6, jobs=None, verbose=False):
+def build(lmax_compiled=6, jobs=None, verbose=False, force=False):
+    """Compile (objects newer than their sources and headers are reused unless
+    force=True) and link libceles_amd.so."""
     os.makedirs(BUILD, exist_ok=True)
     units = []
     for L in range(1, lmax_compiled + 1):
@@ -41,8 +43,14 @@ def build(lmax_compiled=6, jobs=None, verbose=False):
     units.sort(key=lambda u: -int(u[2][0].split("=")[1]) if u[2] else 0)
     jobs = jobs or min(8, os.cpu_count() or 1)
 
+    headers = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hpp", ".h"))]
+    headers.append(os.path.join(HERE, "..", "include", "celes.h"))
+    newest_dep = max(os.path.getmtime(f) for f in headers + [__file__])
+
     def compile_one(u):
         src, obj, extra = u
+        if not force and os.path.exists(obj) and os.path.getmtime(obj) >= max(os.path.getmtime(src), newest_dep):
+            return ""
         lang = ["-x", "hip"] if src.endswith(".cpp") else []
         return _run([HIPCC] + COMMON + extra + lang + ["-c", src, "-o", obj])
 
@@ -74,5 +82,6 @@ if __name__ == "__main__":
     ap.add_argument("--lmax-compiled", type=int, default=int(os.environ.get("CELES_LMAX_COMPILED", "6")))
     ap.add_argument("-j", type=int, default=None)
     ap.add_argument("-v", action="store_true")
+    ap.add_argument("--force", action="store_true")
     a = ap.parse_args()
-    print(build(a.lmax_compiled, a.j, a.v))
+    print(build(a.lmax_compiled, a.j, a.v, a.force))

@@ -341,11 +341,11 @@ int gmres_device(celes_handle* h, const cx<T>* rhs, cx<T>* x, double tol, int ma
                 out->breakdown = true;
                 break;
             }
-            // apply previous Givens rotations
+            // previous Givens rotations G_i = [[conj(c), conj(s)], [-s, c]]
             for (int i = 0; i < kk; ++i) {
                 cplx a = H[(size_t)i * m + kk], bb = H[(size_t)(i + 1) * m + kk];
-                H[(size_t)i * m + kk] = cs[i] * a + sn[i] * bb;
-                H[(size_t)(i + 1) * m + kk] = -std::conj(sn[i]) * a + std::conj(cs[i]) * bb;
+                H[(size_t)i * m + kk] = std::conj(cs[i]) * a + std::conj(sn[i]) * bb;
+                H[(size_t)(i + 1) * m + kk] = -sn[i] * a + cs[i] * bb;
             }
             cplx a = H[(size_t)kk * m + kk], bb = H[(size_t)(kk + 1) * m + kk];
             double den = std::sqrt(std::norm(a) + std::norm(bb));
@@ -353,7 +353,7 @@ int gmres_device(celes_handle* h, const cx<T>* rhs, cx<T>* x, double tol, int ma
             sn[kk] = den > 0 ? bb / den : cplx(0, 0);
             H[(size_t)kk * m + kk] = den;
             H[(size_t)(kk + 1) * m + kk] = 0;
-            g[kk + 1] = -std::conj(sn[kk]) * g[kk];
+            g[kk + 1] = -sn[kk] * g[kk];
             g[kk] = std::conj(cs[kk]) * g[kk];
             out->iterations++;
             used = kk + 1;
