@@ -43,13 +43,23 @@ def build(lmax_compiled=6, jobs=None, verbose=False, force=False):
     units.sort(key=lambda u: -int(u[2][0].split("=")[1]) if u[2] else 0)
     jobs = jobs or min(8, os.cpu_count() or 1)
 
-    headers = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hpp", ".h"))]
-    headers.append(os.path.join(HERE, "..", "include", "celes.h"))
-    newest_dep = max(os.path.getmtime(f) for f in headers + [__file__])
+    def deps(path, seen=None):
+        # local #include "..." files, recursively
+        seen = set() if seen is None else seen
+        if path in seen or not os.path.exists(path):
+            return seen
+        seen.add(path)
+        for line in open(path, encoding="utf-8", errors="replace"):
+            line = line.strip()
+            if line.startswith("#include \""):
+                inc = os.path.normpath(os.path.join(os.path.dirname(path), line.split('"')[1]))
+                deps(inc, seen)
+        return seen
 
     def compile_one(u):
         src, obj, extra = u
-        if not force and os.path.exists(obj) and os.path.getmtime(obj) >= max(os.path.getmtime(src), newest_dep):
+        newest = max(os.path.getmtime(f) for f in deps(src) | {__file__})
+        if not force and os.path.exists(obj) and os.path.getmtime(obj) >= newest:
             return ""
         lang = ["-x", "hip"] if src.endswith(".cpp") else []
         return _run([HIPCC] + COMMON + extra + lang + ["-c", src, "-o", obj])

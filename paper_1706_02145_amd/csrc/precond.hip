@@ -158,28 +158,79 @@ __global__ void assemble_kernel(AsmArgs g, int64_t ntot) {
         }
 }
 
-// out[perm rows of block j] = Minv_j * in[perm rows of block j]; one thread per row
+// Apply: out[perm rows of block j] = Minv_j in[perm rows of block j].  The
+// work is split over 256-row x 256-column tiles of every block (HBM-bound:
+// each matrix element is read once); the x tile is gathered into LDS, each
+// thread owns one row and streams its 256 column entries (column-major, so a
+// wave reads 64 consecutive rows = contiguous memory).  Partial sums per
+// column tile go to part[s][permuted row] and a second kernel adds them in a
+// fixed order and scatters back to the caller's sphere order.
+constexpr int PA_ROWS = 256, PA_COLS = 256;
+
 template <typename T>
-__global__ void __launch_bounds__(256) apply_kernel(const cx<double>* __restrict__ inv, const int64_t* __restrict__ perm,
-                                                    const int64_t* __restrict__ boff, const int64_t* __restrict__ moff,
-                                                    int nmax, const cx<T>* __restrict__ in, cx<T>* __restrict__ out) {
-    const int j = blockIdx.y;
-    const int64_t o = boff[j], nj = boff[j + 1] - o, dim = nj * nmax;
-    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if ((int64_t)blockIdx.x * 256 >= dim) return;
-    const cx<double>* M = inv + moff[j];
-    double re = 0, im = 0;
-    if (r < dim) {
-        for (int64_t c = 0; c < dim; ++c) {
-            const int64_t src = perm[o + c / nmax] * nmax + c % nmax;
-            const cx<T> x = in[src];
-            const cx<double> a = M[r + c * dim];
-            re += a.re * (double)x.re - a.im * (double)x.im;
-            im += a.re * (double)x.im + a.im * (double)x.re;
-        }
-        const int64_t dst = perm[o + r / nmax] * nmax + r % nmax;
-        out[dst] = {(T)re, (T)im};
+__global__ void __launch_bounds__(PA_ROWS) apply_tiles(const cx<double>* __restrict__ inv,
+                                                       const int64_t* __restrict__ perm,
+                                                       const int64_t* __restrict__ boff,
+                                                       const int64_t* __restrict__ moff, int nmax,
+                                                       const cx<T>* __restrict__ in, cx<double>* __restrict__ part,
+                                                       int64_t n) {
+    const int j = blockIdx.z, s = blockIdx.y;
+    const int64_t o = boff[j], dim = (boff[j + 1] - o) * nmax;
+    const int64_t r0 = (int64_t)blockIdx.x * PA_ROWS;
+    if (r0 >= dim) return;
+    const int64_t r = r0 + threadIdx.x;
+    const int64_t c0 = (int64_t)s * PA_COLS;
+    cx<double>* dst = part + (int64_t)s * n + o * nmax;
+    if (c0 >= dim) {
+        if (r < dim) dst[r] = {0.0, 0.0};
+        return;
     }
+    const int ncol = (int)(dim - c0 < PA_COLS ? dim - c0 : PA_COLS);
+    __shared__ cx<double> xs[PA_COLS];
+    if (threadIdx.x < ncol) {
+        const int64_t c = c0 + threadIdx.x;
+        const cx<T> v = in[perm[o + c / nmax] * nmax + c % nmax];
+        xs[threadIdx.x] = {(double)v.re, (double)v.im};
+    }
+    __syncthreads();
+    if (r >= dim) return;
+    const cx<double>* M = inv + moff[j] + c0 * dim + r;
+    double re0 = 0, im0 = 0, re1 = 0, im1 = 0, re2 = 0, im2 = 0, re3 = 0, im3 = 0;
+    int c = 0;
+    for (; c + 4 <= ncol; c += 4) {
+        const cx<double> a0 = M[(int64_t)(c + 0) * dim], a1 = M[(int64_t)(c + 1) * dim];
+        const cx<double> a2 = M[(int64_t)(c + 2) * dim], a3 = M[(int64_t)(c + 3) * dim];
+        const cx<double> x0 = xs[c], x1 = xs[c + 1], x2 = xs[c + 2], x3 = xs[c + 3];
+        re0 = fma(a0.re, x0.re, fma(-a0.im, x0.im, re0));
+        im0 = fma(a0.re, x0.im, fma(a0.im, x0.re, im0));
+        re1 = fma(a1.re, x1.re, fma(-a1.im, x1.im, re1));
+        im1 = fma(a1.re, x1.im, fma(a1.im, x1.re, im1));
+        re2 = fma(a2.re, x2.re, fma(-a2.im, x2.im, re2));
+        im2 = fma(a2.re, x2.im, fma(a2.im, x2.re, im2));
+        re3 = fma(a3.re, x3.re, fma(-a3.im, x3.im, re3));
+        im3 = fma(a3.re, x3.im, fma(a3.im, x3.re, im3));
+    }
+    for (; c < ncol; ++c) {
+        const cx<double> a0 = M[(int64_t)c * dim], x0 = xs[c];
+        re0 = fma(a0.re, x0.re, fma(-a0.im, x0.im, re0));
+        im0 = fma(a0.re, x0.im, fma(a0.im, x0.re, im0));
+    }
+    dst[r] = {(re0 + re1) + (re2 + re3), (im0 + im1) + (im2 + im3)};
+}
+
+// out[perm[t / nmax] nmax + t % nmax] = sum_s part[s][t], t in permuted order
+template <typename T>
+__global__ void apply_reduce(const cx<double>* __restrict__ part, int nsplit, const int64_t* __restrict__ perm,
+                             int nmax, int64_t n, cx<T>* __restrict__ out) {
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= n) return;
+    double re = 0, im = 0;
+    for (int s = 0; s < nsplit; ++s) {
+        const cx<double> v = part[(int64_t)s * n + t];
+        re += v.re;
+        im += v.im;
+    }
+    out[perm[t / nmax] * nmax + t % nmax] = {(T)re, (T)im};
 }
 
 BlockPrecond::~BlockPrecond() {
@@ -187,6 +238,7 @@ BlockPrecond::~BlockPrecond() {
     if (d_boff_) hipFree(d_boff_);
     if (d_moff_) hipFree(d_moff_);
     if (d_inv_) hipFree(d_inv_);
+    if (d_part_) hipFree(d_part_);
 }
 
 int BlockPrecond::build(int64_t N, int L, const double* pos, double k, const cplx* tq, double edge, int hmode,
@@ -207,7 +259,8 @@ int BlockPrecond::build(int64_t N, int L, const double* pos, double k, const cpl
     }
     auto dev = [&](void** p, size_t bytes) { return hipMalloc(p, bytes) == hipSuccess; };
     if (!dev((void**)&d_perm_, N * 8) || !dev((void**)&d_boff_, (nb + 1) * 8) || !dev((void**)&d_moff_, nb * 8) ||
-        !dev((void**)&d_inv_, mat_elems_ * sizeof(cx<double>))) {
+        !dev((void**)&d_inv_, mat_elems_ * sizeof(cx<double>)) ||
+        !dev((void**)&d_part_, (size_t)((max_dim_ + PA_COLS - 1) / PA_COLS) * N * nmax_ * sizeof(cx<double>))) {
         *msg = "cannot allocate the preconditioner (" + std::to_string(mat_elems_ * 16 / (1 << 20)) + " MiB)";
         return CELES_E_OOM_INTERNAL;
     }
@@ -302,8 +355,13 @@ int BlockPrecond::build(int64_t N, int L, const double* pos, double k, const cpl
 template <typename T>
 int BlockPrecond::apply(const cx<T>* in, cx<T>* out, hipStream_t s) const {
     const int nb = (int)offsets_.size() - 1;
-    dim3 grid((unsigned)((max_dim_ + 255) / 256), (unsigned)nb);
-    hipLaunchKernelGGL(apply_kernel<T>, grid, dim3(256), 0, s, d_inv_, d_perm_, d_boff_, d_moff_, nmax_, in, out);
+    const int nsplit = (max_dim_ + PA_COLS - 1) / PA_COLS;
+    const int64_t n = N_ * nmax_;
+    dim3 grid((unsigned)((max_dim_ + PA_ROWS - 1) / PA_ROWS), (unsigned)nsplit, (unsigned)nb);
+    hipLaunchKernelGGL(apply_tiles<T>, grid, dim3(PA_ROWS), 0, s, d_inv_, d_perm_, d_boff_, d_moff_, nmax_, in,
+                       d_part_, n);
+    hipLaunchKernelGGL(apply_reduce<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, d_part_, nsplit,
+                       d_perm_, nmax_, n, out);
     return hipGetLastError() == hipSuccess ? 0 : CELES_E_DEVICE_INTERNAL;
 }
 

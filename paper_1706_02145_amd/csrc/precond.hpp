@@ -43,6 +43,7 @@ class BlockPrecond {
     int64_t* d_boff_ = nullptr;      // [nb+1] sphere offsets
     int64_t* d_moff_ = nullptr;      // [nb] matrix element offsets
     cx<double>* d_inv_ = nullptr;    // block inverses, column-major, concatenated
+    cx<double>* d_part_ = nullptr;   // [column tiles][N nmax] partial sums of the apply
 };
 
 // partition of Section 3.2.1 step 1: cubes of edge `edge` anchored at the
