@@ -75,6 +75,32 @@ def flops_per_pair(L, hankel_lut=True):
     return total
 
 
+def kernel_source_digest():
+    """sha256 of the coupling-kernel sources (counters are only valid for them)."""
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_1706_02145_amd", "csrc")
+    for f in ("wx_kernels.hip", "wx_plan.hpp", "wx_launch.hpp", "device_common.hpp"):
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(N, L, hankel):
+    """HBM bytes per mat-vec launch from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary, or None if it was taken on other kernel sources or
+    another workload."""
+    f = os.path.join(ROOT, "profiles", "wx_fused_slab2000_l4_hbm_traffic.json")
+    if not os.path.exists(f):
+        return None
+    with open(f) as fh:
+        t = json.load(fh)
+    if t.get("kernel_source_sha256") != kernel_source_digest() or t.get("N") != N or t.get("lmax") != L \
+            or t.get("hankel") != hankel:
+        return None
+    return t["bytes_per_launch"]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -151,6 +177,22 @@ def main():
     mv_flops = fpp * N * (N - 1)
     achieved = mv_flops / (mv_ms * 1e-3) / 1e12
 
+    # ablation: the other Hankel evaluation mode on the same geometry
+    other = "direct" if a.hankel == "lut" else "lut"
+    q = P.Problem(w.positions, w.radii, w.n_sphere, w.n0, w.wavelength, L, lut_dr=w.lut_dr,
+                  hankel=P.CELES_HANKEL_DIRECT if other == "direct" else P.CELES_HANKEL_LUT)
+    for _ in range(3):
+        q.apply_W(x, y, P.CELES_FP64, stream=stream)
+    ev0.record(stream)
+    for _ in range(reps):
+        q.apply_W(x, y, P.CELES_FP64, stream=stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    other_ms = ev0.elapsed_time(ev1) / reps
+    other_fpp = flops_per_pair(L, other == "lut")
+    q.close()
+    traffic = measured_traffic(N, L, a.hankel)
+
     # ---- timed solves ----
     for _ in range(a.warmup):
         p.solve()
@@ -216,9 +258,14 @@ def main():
                                f"block-diagonal preconditioned GMRES to 1e-8 (complex128)",
                    "N": N, "lmax": L, "hankel": a.hankel, "cuboid_edge_nm": a.cuboid_edge},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VALU_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_VALU_TFLOPS, "traffic": None},
+                     "frac": achieved / PEAK_FP64_VALU_TFLOPS, "traffic": traffic},
         "cpu_baseline": cpu,
+        "kernel": "wx_fused_kernel<double, 4, %d> (one launch = one W.b over all N(N-1) pairs)" % (0 if a.hankel == "lut" else 1),
         "matvec_ms": mv_ms,
+        "matvec_other_hankel": {"hankel": other, "matvec_ms": other_ms,
+                                "updates_per_s": updates_per_mv / (other_ms * 1e-3),
+                                "tflops": other_fpp * N * (N - 1) / (other_ms * 1e-3) / 1e12,
+                                "frac": other_fpp * N * (N - 1) / (other_ms * 1e-3) / 1e12 / PEAK_FP64_VALU_TFLOPS},
         "matvec_updates_per_s": updates_per_mv / (mv_ms * 1e-3),
         "flops_per_pair": fpp,
         "solve": {"iterations": infos[-1]["iterations"], "matvecs_per_solve": infos[-1]["matvecs"],

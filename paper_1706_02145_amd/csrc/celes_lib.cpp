@@ -211,10 +211,10 @@ int build_lut(celes_handle* h) {
 // ---------------------------------------------------------------------------
 // mat-vec driver
 // ---------------------------------------------------------------------------
-int pick_chunks(int64_t N) {
+int pick_chunks(int64_t N, int L) {
     const char* env = std::getenv("CELES_WX_TARGET_BLOCKS");
     int target = env ? std::max(1, std::atoi(env)) : 1024;
-    int64_t nbx = (N + celes::WX_BLOCK_SIZE - 1) / celes::WX_BLOCK_SIZE;
+    int64_t nbx = (N + celes::WX_BLOCK_SIZE - 1) / celes::WX_BLOCK_SIZE * celes::wx_num_groups(L);
     int64_t nchunk = (target + nbx - 1) / nbx;
     int64_t maxc = (N + celes::WX_TILE_SIZE - 1) / celes::WX_TILE_SIZE;
     nchunk = std::max<int64_t>(1, std::min(nchunk, maxc));
@@ -224,7 +224,7 @@ int pick_chunks(int64_t N) {
 template <typename T>
 int matvec(celes_handle* h, const cx<T>* x, cx<T>* y, int epilogue, hipStream_t s) {
     const int64_t N = h->N;
-    const int nchunk = pick_chunks(N);
+    const int nchunk = pick_chunks(N, h->L);
     int64_t chunk_len = (N + nchunk - 1) / nchunk;
     chunk_len = (chunk_len + celes::WX_TILE_SIZE - 1) / celes::WX_TILE_SIZE * celes::WX_TILE_SIZE;
     const int nchunk_eff = (int)((N + chunk_len - 1) / chunk_len);

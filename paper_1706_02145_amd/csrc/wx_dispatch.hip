@@ -54,6 +54,18 @@ __global__ void wx_finish_kernel(const cx<T>* __restrict__ part, int nchunk, int
     y[b2] = y2;
 }
 
+int wx_num_groups(int L) {
+    switch (L) {
+        case 1: return wx_num_groups_L<1>();
+        case 2: return wx_num_groups_L<2>();
+        case 3: return wx_num_groups_L<3>();
+        case 4: return wx_num_groups_L<4>();
+        case 5: return wx_num_groups_L<5>();
+        case 6: return wx_num_groups_L<6>();
+        default: return 1;
+    }
+}
+
 template <typename T>
 int wx_launch(const WxArgs<T>& a, int L, int hmode, int nchunk, const cx<T>* x, const cx<T>* tq,
               cx<T>* y, int epilogue, hipStream_t s) {

@@ -98,185 +98,230 @@ __device__ __forceinline__ void hankel_lut(double d, const LutView<T>& lut, cx<T
 }
 
 // ---------------------------------------------------------------------------
-// one pass of the coupling mat-vec
+// accumulation of one receiving |m| = M0 for one (mu, Legendre column) step
 // ---------------------------------------------------------------------------
-template <typename T, int L, int M0, int HMODE>
-__global__ __launch_bounds__(WX_BLOCK) void wx_pass_kernel(WxArgs<T> a) {
+template <typename T, int L, int M0, int mu>
+__device__ __forceinline__ void pass_mu_step(const cx<T>* xs, const cx<T> (&H)[2 * L + 1], cx<T> emu,
+                                             cx<T> (&accP)[L], cx<T> (&accM)[L], cx<T> (&accPm)[L],
+                                             cx<T> (&accMm)[L]) {
     constexpr int HALF = L * (L + 2);
-    constexpr int P2 = 2 * L;
     constexpr int LLO = l_lo(M0);
-    constexpr int NL = L - LLO + 1;
-    constexpr int MUMAX = mu_max(L, M0);
     constexpr bool MIRROR = M0 > 0;
-
-    const int i = blockIdx.x * WX_BLOCK + threadIdx.x;
-    // source tile staged in LDS; every lane reads the same element (broadcast)
-    __shared__ cx<T> tile[WX_TILE * 2 * HALF];
-    const int chunk = blockIdx.y;
-    const bool active = i < a.n;
-    const double xi = active ? a.px[i] : 0.0;
-    const double yi = active ? a.py[i] : 0.0;
-    const double zi = active ? a.pz[i] : 0.0;
-
-    cx<T> accP[NL], accM[NL], accPm[NL], accMm[NL];
-#pragma unroll
-    for (int q = 0; q < NL; ++q) {
-        accP[q] = {0, 0};
-        accM[q] = {0, 0};
-        accPm[q] = {0, 0};
-        accMm[q] = {0, 0};
-    }
-
-    const int j0 = chunk * a.chunk_len;
-    const int j1 = min(a.n, j0 + a.chunk_len);
-    for (int t0 = j0; t0 < j1; t0 += WX_TILE) {
-      const int nt = min(WX_TILE, j1 - t0);
-      __syncthreads();
-      {
-        const cx<T>* src = a.xsd + (size_t)t0 * (2 * HALF);
-        for (int e = threadIdx.x; e < nt * 2 * HALF; e += WX_BLOCK) tile[e] = src[e];
-      }
-      __syncthreads();
-      for (int jj = 0; jj < nt; ++jj) {
-        const int j = t0 + jj;
-        if (!active || j == i) continue;
-        // ---- pair geometry (FP64) ----
-        const double dx = xi - a.px[j], dy = yi - a.py[j], dz = zi - a.pz[j];
-        const double rho2 = dx * dx + dy * dy;
-        const double r = sqrt(rho2 + dz * dz);
-        const double inv_r = 1.0 / r;
-        const double rho = sqrt(rho2);
-        const T ct = (T)(dz * inv_r), st = (T)(rho * inv_r);
-        T cph = 1, sph = 0;
-        if (rho > 0.0) {
-            const double ir = 1.0 / rho;
-            cph = (T)(dx * ir);
-            sph = (T)(dy * ir);
-        }
-        // ---- radial functions ----
-        cx<T> h[P2 + 1];
-        if constexpr (HMODE == 0)
-            hankel_lut<T, P2>(r, a.lut, h);
-        else
-            hankel_direct<T, P2>(a.k * r, h);
-
-            const cx<T>* xs = tile + jj * (2 * HALF);
-        const cx<T> e1 = {cph, sph};
-        cx<T> emu = {1, 0};
-        T pmm = (T)0.70710678118654752440;   // P_0^0
-        sfor<0, MUMAX + 1>([&](auto MU_) {
-            constexpr int mu = decltype(MU_)::value;
-            if constexpr (mu > 0) {
-                constexpr double cd = leg_diag(mu);
-                pmm = (T)cd * st * pmm;
-                emu = cmul(emu, e1);
-            }
-            // Legendre column P_p^mu, p = mu..2L, and H_p = h_p P_p^mu
-            T Pc[P2 + 1];
-            cx<T> H[P2 + 1];
-            sfor<mu, P2 + 1>([&](auto PP_) {
-                constexpr int p = decltype(PP_)::value;
-                if constexpr (p == mu) {
-                    Pc[p] = pmm;
-                } else if constexpr (p == mu + 1) {
-                    constexpr double cs = leg_sub(mu);
-                    Pc[p] = (T)cs * ct * pmm;
-                } else {
-                    constexpr double ca = leg_a(p, mu), cb = leg_b(p, mu);
-                    Pc[p] = (T)ca * ct * Pc[p - 1] - (T)cb * Pc[p - 2];
+    sfor<0, 2>([&](auto SG_) {
+        constexpr int sgn = decltype(SG_)::value == 0 ? 1 : -1;
+        if constexpr (branch(L, M0, mu, sgn)) {
+            constexpr int mp = M0 + sgn * mu;
+            constexpr bool two = MIRROR || mu > 0;
+            const cx<T> rot = sgn > 0 ? emu : cx<T>{emu.re, -emu.im};
+            const cx<T> rotc = {rot.re, -rot.im};
+            sfor<lp_lo(mp), L + 1>([&](auto LP_) {
+                constexpr int lp = decltype(LP_)::value;
+                // keep the group's LDS reads next to their use (bounded live range)
+                __builtin_amdgcn_sched_barrier(0);
+                // source coefficients of (l', m') and of the mirror (l', -m')
+                const cx<T> s1 = xs[lp * (lp + 1) + mp - 1];
+                const cx<T> d1 = xs[HALF + lp * (lp + 1) + mp - 1];
+                const cx<T> ts = cmul(rot, s1), td = cmul(rot, d1);
+                cx<T> us = {0, 0}, ud = {0, 0};
+                if constexpr (two) {
+                    const cx<T> s2 = xs[lp * (lp + 1) - mp - 1];
+                    const cx<T> d2 = xs[HALF + lp * (lp + 1) - mp - 1];
+                    us = cmul(rotc, s2);
+                    ud = cmul(rotc, d2);
                 }
-                H[p] = {h[p].re * Pc[p], h[p].im * Pc[p]};
-            });
-            sfor<0, 2>([&](auto SG_) {
-                constexpr int sgn = decltype(SG_)::value == 0 ? 1 : -1;
-                if constexpr (branch(L, M0, mu, sgn)) {
-                    constexpr int mp = M0 + sgn * mu;
-                    constexpr bool two = MIRROR || mu > 0;
-                    const cx<T> rot = sgn > 0 ? emu : cx<T>{emu.re, -emu.im};
-                    const cx<T> rotc = {rot.re, -rot.im};
-                    sfor<lp_lo(mp), L + 1>([&](auto LP_) {
-                        constexpr int lp = decltype(LP_)::value;
-                        // keep the group's LDS reads next to their use (bounded live range)
-                        __builtin_amdgcn_sched_barrier(0);
-                        // source coefficients of (l', m') and of the mirror (l', -m')
-                        const cx<T> s1 = xs[lp * (lp + 1) + mp - 1];
-                        const cx<T> d1 = xs[HALF + lp * (lp + 1) + mp - 1];
-                        const cx<T> ts = cmul(rot, s1), td = cmul(rot, d1);
-                        cx<T> us = {0, 0}, ud = {0, 0};
-                        if constexpr (two) {
-                            const cx<T> s2 = xs[lp * (lp + 1) - mp - 1];
-                            const cx<T> d2 = xs[HALF + lp * (lp + 1) - mp - 1];
-                            us = cmul(rotc, s2);
-                            ud = cmul(rotc, d2);
-                        }
-                        sfor<LLO, L + 1>([&](auto LL_) {
-                            constexpr int l = decltype(LL_)::value;
-                            constexpr int pa0 = pa_lo(l, lp, mu), nA = na(l, lp, mu);
-                            constexpr int pb0 = pb_lo(l, lp, mu), nB = nb(l, lp, mu);
-                            cx<T> A = {0, 0}, B = {0, 0};
-                            sfor<0, nA>([&](auto QA_) {
-                                constexpr int t = decltype(QA_)::value;
-                                constexpr double cv = ca5(lp, mp, l, M0, pa0 + 2 * t);
-                                const T c = (T)cv;
-                                A.re = fma(c, H[pa0 + 2 * t].re, A.re);
-                                A.im = fma(c, H[pa0 + 2 * t].im, A.im);
-                            });
-                            sfor<0, nB>([&](auto QB_) {
-                                constexpr int t = decltype(QB_)::value;
-                                constexpr double cv = cb5im(lp, mp, l, M0, pb0 + 2 * t);
-                                const T c = (T)cv;
-                                B.re = fma(c, H[pb0 + 2 * t].re, B.re);
-                                B.im = fma(c, H[pb0 + 2 * t].im, B.im);
-                            });
-                            // P = A + iB, Q = A - iB
-                            const cx<T> Pv = {A.re - B.im, A.im + B.re};
-                            const cx<T> Qv = {A.re + B.im, A.im - B.re};
-                            constexpr int q = l - LLO;
-                            cfma(accP[q], Pv, ts);
-                            cfma(accM[q], Qv, td);
-                            if constexpr (MIRROR) {
-                                cfma(accPm[q], Qv, us);
-                                cfma(accMm[q], Pv, ud);
-                            } else if constexpr (two) {
-                                cfma(accP[q], Qv, us);
-                                cfma(accM[q], Pv, ud);
-                            }
-                        });
+                sfor<LLO, L + 1>([&](auto LL_) {
+                    constexpr int l = decltype(LL_)::value;
+                    constexpr int pa0 = pa_lo(l, lp, mu), nA = na(l, lp, mu);
+                    constexpr int pb0 = pb_lo(l, lp, mu), nB = nb(l, lp, mu);
+                    cx<T> A = {0, 0}, B = {0, 0};
+                    sfor<0, nA>([&](auto QA_) {
+                        constexpr int t = decltype(QA_)::value;
+                        constexpr double cv = ca5(lp, mp, l, M0, pa0 + 2 * t);
+                        const T c = (T)cv;
+                        A.re = fma(c, H[pa0 + 2 * t].re, A.re);
+                        A.im = fma(c, H[pa0 + 2 * t].im, A.im);
                     });
-                }
+                    sfor<0, nB>([&](auto QB_) {
+                        constexpr int t = decltype(QB_)::value;
+                        constexpr double cv = cb5im(lp, mp, l, M0, pb0 + 2 * t);
+                        const T c = (T)cv;
+                        B.re = fma(c, H[pb0 + 2 * t].re, B.re);
+                        B.im = fma(c, H[pb0 + 2 * t].im, B.im);
+                    });
+                    // P = A + iB, Q = A - iB
+                    const cx<T> Pv = {A.re - B.im, A.im + B.re};
+                    const cx<T> Qv = {A.re + B.im, A.im - B.re};
+                    constexpr int q = l - LLO;
+                    cfma(accP[q], Pv, ts);
+                    cfma(accM[q], Qv, td);
+                    if constexpr (MIRROR) {
+                        cfma(accPm[q], Qv, us);
+                        cfma(accMm[q], Pv, ud);
+                    } else if constexpr (two) {
+                        cfma(accP[q], Qv, us);
+                        cfma(accM[q], Pv, ud);
+                    }
+                });
             });
-        });
-      }
-    }
-    if (!active) return;
-    // partial sums: part[chunk][kk][i], kk = plus-space (l,m) or HALF + minus-space (l,m)
+        }
+    });
+}
+
+template <typename T, int L, int M0>
+__device__ __forceinline__ void pass_store(const WxArgs<T>& a, int chunk, int i, const cx<T> (&accP)[L],
+                                           const cx<T> (&accM)[L], const cx<T> (&accPm)[L],
+                                           const cx<T> (&accMm)[L]) {
+    constexpr int HALF = L * (L + 2);
+    constexpr int LLO = l_lo(M0);
     cx<T>* out = a.part + (size_t)chunk * (2 * HALF) * a.ldp;
 #pragma unroll
     for (int l = LLO; l <= L; ++l) {
         const int q = l - LLO;
         out[(size_t)(l * (l + 1) + M0 - 1) * a.ldp + i] = accP[q];
         out[(size_t)(HALF + l * (l + 1) + M0 - 1) * a.ldp + i] = accM[q];
-        if constexpr (MIRROR) {
+        if constexpr (M0 > 0) {
             out[(size_t)(l * (l + 1) - M0 - 1) * a.ldp + i] = accPm[q];
             out[(size_t)(HALF + l * (l + 1) - M0 - 1) * a.ldp + i] = accMm[q];
         }
     }
 }
 
-template <typename T, int L, int HMODE, int M0>
-static void launch_pass(const WxArgs<T>& a, int nchunk, hipStream_t s) {
-    dim3 grid((a.n + WX_BLOCK - 1) / WX_BLOCK, nchunk);
-    hipLaunchKernelGGL((wx_pass_kernel<T, L, M0, HMODE>), grid, dim3(WX_BLOCK), 0, s, a);
-    if constexpr (M0 > 0) launch_pass<T, L, HMODE, M0 - 1>(a, nchunk, s);
+// ---------------------------------------------------------------------------
+// one group of passes (receiving |m| = MA, and MB >= 0 if present) of the
+// coupling mat-vec over one (receiver tile, source chunk); the pair
+// geometry, the Hankel functions and the Legendre columns are computed once
+// per pair and shared by the passes of the group
+// ---------------------------------------------------------------------------
+template <typename T, int L, int HMODE, int MA, int MB>
+__device__ __forceinline__ void wx_group(const WxArgs<T>& a, cx<T>* tile) {
+    constexpr int HALF = L * (L + 2);
+    constexpr int P2 = 2 * L;
+    constexpr bool HASB = MB >= 0;
+    constexpr int MUMAX = HASB ? imax(mu_max(L, MA), mu_max(L, MB)) : mu_max(L, MA);
+
+    const int i = blockIdx.x * WX_BLOCK + threadIdx.x;
+    const int chunk = blockIdx.y;
+    const bool active = i < a.n;
+    const double xi = active ? a.px[i] : 0.0;
+    const double yi = active ? a.py[i] : 0.0;
+    const double zi = active ? a.pz[i] : 0.0;
+
+    cx<T> aP[L], aM[L], aPm[L], aMm[L];
+    cx<T> bP[L], bM[L], bPm[L], bMm[L];
+#pragma unroll
+    for (int q = 0; q < L; ++q) {
+        aP[q] = aM[q] = aPm[q] = aMm[q] = {0, 0};
+        bP[q] = bM[q] = bPm[q] = bMm[q] = {0, 0};
+    }
+
+    const int j0 = chunk * a.chunk_len;
+    const int j1 = min(a.n, j0 + a.chunk_len);
+    for (int t0 = j0; t0 < j1; t0 += WX_TILE) {
+        const int nt = min(WX_TILE, j1 - t0);
+        __syncthreads();
+        {
+            const cx<T>* src = a.xsd + (size_t)t0 * (2 * HALF);
+            for (int e = threadIdx.x; e < nt * 2 * HALF; e += WX_BLOCK) tile[e] = src[e];
+        }
+        __syncthreads();
+        for (int jj = 0; jj < nt; ++jj) {
+            const int j = t0 + jj;
+            if (!active || j == i) continue;
+            // ---- pair geometry (FP64) ----
+            const double dx = xi - a.px[j], dy = yi - a.py[j], dz = zi - a.pz[j];
+            const double rho2 = dx * dx + dy * dy;
+            const double r = sqrt(rho2 + dz * dz);
+            const double inv_r = 1.0 / r;
+            const double rho = sqrt(rho2);
+            const T ct = (T)(dz * inv_r), st = (T)(rho * inv_r);
+            T cph = 1, sph = 0;
+            if (rho > 0.0) {
+                const double ir = 1.0 / rho;
+                cph = (T)(dx * ir);
+                sph = (T)(dy * ir);
+            }
+            // ---- radial functions ----
+            cx<T> h[P2 + 1];
+            if constexpr (HMODE == 0)
+                hankel_lut<T, P2>(r, a.lut, h);
+            else
+                hankel_direct<T, P2>(a.k * r, h);
+
+            const cx<T>* xs = tile + jj * (2 * HALF);
+            const cx<T> e1 = {cph, sph};
+            cx<T> emu = {1, 0};
+            T pmm = (T)0.70710678118654752440;   // P_0^0
+            sfor<0, MUMAX + 1>([&](auto MU_) {
+                constexpr int mu = decltype(MU_)::value;
+                if constexpr (mu > 0) {
+                    constexpr double cd = leg_diag(mu);
+                    pmm = (T)cd * st * pmm;
+                    emu = cmul(emu, e1);
+                }
+                // Legendre column P_p^mu, p = mu..2L, and H_p = h_p P_p^mu
+                T Pc[P2 + 1];
+                cx<T> H[P2 + 1];
+                sfor<mu, P2 + 1>([&](auto PP_) {
+                    constexpr int p = decltype(PP_)::value;
+                    if constexpr (p == mu) {
+                        Pc[p] = pmm;
+                    } else if constexpr (p == mu + 1) {
+                        constexpr double cs = leg_sub(mu);
+                        Pc[p] = (T)cs * ct * pmm;
+                    } else {
+                        constexpr double ca = leg_a(p, mu), cb = leg_b(p, mu);
+                        Pc[p] = (T)ca * ct * Pc[p - 1] - (T)cb * Pc[p - 2];
+                    }
+                    H[p] = {h[p].re * Pc[p], h[p].im * Pc[p]};
+                });
+                if constexpr (mu <= mu_max(L, MA)) pass_mu_step<T, L, MA, mu>(xs, H, emu, aP, aM, aPm, aMm);
+                if constexpr (HASB) {
+                    if constexpr (mu <= mu_max(L, MB)) pass_mu_step<T, L, MB, mu>(xs, H, emu, bP, bM, bPm, bMm);
+                }
+            });
+        }
+    }
+    if (!active) return;
+    pass_store<T, L, MA>(a, chunk, i, aP, aM, aPm, aMm);
+    if constexpr (HASB) pass_store<T, L, MB>(a, chunk, i, bP, bM, bPm, bMm);
+}
+
+// Pass groups per cut-off, heaviest first (blockIdx.z indexes the group).
+// Groups share one pair set-up; they are sized so that each stays within
+// 256 VGPRs in FP64 (two waves per SIMD).
+template <int L>
+struct Groups;
+template <> struct Groups<1> { static constexpr int n = 1; static constexpr int a[1] = {0}; static constexpr int b[1] = {1}; };
+template <> struct Groups<2> { static constexpr int n = 2; static constexpr int a[2] = {1, 0}; static constexpr int b[2] = {-1, 2}; };
+template <> struct Groups<3> { static constexpr int n = 3; static constexpr int a[3] = {1, 2, 0}; static constexpr int b[3] = {-1, 3, -1}; };
+template <> struct Groups<4> { static constexpr int n = 4; static constexpr int a[4] = {1, 2, 0, 3}; static constexpr int b[4] = {-1, -1, -1, 4}; };
+template <> struct Groups<5> { static constexpr int n = 5; static constexpr int a[5] = {1, 2, 3, 0, 4}; static constexpr int b[5] = {-1, -1, -1, -1, 5}; };
+template <> struct Groups<6> { static constexpr int n = 6; static constexpr int a[6] = {1, 2, 3, 0, 4, 5}; static constexpr int b[6] = {-1, -1, -1, -1, -1, 6}; };
+
+template <typename T, int L, int HMODE>
+__global__ __launch_bounds__(WX_BLOCK) void wx_fused_kernel(WxArgs<T> a) {
+    constexpr int HALF = L * (L + 2);
+    // source tile staged in LDS; every lane reads the same element (broadcast)
+    __shared__ cx<T> tile[WX_TILE * 2 * HALF];
+    const int g = blockIdx.z;
+    sfor<0, Groups<L>::n>([&](auto G_) {
+        constexpr int gi = decltype(G_)::value;
+        if (g == gi) wx_group<T, L, HMODE, Groups<L>::a[gi], Groups<L>::b[gi]>(a, tile);
+    });
 }
 
 template <typename T, int L>
 void wx_run_L(const WxArgs<T>& a, int hmode, int nchunk, hipStream_t s) {
+    dim3 grid((a.n + WX_BLOCK - 1) / WX_BLOCK, nchunk, Groups<L>::n);
     if (hmode == 0)
-        launch_pass<T, L, 0, L>(a, nchunk, s);
+        hipLaunchKernelGGL((wx_fused_kernel<T, L, 0>), grid, dim3(WX_BLOCK), 0, s, a);
     else
-        launch_pass<T, L, 1, L>(a, nchunk, s);
+        hipLaunchKernelGGL((wx_fused_kernel<T, L, 1>), grid, dim3(WX_BLOCK), 0, s, a);
 }
+
+template <int L>
+int wx_num_groups_L() { return Groups<L>::n; }
+template int wx_num_groups_L<CELES_WX_L>();
 
 template void wx_run_L<double, CELES_WX_L>(const WxArgs<double>&, int, int, hipStream_t);
 template void wx_run_L<float, CELES_WX_L>(const WxArgs<float>&, int, int, hipStream_t);

@@ -31,6 +31,10 @@ struct WxArgs {
 // per-L pass launcher (defined in wx_kernels.hip, one translation unit per L)
 template <typename T, int L>
 void wx_run_L(const WxArgs<T>& a, int hmode, int nchunk, hipStream_t s);
+// number of pass groups (third grid dimension) of cut-off L
+template <int L>
+int wx_num_groups_L();
+int wx_num_groups(int L);
 
 constexpr int WX_BLOCK_SIZE = 256;  // receivers per block
 constexpr int WX_TILE_SIZE = 16;    // sources per LDS tile
