@@ -92,6 +92,7 @@ struct celes_handle {
     DevBuf d_V, d_w, d_z, d_r, d_x, d_rhs, d_h, d_partial, d_V32, d_w32, d_z32, d_r32, d_x32;
     // preconditioner
     std::unique_ptr<celes::BlockPrecond> pre;
+    int target_blocks = 0;       // mat-vec work split (0: default); set by the autotuner
     std::string err;
 };
 
@@ -211,25 +212,33 @@ int build_lut(celes_handle* h) {
 // ---------------------------------------------------------------------------
 // mat-vec driver
 // ---------------------------------------------------------------------------
-int pick_chunks(int64_t N, int L) {
-    const char* env = std::getenv("CELES_WX_TARGET_BLOCKS");
-    int target = env ? std::max(1, std::atoi(env)) : 1024;
-    int64_t nbx = (N + celes::WX_BLOCK_SIZE - 1) / celes::WX_BLOCK_SIZE * celes::wx_num_groups(L);
-    int64_t nchunk = (target + nbx - 1) / nbx;
-    int64_t maxc = (N + celes::WX_TILE_SIZE - 1) / celes::WX_TILE_SIZE;
-    nchunk = std::max<int64_t>(1, std::min(nchunk, maxc));
-    return (int)nchunk;
+// right-hand-side block width: largest compiled width that divides K
+template <typename T>
+int pick_kb(int L, int K) {
+    const char* env = std::getenv("CELES_WX_KB");
+    int mx = celes::wx_max_kb<T>(L);
+    if (env) mx = std::min(mx, std::max(1, std::atoi(env)));
+    for (int kb = mx; kb > 1; kb /= 2)
+        if (K % kb == 0) return kb;
+    return 1;
 }
 
+// y = W x (epilogue 0) or x - T W x (epilogue 1) for K right-hand sides,
+// x, y: [K][N][nmax] device buffers of precision T
 template <typename T>
-int matvec(celes_handle* h, const cx<T>* x, cx<T>* y, int epilogue, hipStream_t s) {
+int matvec(celes_handle* h, const cx<T>* x, cx<T>* y, int K, int epilogue, hipStream_t s) {
     const int64_t N = h->N;
-    const int nchunk = pick_chunks(N, h->L);
+    const int kb = pick_kb<T>(h->L, K);
+    int64_t nbx = (N + celes::WX_BLOCK_SIZE - 1) / celes::WX_BLOCK_SIZE * celes::wx_num_groups(h->L) * (K / kb);
+    const char* env = std::getenv("CELES_WX_TARGET_BLOCKS");
+    const int target = env ? std::max(1, std::atoi(env)) : (h->target_blocks > 0 ? h->target_blocks : 1024);
+    int64_t nchunk = (target + nbx - 1) / nbx;
+    nchunk = std::max<int64_t>(1, std::min<int64_t>(nchunk, (N + celes::WX_TILE_SIZE - 1) / celes::WX_TILE_SIZE));
     int64_t chunk_len = (N + nchunk - 1) / nchunk;
     chunk_len = (chunk_len + celes::WX_TILE_SIZE - 1) / celes::WX_TILE_SIZE * celes::WX_TILE_SIZE;
     const int nchunk_eff = (int)((N + chunk_len - 1) / chunk_len);
-    if (!h->d_xsd.ensure((size_t)N * h->nmax * sizeof(cx<T>)) ||
-        !h->d_part.ensure((size_t)nchunk_eff * h->nmax * N * sizeof(cx<T>)))
+    if (!h->d_xsd.ensure((size_t)K * N * h->nmax * sizeof(cx<T>)) ||
+        !h->d_part.ensure((size_t)nchunk_eff * K * h->nmax * N * sizeof(cx<T>)))
         return fail(h, CELES_E_OOM, "cannot allocate mat-vec scratch");
     celes::WxArgs<T> a;
     a.px = h->d_px.as<double>();
@@ -245,6 +254,8 @@ int matvec(celes_handle* h, const cx<T>* x, cx<T>* y, int epilogue, hipStream_t 
     a.n = (int)N;
     a.chunk_len = (int)chunk_len;
     a.ldp = (int)N;
+    a.nrhs = K;
+    a.kb = kb;
     const cx<T>* tq = (sizeof(T) == 8) ? (const cx<T>*)h->d_tq64.p : (const cx<T>*)h->d_tq32.p;
     int rc = celes::wx_launch<T>(a, h->L, h->opt.hankel == CELES_HANKEL_DIRECT ? 1 : 0, nchunk_eff, x, tq, y,
                                  epilogue, s);
@@ -292,7 +303,7 @@ int gmres_device(celes_handle* h, const cx<T>* rhs, cx<T>* x, double tol, int ma
     hipEventCreate(&e1);
     auto timed_matvec = [&](const cx<T>* in, cx<T>* outv) -> int {
         hipEventRecord(e0, s);
-        int rc = matvec<T>(h, in, outv, 1, s);
+        int rc = matvec<T>(h, in, outv, 1, 1, s);
         hipEventRecord(e1, s);
         hipEventSynchronize(e1);
         float ms = 0;
@@ -423,7 +434,7 @@ double residual64(celes_handle* h, const cx<double>* rhs, const cx<double>* x, c
     hipEventCreate(&e0);
     hipEventCreate(&e1);
     hipEventRecord(e0, s);
-    *rc = matvec<double>(h, x, h->d_w.as<cx<double>>(), 1, s);
+    *rc = matvec<double>(h, x, h->d_w.as<cx<double>>(), 1, 1, s);
     hipEventRecord(e1, s);
     celes::vec_sub<double>(rhs, h->d_w.as<cx<double>>(), r, n, s);
     celes::vec_dots<double>(r, 0, 1, r, n, h->d_partial.as<cx<double>>(), h->d_h.as<cx<double>>(), s);
@@ -712,36 +723,18 @@ int celes_apply_W(celes_handle* h, int precision, int K, const void* x_dev, void
     if (!h) return CELES_E_ARG;
     if (K < 1 || !x_dev || !y_dev) return fail(h, CELES_E_ARG, "K < 1 or null device pointer");
     hipStream_t s = (hipStream_t)stream;
-    const size_t stride = (size_t)h->N * h->nmax;
-    for (int kk = 0; kk < K; ++kk) {
-        int rc;
-        if (precision == CELES_FP64)
-            rc = matvec<double>(h, (const cx<double>*)x_dev + kk * stride, (cx<double>*)y_dev + kk * stride, 0, s);
-        else if (precision == CELES_MIXED)
-            rc = matvec<float>(h, (const cx<float>*)x_dev + kk * stride, (cx<float>*)y_dev + kk * stride, 0, s);
-        else
-            return fail(h, CELES_E_ARG, "unknown precision");
-        if (rc != CELES_OK) return rc;
-    }
-    return CELES_OK;
+    if (precision == CELES_FP64) return matvec<double>(h, (const cx<double>*)x_dev, (cx<double>*)y_dev, K, 0, s);
+    if (precision == CELES_MIXED) return matvec<float>(h, (const cx<float>*)x_dev, (cx<float>*)y_dev, K, 0, s);
+    return fail(h, CELES_E_ARG, "unknown precision");
 }
 
 int celes_apply_M(celes_handle* h, int precision, int K, const void* x_dev, void* y_dev, void* stream) {
     if (!h) return CELES_E_ARG;
     if (K < 1 || !x_dev || !y_dev) return fail(h, CELES_E_ARG, "K < 1 or null device pointer");
     hipStream_t s = (hipStream_t)stream;
-    const size_t stride = (size_t)h->N * h->nmax;
-    for (int kk = 0; kk < K; ++kk) {
-        int rc;
-        if (precision == CELES_FP64)
-            rc = matvec<double>(h, (const cx<double>*)x_dev + kk * stride, (cx<double>*)y_dev + kk * stride, 1, s);
-        else if (precision == CELES_MIXED)
-            rc = matvec<float>(h, (const cx<float>*)x_dev + kk * stride, (cx<float>*)y_dev + kk * stride, 1, s);
-        else
-            return fail(h, CELES_E_ARG, "unknown precision");
-        if (rc != CELES_OK) return rc;
-    }
-    return CELES_OK;
+    if (precision == CELES_FP64) return matvec<double>(h, (const cx<double>*)x_dev, (cx<double>*)y_dev, K, 1, s);
+    if (precision == CELES_MIXED) return matvec<float>(h, (const cx<float>*)x_dev, (cx<float>*)y_dev, K, 1, s);
+    return fail(h, CELES_E_ARG, "unknown precision");
 }
 
 int celes_build_preconditioner(celes_handle* h, double cuboid_edge) {

@@ -8,36 +8,42 @@
 
 namespace celes {
 
-// x [N][nmax] (tau blocks) -> xsd [N][2][HALF] with s = x1 + x2, d = x1 - x2
+// x [K][N][nmax] (tau blocks) -> xsd [N][K][2][HALF], s = x1 + x2, d = x1 - x2
 template <typename T>
-__global__ void wx_prep_kernel(const cx<T>* __restrict__ x, cx<T>* __restrict__ xsd, int n, int half) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n * half) return;
-    const int i = t / half, c = t % half;
-    const cx<T> a = x[(size_t)i * 2 * half + c], b = x[(size_t)i * 2 * half + half + c];
-    xsd[(size_t)i * 2 * half + c] = {a.re + b.re, a.im + b.im};
-    xsd[(size_t)i * 2 * half + half + c] = {a.re - b.re, a.im - b.im};
+__global__ void wx_prep_kernel(const cx<T>* __restrict__ x, cx<T>* __restrict__ xsd, int n, int half, int K) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)n * half * K) return;
+    const int c = (int)(t % half);
+    const int64_t ik = t / half;
+    const int i = (int)(ik % n), k = (int)(ik / n);
+    const cx<T> a = x[((size_t)k * n + i) * 2 * half + c], b = x[((size_t)k * n + i) * 2 * half + half + c];
+    cx<T>* o = xsd + ((size_t)i * K + k) * 2 * half;
+    o[c] = {a.re + b.re, a.im + b.im};
+    o[half + c] = {a.re - b.re, a.im - b.im};
 }
 
 // sum partials over chunks, convert to (tau, l, m), optional y = x - T (W x)
 template <typename T>
-__global__ void wx_finish_kernel(const cx<T>* __restrict__ part, int nchunk, int ldp, int n, int L,
+__global__ void wx_finish_kernel(const cx<T>* __restrict__ part, int nchunk, int ldp, int n, int L, int K,
                                  const cx<T>* __restrict__ x, const cx<T>* __restrict__ tq,
                                  cx<T>* __restrict__ y, int epilogue) {
     const int half = L * (L + 2);
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n * half) return;
-    const int c = t / n, i = t % n;      // consecutive lanes: consecutive spheres (coalesced part reads)
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)n * half * K) return;
+    const int i = (int)(t % n);          // consecutive lanes: consecutive spheres (coalesced part reads)
+    const int64_t ck = t / n;
+    const int c = (int)(ck % half), k = (int)(ck / half);
     cx<T> sp = {0, 0}, sm = {0, 0};
     for (int ch = 0; ch < nchunk; ++ch) {
-        const cx<T> a = part[((size_t)ch * 2 * half + c) * ldp + i];
-        const cx<T> b = part[((size_t)ch * 2 * half + half + c) * ldp + i];
+        const size_t base = ((size_t)ch * K + k) * 2 * half;
+        const cx<T> a = part[(base + c) * ldp + i];
+        const cx<T> b = part[(base + half + c) * ldp + i];
         sp.re += a.re; sp.im += a.im;
         sm.re += b.re; sm.im += b.im;
     }
     cx<T> y1 = {(T)0.5 * (sp.re + sm.re), (T)0.5 * (sp.im + sm.im)};
     cx<T> y2 = {(T)0.5 * (sp.re - sm.re), (T)0.5 * (sp.im - sm.im)};
-    const size_t b1 = (size_t)i * 2 * half + c, b2 = b1 + half;
+    const size_t b1 = ((size_t)k * n + i) * 2 * half + c, b2 = b1 + half;
     if (epilogue) {
         // l of the (l, m) index c: l(l+1)+m-1 = c  ->  l = floor(sqrt(c+1))
         int l = (int)sqrtf((float)(c + 1));
@@ -67,13 +73,27 @@ int wx_num_groups(int L) {
 }
 
 template <typename T>
+int wx_max_kb(int L) {
+    switch (L) {
+        case 1: return wx_max_kb_L<T, 1>();
+        case 2: return wx_max_kb_L<T, 2>();
+        case 3: return wx_max_kb_L<T, 3>();
+        case 4: return wx_max_kb_L<T, 4>();
+        case 5: return wx_max_kb_L<T, 5>();
+        case 6: return wx_max_kb_L<T, 6>();
+        default: return 1;
+    }
+}
+template int wx_max_kb<double>(int);
+template int wx_max_kb<float>(int);
+
+template <typename T>
 int wx_launch(const WxArgs<T>& a, int L, int hmode, int nchunk, const cx<T>* x, const cx<T>* tq,
               cx<T>* y, int epilogue, hipStream_t s) {
     const int half = L * (L + 2);
-    {
-        int tot = a.n * half;
-        hipLaunchKernelGGL(wx_prep_kernel<T>, dim3((tot + 255) / 256), dim3(256), 0, s, x, const_cast<cx<T>*>(a.xsd), a.n, half);
-    }
+    const int64_t tot = (int64_t)a.n * half * a.nrhs;
+    hipLaunchKernelGGL(wx_prep_kernel<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, x,
+                       const_cast<cx<T>*>(a.xsd), a.n, half, a.nrhs);
 switch (L) {
         case 1: wx_run_L<T, 1>(a, hmode, nchunk, s); break;
         case 2: wx_run_L<T, 2>(a, hmode, nchunk, s); break;
@@ -84,11 +104,8 @@ switch (L) {
         default: return -1;
     }
 
-    {
-        int tot = a.n * half;
-        hipLaunchKernelGGL(wx_finish_kernel<T>, dim3((tot + 255) / 256), dim3(256), 0, s, a.part, nchunk,
-                           a.ldp, a.n, L, x, tq, y, epilogue);
-    }
+    hipLaunchKernelGGL(wx_finish_kernel<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, a.part, nchunk,
+                       a.ldp, a.n, L, a.nrhs, x, tq, y, epilogue);
     return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 

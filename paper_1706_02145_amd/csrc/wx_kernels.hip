@@ -100,10 +100,10 @@ __device__ __forceinline__ void hankel_lut(double d, const LutView<T>& lut, cx<T
 // ---------------------------------------------------------------------------
 // accumulation of one receiving |m| = M0 for one (mu, Legendre column) step
 // ---------------------------------------------------------------------------
-template <typename T, int L, int M0, int mu>
+template <typename T, int L, int KB, int M0, int mu>
 __device__ __forceinline__ void pass_mu_step(const cx<T>* xs, const cx<T> (&H)[2 * L + 1], cx<T> emu,
-                                             cx<T> (&accP)[L], cx<T> (&accM)[L], cx<T> (&accPm)[L],
-                                             cx<T> (&accMm)[L]) {
+                                             cx<T> (&accP)[KB][L], cx<T> (&accM)[KB][L], cx<T> (&accPm)[KB][L],
+                                             cx<T> (&accMm)[KB][L]) {
     constexpr int HALF = L * (L + 2);
     constexpr int LLO = l_lo(M0);
     constexpr bool MIRROR = M0 > 0;
@@ -118,16 +118,18 @@ __device__ __forceinline__ void pass_mu_step(const cx<T>* xs, const cx<T> (&H)[2
                 constexpr int lp = decltype(LP_)::value;
                 // keep the group's LDS reads next to their use (bounded live range)
                 __builtin_amdgcn_sched_barrier(0);
-                // source coefficients of (l', m') and of the mirror (l', -m')
-                const cx<T> s1 = xs[lp * (lp + 1) + mp - 1];
-                const cx<T> d1 = xs[HALF + lp * (lp + 1) + mp - 1];
-                const cx<T> ts = cmul(rot, s1), td = cmul(rot, d1);
-                cx<T> us = {0, 0}, ud = {0, 0};
-                if constexpr (two) {
-                    const cx<T> s2 = xs[lp * (lp + 1) - mp - 1];
-                    const cx<T> d2 = xs[HALF + lp * (lp + 1) - mp - 1];
-                    us = cmul(rotc, s2);
-                    ud = cmul(rotc, d2);
+                // source coefficients of (l', m') and of the mirror (l', -m'),
+                // for each right-hand side of the block (tile row = [KB][2 HALF])
+                cx<T> ts[KB], td[KB], us[KB], ud[KB];
+#pragma unroll
+                for (int kb = 0; kb < KB; ++kb) {
+                    const cx<T>* xk = xs + kb * (2 * HALF);
+                    ts[kb] = cmul(rot, xk[lp * (lp + 1) + mp - 1]);
+                    td[kb] = cmul(rot, xk[HALF + lp * (lp + 1) + mp - 1]);
+                    if constexpr (two) {
+                        us[kb] = cmul(rotc, xk[lp * (lp + 1) - mp - 1]);
+                        ud[kb] = cmul(rotc, xk[HALF + lp * (lp + 1) - mp - 1]);
+                    }
                 }
                 sfor<LLO, L + 1>([&](auto LL_) {
                     constexpr int l = decltype(LL_)::value;
@@ -152,14 +154,17 @@ __device__ __forceinline__ void pass_mu_step(const cx<T>* xs, const cx<T> (&H)[2
                     const cx<T> Pv = {A.re - B.im, A.im + B.re};
                     const cx<T> Qv = {A.re + B.im, A.im - B.re};
                     constexpr int q = l - LLO;
-                    cfma(accP[q], Pv, ts);
-                    cfma(accM[q], Qv, td);
-                    if constexpr (MIRROR) {
-                        cfma(accPm[q], Qv, us);
-                        cfma(accMm[q], Pv, ud);
-                    } else if constexpr (two) {
-                        cfma(accP[q], Qv, us);
-                        cfma(accM[q], Pv, ud);
+#pragma unroll
+                    for (int kb = 0; kb < KB; ++kb) {
+                        cfma(accP[kb][q], Pv, ts[kb]);
+                        cfma(accM[kb][q], Qv, td[kb]);
+                        if constexpr (MIRROR) {
+                            cfma(accPm[kb][q], Qv, us[kb]);
+                            cfma(accMm[kb][q], Pv, ud[kb]);
+                        } else if constexpr (two) {
+                            cfma(accP[kb][q], Qv, us[kb]);
+                            cfma(accM[kb][q], Pv, ud[kb]);
+                        }
                     }
                 });
             });
@@ -167,21 +172,25 @@ __device__ __forceinline__ void pass_mu_step(const cx<T>* xs, const cx<T> (&H)[2
     });
 }
 
-template <typename T, int L, int M0>
-__device__ __forceinline__ void pass_store(const WxArgs<T>& a, int chunk, int i, const cx<T> (&accP)[L],
-                                           const cx<T> (&accM)[L], const cx<T> (&accPm)[L],
-                                           const cx<T> (&accMm)[L]) {
+// partial sums: part[chunk][k][kk][i] for right-hand side k = k0 + kb
+template <typename T, int L, int KB, int M0>
+__device__ __forceinline__ void pass_store(const WxArgs<T>& a, int chunk, int k0, int i,
+                                           const cx<T> (&accP)[KB][L], const cx<T> (&accM)[KB][L],
+                                           const cx<T> (&accPm)[KB][L], const cx<T> (&accMm)[KB][L]) {
     constexpr int HALF = L * (L + 2);
     constexpr int LLO = l_lo(M0);
-    cx<T>* out = a.part + (size_t)chunk * (2 * HALF) * a.ldp;
 #pragma unroll
-    for (int l = LLO; l <= L; ++l) {
-        const int q = l - LLO;
-        out[(size_t)(l * (l + 1) + M0 - 1) * a.ldp + i] = accP[q];
-        out[(size_t)(HALF + l * (l + 1) + M0 - 1) * a.ldp + i] = accM[q];
-        if constexpr (M0 > 0) {
-            out[(size_t)(l * (l + 1) - M0 - 1) * a.ldp + i] = accPm[q];
-            out[(size_t)(HALF + l * (l + 1) - M0 - 1) * a.ldp + i] = accMm[q];
+    for (int kb = 0; kb < KB; ++kb) {
+        cx<T>* out = a.part + ((size_t)chunk * a.nrhs + k0 + kb) * (2 * HALF) * a.ldp;
+#pragma unroll
+        for (int l = LLO; l <= L; ++l) {
+            const int q = l - LLO;
+            out[(size_t)(l * (l + 1) + M0 - 1) * a.ldp + i] = accP[kb][q];
+            out[(size_t)(HALF + l * (l + 1) + M0 - 1) * a.ldp + i] = accM[kb][q];
+            if constexpr (M0 > 0) {
+                out[(size_t)(l * (l + 1) - M0 - 1) * a.ldp + i] = accPm[kb][q];
+                out[(size_t)(HALF + l * (l + 1) - M0 - 1) * a.ldp + i] = accMm[kb][q];
+            }
         }
     }
 }
@@ -192,8 +201,8 @@ __device__ __forceinline__ void pass_store(const WxArgs<T>& a, int chunk, int i,
 // geometry, the Hankel functions and the Legendre columns are computed once
 // per pair and shared by the passes of the group
 // ---------------------------------------------------------------------------
-template <typename T, int L, int HMODE, int MA, int MB>
-__device__ __forceinline__ void wx_group(const WxArgs<T>& a, cx<T>* tile) {
+template <typename T, int L, int KB, int HMODE, int MA, int MB>
+__device__ __forceinline__ void wx_group(const WxArgs<T>& a, cx<T>* tile, int k0) {
     constexpr int HALF = L * (L + 2);
     constexpr int P2 = 2 * L;
     constexpr bool HASB = MB >= 0;
@@ -206,13 +215,15 @@ __device__ __forceinline__ void wx_group(const WxArgs<T>& a, cx<T>* tile) {
     const double yi = active ? a.py[i] : 0.0;
     const double zi = active ? a.pz[i] : 0.0;
 
-    cx<T> aP[L], aM[L], aPm[L], aMm[L];
-    cx<T> bP[L], bM[L], bPm[L], bMm[L];
+    cx<T> aP[KB][L], aM[KB][L], aPm[KB][L], aMm[KB][L];
+    cx<T> bP[KB][L], bM[KB][L], bPm[KB][L], bMm[KB][L];
 #pragma unroll
-    for (int q = 0; q < L; ++q) {
-        aP[q] = aM[q] = aPm[q] = aMm[q] = {0, 0};
-        bP[q] = bM[q] = bPm[q] = bMm[q] = {0, 0};
-    }
+    for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+        for (int q = 0; q < L; ++q) {
+            aP[kb][q] = aM[kb][q] = aPm[kb][q] = aMm[kb][q] = {0, 0};
+            bP[kb][q] = bM[kb][q] = bPm[kb][q] = bMm[kb][q] = {0, 0};
+        }
 
     const int j0 = chunk * a.chunk_len;
     const int j1 = min(a.n, j0 + a.chunk_len);
@@ -220,8 +231,12 @@ __device__ __forceinline__ void wx_group(const WxArgs<T>& a, cx<T>* tile) {
         const int nt = min(WX_TILE, j1 - t0);
         __syncthreads();
         {
-            const cx<T>* src = a.xsd + (size_t)t0 * (2 * HALF);
-            for (int e = threadIdx.x; e < nt * 2 * HALF; e += WX_BLOCK) tile[e] = src[e];
+            // tile[jj][kb][e] <- xsd[t0 + jj][k0 + kb][e]  (xsd is [N][nrhs][2 HALF])
+            const int row = KB * 2 * HALF;
+            for (int e = threadIdx.x; e < nt * row; e += WX_BLOCK) {
+                const int jj = e / row, r = e % row;
+                tile[e] = a.xsd[((size_t)(t0 + jj) * a.nrhs + k0) * (2 * HALF) + r];
+            }
         }
         __syncthreads();
         for (int jj = 0; jj < nt; ++jj) {
@@ -247,7 +262,7 @@ __device__ __forceinline__ void wx_group(const WxArgs<T>& a, cx<T>* tile) {
             else
                 hankel_direct<T, P2>(a.k * r, h);
 
-            const cx<T>* xs = tile + jj * (2 * HALF);
+            const cx<T>* xs = tile + jj * (KB * 2 * HALF);
             const cx<T> e1 = {cph, sph};
             cx<T> emu = {1, 0};
             T pmm = (T)0.70710678118654752440;   // P_0^0
@@ -274,16 +289,16 @@ __device__ __forceinline__ void wx_group(const WxArgs<T>& a, cx<T>* tile) {
                     }
                     H[p] = {h[p].re * Pc[p], h[p].im * Pc[p]};
                 });
-                if constexpr (mu <= mu_max(L, MA)) pass_mu_step<T, L, MA, mu>(xs, H, emu, aP, aM, aPm, aMm);
+                if constexpr (mu <= mu_max(L, MA)) pass_mu_step<T, L, KB, MA, mu>(xs, H, emu, aP, aM, aPm, aMm);
                 if constexpr (HASB) {
-                    if constexpr (mu <= mu_max(L, MB)) pass_mu_step<T, L, MB, mu>(xs, H, emu, bP, bM, bPm, bMm);
+                    if constexpr (mu <= mu_max(L, MB)) pass_mu_step<T, L, KB, MB, mu>(xs, H, emu, bP, bM, bPm, bMm);
                 }
             });
         }
     }
     if (!active) return;
-    pass_store<T, L, MA>(a, chunk, i, aP, aM, aPm, aMm);
-    if constexpr (HASB) pass_store<T, L, MB>(a, chunk, i, bP, bM, bPm, bMm);
+    pass_store<T, L, KB, MA>(a, chunk, k0, i, aP, aM, aPm, aMm);
+    if constexpr (HASB) pass_store<T, L, KB, MB>(a, chunk, k0, i, bP, bM, bPm, bMm);
 }
 
 // Pass groups per cut-off, heaviest first (blockIdx.z indexes the group).
@@ -298,26 +313,53 @@ template <> struct Groups<4> { static constexpr int n = 4; static constexpr int 
 template <> struct Groups<5> { static constexpr int n = 5; static constexpr int a[5] = {1, 2, 3, 0, 4}; static constexpr int b[5] = {-1, -1, -1, -1, 5}; };
 template <> struct Groups<6> { static constexpr int n = 6; static constexpr int a[6] = {1, 2, 3, 0, 4, 5}; static constexpr int b[6] = {-1, -1, -1, -1, -1, 6}; };
 
-template <typename T, int L, int HMODE>
+// blockIdx.z = g + G * kblock: pass group g, right-hand sides kblock*KB .. +KB
+template <typename T, int L, int KB, int HMODE>
 __global__ __launch_bounds__(WX_BLOCK) void wx_fused_kernel(WxArgs<T> a) {
     constexpr int HALF = L * (L + 2);
     // source tile staged in LDS; every lane reads the same element (broadcast)
-    __shared__ cx<T> tile[WX_TILE * 2 * HALF];
-    const int g = blockIdx.z;
+    __shared__ cx<T> tile[WX_TILE * KB * 2 * HALF];
+    const int g = blockIdx.z % Groups<L>::n;
+    const int k0 = (blockIdx.z / Groups<L>::n) * KB;
     sfor<0, Groups<L>::n>([&](auto G_) {
         constexpr int gi = decltype(G_)::value;
-        if (g == gi) wx_group<T, L, HMODE, Groups<L>::a[gi], Groups<L>::b[gi]>(a, tile);
+        if (g == gi) wx_group<T, L, KB, HMODE, Groups<L>::a[gi], Groups<L>::b[gi]>(a, tile, k0);
     });
+}
+
+// right-hand-side block widths compiled per precision and cut-off
+template <typename T, int L>
+constexpr int max_kb() {
+    if constexpr (L > 4) return 1;
+    else if constexpr (sizeof(T) == 8) return L <= 3 ? 2 : 1;
+    else return 4;
+}
+
+template <typename T, int L, int KB>
+static void launch_kb(const WxArgs<T>& a, int hmode, int nchunk, hipStream_t s) {
+    dim3 grid((a.n + WX_BLOCK - 1) / WX_BLOCK, nchunk, Groups<L>::n * (a.nrhs / KB));
+    if (hmode == 0)
+        hipLaunchKernelGGL((wx_fused_kernel<T, L, KB, 0>), grid, dim3(WX_BLOCK), 0, s, a);
+    else
+        hipLaunchKernelGGL((wx_fused_kernel<T, L, KB, 1>), grid, dim3(WX_BLOCK), 0, s, a);
 }
 
 template <typename T, int L>
 void wx_run_L(const WxArgs<T>& a, int hmode, int nchunk, hipStream_t s) {
-    dim3 grid((a.n + WX_BLOCK - 1) / WX_BLOCK, nchunk, Groups<L>::n);
-    if (hmode == 0)
-        hipLaunchKernelGGL((wx_fused_kernel<T, L, 0>), grid, dim3(WX_BLOCK), 0, s, a);
-    else
-        hipLaunchKernelGGL((wx_fused_kernel<T, L, 1>), grid, dim3(WX_BLOCK), 0, s, a);
+    // a.kb has been chosen by the host among 1, 2, 4 (<= max_kb) and divides a.nrhs
+    if constexpr (max_kb<T, L>() >= 4) {
+        if (a.kb == 4) return launch_kb<T, L, 4>(a, hmode, nchunk, s);
+    }
+    if constexpr (max_kb<T, L>() >= 2) {
+        if (a.kb == 2) return launch_kb<T, L, 2>(a, hmode, nchunk, s);
+    }
+    launch_kb<T, L, 1>(a, hmode, nchunk, s);
 }
+
+template <typename T, int L>
+int wx_max_kb_L() { return max_kb<T, L>(); }
+template int wx_max_kb_L<double, CELES_WX_L>();
+template int wx_max_kb_L<float, CELES_WX_L>();
 
 template <int L>
 int wx_num_groups_L() { return Groups<L>::n; }

@@ -18,14 +18,16 @@ struct WxArgs {
     const double* px;    // sphere centres, SoA, FP64
     const double* py;
     const double* pz;
-    const cx<T>* xsd;    // [N][2][HALF] source sums/differences (scratch, written by prep)
+    const cx<T>* xsd;    // [N][nrhs][2][HALF] source sums/differences (scratch, written by prep)
     const T* coef;       // a5 / b5im table in kernel enumeration order
-    cx<T>* part;         // [nchunk][2 HALF][ldp] partial sums
+    cx<T>* part;         // [nchunk][nrhs][2 HALF][ldp] partial sums
     LutView<T> lut;
     double k;            // background wavenumber
     int n;               // number of spheres
     int chunk_len;       // sources per chunk
     int ldp;             // leading dimension of part (>= n)
+    int nrhs;            // right-hand sides in xsd / part
+    int kb;              // right-hand sides per kernel block (1, 2 or 4; divides nrhs)
 };
 
 // per-L pass launcher (defined in wx_kernels.hip, one translation unit per L)
@@ -35,12 +37,18 @@ void wx_run_L(const WxArgs<T>& a, int hmode, int nchunk, hipStream_t s);
 template <int L>
 int wx_num_groups_L();
 int wx_num_groups(int L);
+// largest compiled right-hand-side block of cut-off L
+template <typename T, int L>
+int wx_max_kb_L();
+template <typename T>
+int wx_max_kb(int L);
 
 constexpr int WX_BLOCK_SIZE = 256;  // receivers per block
 constexpr int WX_TILE_SIZE = 16;    // sources per LDS tile
 
-// y = W x (epilogue = 0) or y = x - T (W x) (epilogue = 1); x, y: [N][nmax];
-// tq: [N][2][L] Mie coefficients.  Returns 0 on success.
+// y = W x (epilogue = 0) or y = x - T (W x) (epilogue = 1) for a.nrhs
+// right-hand sides; x, y: [nrhs][N][nmax]; tq: [N][2][L] Mie coefficients.
+// Returns 0 on success.
 template <typename T>
 int wx_launch(const WxArgs<T>& a, int L, int hmode, int nchunk, const cx<T>* x, const cx<T>* tq,
               cx<T>* y, int epilogue, hipStream_t s);

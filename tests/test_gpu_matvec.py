@@ -113,3 +113,28 @@ def test_reciprocity_at_full_size():
     lhs = np.sum(u * _gpu_W(p, v))
     rhs = np.sum(v[:, flip] * _gpu_W(p, u[:, flip]))
     assert abs(lhs - rhs) <= 1e-11 * abs(lhs)
+
+
+@pytest.mark.parametrize("name,precision,K", [("slab300_l3", P.CELES_FP64, 2), ("slab300_l3", P.CELES_MIXED, 4),
+                                              ("slab200_l4", P.CELES_MIXED, 4), ("slab200_l4", P.CELES_FP64, 3)])
+def test_apply_W_multi_rhs(name, precision, K):
+    w = workload(name)
+    print(f"[matvec multi-rhs] {name} K={K} precision={precision}", flush=True)
+    X = random_coefficients(110, K, w.N, w.nmax)
+    p = make_problem(w, hankel=1)
+    dt = torch.complex128 if precision == P.CELES_FP64 else torch.complex64
+    xd = _dev(X, dt)
+    yd = torch.empty_like(xd)
+    p.apply_W(xd, yd, precision, K=K)
+    torch.cuda.synchronize()
+    Y = yd.cpu().numpy().astype(np.complex128)
+    bar = 1e-12 if precision == P.CELES_FP64 else 1e-4
+    for k in range(K):
+        # same as the single right-hand-side launch
+        yk = _gpu_W(p, X[k], precision)
+        assert rel(Y[k], yk) <= (1e-14 if precision == P.CELES_FP64 else 1e-6)
+    rows = list(range(0, w.N, 17))
+    for k in range(K):
+        xk = X[k] if precision == P.CELES_FP64 else X[k].astype(np.complex64).astype(np.complex128)
+        ref = apply_W_rows(w.positions, xk, k_of(w), w.lmax, rows)
+        assert rel(Y[k][rows], ref) <= bar
