@@ -204,6 +204,58 @@ int celes_dims(const celes_handle* h, int64_t* N, int* lmax, int* nmax);
  * the host tables.  Errors: CELES_E_ARG. */
 int celes_translation_tables(int lmax, double* a5_out, double* b5im_out);
 
+/* Copy the scattered-field coefficients of the last solve of this problem
+ * (by celes_solve or by a batch containing it) to b_out [K][N][nmax]
+ * complex128.  Errors: CELES_E_STATE (no solution), CELES_E_ARG. */
+int celes_get_solution(const celes_handle* h, double* b_out);
+
+/* ---------------------------------------------------------------------------
+ * Batched solves.  A batch couples nothing: it solves the master equation
+ * (Section 2.2) of every right-hand side of every problem independently, but
+ * advances all of them together: one persistent mat-vec launch per Arnoldi
+ * step covers all problems and right-hand sides (ragged sizes allowed), the
+ * Krylov state of every system stays on the device, and one Arnoldi step is
+ * captured once in a hipGraph and replayed.  precision CELES_MIXED runs
+ * complex64 inner GMRES with FP64 residuals and refinement; CELES_FP64 runs
+ * FP64 throughout.  No preconditioner is applied in a batch.
+ * ------------------------------------------------------------------------- */
+typedef struct celes_batch celes_batch;
+
+/* Build a batch over nprob problems (all with the same lmax, each with its
+ * incident field set).  The handles stay owned by the caller and must
+ * outlive the batch; opt (precision, tol, inner_tol, restart, maxiter,
+ * max_refinements, hankel) applies to the whole batch (NULL: defaults).
+ * Errors: CELES_E_ARG, CELES_E_STATE, CELES_E_OOM, CELES_E_DEVICE. */
+int celes_batch_create(celes_batch** b, int nprob, celes_handle* const* probs, const celes_options* opt);
+
+/* Release the batch (not the problems).  NULL is allowed. */
+void celes_batch_destroy(celes_batch* b);
+
+/* Number of systems (sum of the problems' right-hand sides). */
+int celes_batch_num_systems(const celes_batch* b);
+
+/* Text of the last error of the batch (or of a failed create when b is NULL). */
+const char* celes_batch_last_error(const celes_batch* b);
+
+/* y = M x for every system at once on device buffers in the batch's flat
+ * layout (problem after problem, each [K_p][N_p][nmax]); complex128 for
+ * CELES_FP64, complex64 for CELES_MIXED.  Enqueued on `stream`.
+ * Errors: CELES_E_ARG, CELES_E_DEVICE. */
+int celes_batch_apply_M(celes_batch* b, int precision, const void* x_dev, void* y_dev, void* stream);
+
+/* Choose the batched mat-vec's source-chunk length and right-hand-side block
+ * width by timing the candidates on this batch; the choice is kept by the
+ * batch.  Outputs (may be NULL): the best time of one batched M x in ms, the
+ * chunk length, the block width.  Errors: CELES_E_ARG. */
+int celes_batch_autotune(celes_batch* b, int precision, double* best_ms, int* best_chunk, int* best_kb);
+
+/* Solve every system from a zero initial guess to opt.tol; solutions are
+ * stored in the problems (celes_get_solution, celes_cross_sections).  infos
+ * [num_systems] (may be NULL) receives per-system iterations and residuals,
+ * summary (may be NULL) totals and wall time.  Returns CELES_OK,
+ * CELES_E_NOCONV, CELES_E_BREAKDOWN, CELES_E_OOM or CELES_E_DEVICE. */
+int celes_batch_solve(celes_batch* b, celes_solve_info* infos, celes_solve_info* summary);
+
 #ifdef __cplusplus
 }
 #endif

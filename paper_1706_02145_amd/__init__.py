@@ -12,7 +12,7 @@ import numpy as np
 from ._capi import (CELES_FP64, CELES_HANKEL_DIRECT, CELES_HANKEL_LUT, CELES_MIXED, ERRORS, Options,
                     SolveInfo, lib, LIB_PATH)
 
-__all__ = ["Problem", "CelesError", "default_options", "mie_coefficients", "translation_tables", "version",
+__all__ = ["Problem", "Batch", "CelesError", "default_options", "mie_coefficients", "translation_tables", "version",
            "CELES_FP64", "CELES_MIXED", "CELES_HANKEL_LUT", "CELES_HANKEL_DIRECT", "LIB_PATH"]
 
 
@@ -188,7 +188,70 @@ class Problem:
                                       _dptr(out.view(np.float64))), self._h)
         return out
 
+    def solution(self):
+        out = np.zeros((self.num_rhs, self.N, self.nmax), dtype=np.complex128)
+        _check(lib().celes_get_solution(self._h, _dptr(out.view(np.float64))), self._h)
+        return out
+
     def lut_info(self):
         lo, dr, n = C.c_double(), C.c_double(), C.c_int64()
         _check(lib().celes_lut_info(self._h, C.byref(lo), C.byref(dr), C.byref(n)), self._h)
         return lo.value, dr.value, n.value
+
+
+def _bcheck(rc, b=None):
+    if rc != 0:
+        msg = lib().celes_batch_last_error(b)
+        raise CelesError(rc, msg.decode() if msg else "")
+
+
+class Batch:
+    """Independent problems solved together (celes_batch_*): one persistent
+    mat-vec launch per Arnoldi step over all problems and right-hand sides."""
+
+    def __init__(self, problems, options=None, **kw):
+        self.problems = list(problems)
+        arr = (C.c_void_p * len(self.problems))(*[p._h.value for p in self.problems])
+        opt = options if options is not None else default_options(**kw)
+        self._b = C.c_void_p()
+        rc = lib().celes_batch_create(C.byref(self._b), len(self.problems), arr, C.byref(opt))
+        if rc != 0:
+            self._b = None
+            _bcheck(rc, None)
+        self.options = opt
+
+    @property
+    def num_systems(self):
+        return lib().celes_batch_num_systems(self._b)
+
+    def close(self):
+        if getattr(self, "_b", None):
+            lib().celes_batch_destroy(self._b)
+            self._b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def apply_M(self, x, y, precision=CELES_FP64, stream=None):
+        xp = x.data_ptr() if hasattr(x, "data_ptr") else int(x)
+        yp = y.data_ptr() if hasattr(y, "data_ptr") else int(y)
+        _bcheck(lib().celes_batch_apply_M(self._b, precision, C.c_void_p(xp), C.c_void_p(yp), _stream_ptr(stream)),
+                self._b)
+
+    def autotune(self, precision=CELES_MIXED):
+        ms, ch, kb = C.c_double(), C.c_int(), C.c_int()
+        _bcheck(lib().celes_batch_autotune(self._b, precision, C.byref(ms), C.byref(ch), C.byref(kb)), self._b)
+        return {"ms": ms.value, "chunk_len": ch.value, "kb": kb.value}
+
+    def solve(self, check=True):
+        n = self.num_systems
+        infos = (SolveInfo * n)()
+        summ = SolveInfo()
+        rc = lib().celes_batch_solve(self._b, infos, C.byref(summ))
+        if check and rc != 0:
+            _bcheck(rc, self._b)
+        per = [{f: getattr(i, f) for f, _ in SolveInfo._fields_} for i in infos]
+        return per, {f: getattr(summ, f) for f, _ in SolveInfo._fields_}

@@ -55,6 +55,14 @@ SIGNATURES = {
     "celes_lut_info": (C.c_int, [_h, _dp, _dp, C.POINTER(C.c_int64)]),
     "celes_dims": (C.c_int, [_h, C.POINTER(C.c_int64), _ip, _ip]),
     "celes_translation_tables": (C.c_int, [C.c_int, _dp, _dp]),
+    "celes_get_solution": (C.c_int, [_h, _dp]),
+    "celes_batch_create": (C.c_int, [C.POINTER(_h), C.c_int, C.POINTER(_h), C.POINTER(Options)]),
+    "celes_batch_destroy": (None, [_h]),
+    "celes_batch_num_systems": (C.c_int, [_h]),
+    "celes_batch_last_error": (C.c_char_p, [_h]),
+    "celes_batch_apply_M": (C.c_int, [_h, C.c_int, _vp, _vp, _vp]),
+    "celes_batch_autotune": (C.c_int, [_h, C.c_int, _dp, _ip, _ip]),
+    "celes_batch_solve": (C.c_int, [_h, C.POINTER(SolveInfo), C.POINTER(SolveInfo)]),
 }
 
 _lib = None

@@ -37,7 +37,8 @@ def build(lmax_compiled=6, jobs=None, verbose=False, force=False):
     units = []
     for L in range(1, lmax_compiled + 1):
         units.append((os.path.join(CSRC, "wx_kernels.hip"), os.path.join(BUILD, f"wx_L{L}.o"), [f"-DCELES_WX_L={L}"]))
-    for f in ("wx_dispatch.hip", "vec_kernels.hip", "precond.hip", "host_math.cpp", "celes_lib.cpp"):
+    for f in ("wx_dispatch.hip", "vec_kernels.hip", "batch_kernels.hip", "precond.hip", "host_math.cpp",
+              "celes_lib.cpp"):
         units.append((os.path.join(CSRC, f), os.path.join(BUILD, os.path.splitext(f)[0] + ".o"), []))
     # the largest cut-offs take longest: start them first
     units.sort(key=lambda u: -int(u[2][0].split("=")[1]) if u[2] else 0)
@@ -80,6 +81,8 @@ def build(lmax_compiled=6, jobs=None, verbose=False, force=False):
                 f.write(f"template <> int wx_num_groups_L<{L}>() {{ return 1; }}\n")
                 for T in ("double", "float"):
                     f.write(f"template <> int wx_max_kb_L<{T}, {L}>() {{ return 1; }}\n")
+                    f.write(f"template <> void wx_batch_run_L<{T}, {L}>(const WxArgs<{T}>*, const int*, const int*, "
+                            f"const int*, int, int*, int, int, int, hipStream_t) {{}}\n")
             f.write("}\n")
         _run([HIPCC] + COMMON + ["-c", stub, "-o", os.path.join(BUILD, "wx_stub.o")])
         objs.append(os.path.join(BUILD, "wx_stub.o"))

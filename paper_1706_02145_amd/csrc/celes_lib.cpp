@@ -20,6 +20,7 @@
 #include "precond.hpp"
 #include "vec_kernels.hpp"
 #include "wx_launch.hpp"
+#include "batch_kernels.hpp"
 
 using celes::cplx;
 using celes::cx;
@@ -256,6 +257,8 @@ int matvec(celes_handle* h, const cx<T>* x, cx<T>* y, int K, int epilogue, hipSt
     a.ldp = (int)N;
     a.nrhs = K;
     a.kb = kb;
+    a.active = nullptr;
+    a.sys0 = 0;
     const cx<T>* tq = (sizeof(T) == 8) ? (const cx<T>*)h->d_tq64.p : (const cx<T>*)h->d_tq32.p;
     int rc = celes::wx_launch<T>(a, h->L, h->opt.hankel == CELES_HANKEL_DIRECT ? 1 : 0, nchunk_eff, x, tq, y,
                                  epilogue, s);
@@ -1084,3 +1087,565 @@ int celes_near_field(celes_handle* h, int64_t npt, const double* pts, int add_in
 
 }  // extern "C"
 
+
+// ===========================================================================
+// batched solver: many problems and right-hand sides in one flat vector
+// ===========================================================================
+struct celes_batch {
+    std::vector<celes_handle*> probs;
+    celes_options opt;
+    int L = 0, nmax = 0, half = 0, nprob = 0, nsys = 0, m = 0;
+    int64_t total = 0;
+    std::vector<int64_t> elem_off;   // [nprob+1]
+    std::vector<int> sys0;           // [nprob+1]
+    std::vector<int> sys_prob;       // [nsys]
+    // mat-vec configuration (set by celes_batch_autotune or defaults)
+    int chunk_len = 256, kb32 = 1, kb64 = 1, persist_blocks = 2048;
+    // device buffers
+    DevBuf d_elem_off, d_half_off, d_n, d_nrhs, d_nchunk, d_part_off, d_tq32, d_tq64;
+    DevBuf d_args32, d_args64, d_item_off, d_nbx, d_nch, d_counter;
+    DevBuf d_xsd, d_part;
+    DevBuf d_bseg, d_blo, d_bhi, d_sblk;
+    DevBuf d_rhs64, d_x64, d_r64, d_t64, d_V, d_d32, d_rhs32, d_t32, d_partial;
+    DevBuf st_H, st_cs, st_sn, st_g, st_y, st_h1, st_h2, st_hn, st_bn, st_est, st_sc, st_act, st_en, st_used, st_it, d_k;
+    celes::SegInfo si{};
+    celes::GmresState st{};
+    int nseg_blocks = 0;
+    int64_t part_elems = 0;
+    hipStream_t stream = nullptr;
+    hipGraphExec_t graph32 = nullptr, graph64 = nullptr;
+    void* graph_V = nullptr;          // basis the captured graphs point to
+    std::string err;
+    ~celes_batch() {
+        if (graph32) hipGraphExecDestroy(graph32);
+        if (graph64) hipGraphExecDestroy(graph64);
+        if (stream) hipStreamDestroy(stream);
+    }
+};
+
+namespace {
+
+int bfail(celes_batch* b, int code, const std::string& msg) {
+    if (b) b->err = msg;
+    else g_create_error = msg;
+    return code;
+}
+
+template <typename T>
+bool upload(DevBuf& d, const std::vector<T>& v) {
+    if (!d.ensure(std::max<size_t>(1, v.size()) * sizeof(T))) return false;
+    return v.empty() || hipMemcpy(d.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice) == hipSuccess;
+}
+
+// (re)build the work items and WxArgs of both precisions for the current
+// chunk length / right-hand-side blocks
+int batch_configure(celes_batch* b) {
+    const int G = celes::wx_num_groups(b->L);
+    std::vector<int> nbx(b->nprob), nch(b->nprob), item32(b->nprob + 1, 0), item64(b->nprob + 1, 0);
+    std::vector<int64_t> part_off(b->nprob);
+    std::vector<celes::WxArgs<float>> a32(b->nprob);
+    std::vector<celes::WxArgs<double>> a64(b->nprob);
+    int64_t poff = 0;
+    for (int p = 0; p < b->nprob; ++p) {
+        celes_handle* h = b->probs[p];
+        const int K = b->sys0[p + 1] - b->sys0[p];
+        const int64_t N = h->N;
+        nbx[p] = (int)((N + celes::WX_BLOCK_SIZE - 1) / celes::WX_BLOCK_SIZE);
+        int64_t cl = std::max<int64_t>(celes::WX_TILE_SIZE, (int64_t)b->chunk_len);
+        cl = (cl + celes::WX_TILE_SIZE - 1) / celes::WX_TILE_SIZE * celes::WX_TILE_SIZE;
+        nch[p] = (int)((N + cl - 1) / cl);
+        part_off[p] = poff;
+        poff += (int64_t)nch[p] * K * b->nmax * N;
+        item32[p + 1] = item32[p] + nbx[p] * nch[p] * G * (K / b->kb32);
+        item64[p + 1] = item64[p] + nbx[p] * nch[p] * G * (K / b->kb64);
+        auto fill = [&](auto& a) {
+            a.px = h->d_px.as<double>();
+            a.py = h->d_py.as<double>();
+            a.pz = h->d_pz.as<double>();
+            a.lut.d_lo = h->lut_lo;
+            a.lut.inv_dr = 1.0 / h->lut_dr;
+            a.lut.n_int = (int)h->lut_n;
+            a.k = h->k;
+            a.n = (int)N;
+            a.chunk_len = (int)cl;
+            a.ldp = (int)N;
+            a.nrhs = K;
+            a.sys0 = b->sys0[p];
+            a.active = b->st_act.as<int>();
+        };
+        fill(a32[p]);
+        fill(a64[p]);
+        a32[p].lut.coef = h->d_lut32.as<cx<float>>();
+        a64[p].lut.coef = h->d_lut64.as<cx<double>>();
+        a32[p].kb = b->kb32;
+        a64[p].kb = b->kb64;
+    }
+    b->part_elems = poff;
+    // scratch: xsd sized for FP64 (also serves FP32), partial sums likewise
+    if (!b->d_xsd.ensure((size_t)b->total * sizeof(cx<double>)) ||
+        !b->d_part.ensure((size_t)std::max<int64_t>(1, poff) * sizeof(cx<double>)))
+        return bfail(b, CELES_E_OOM, "cannot allocate batch mat-vec scratch");
+    for (int p = 0; p < b->nprob; ++p) {
+        a32[p].xsd = (const cx<float>*)b->d_xsd.p + b->elem_off[p];
+        a64[p].xsd = (const cx<double>*)b->d_xsd.p + b->elem_off[p];
+        a32[p].part = (cx<float>*)b->d_part.p + part_off[p];
+        a64[p].part = (cx<double>*)b->d_part.p + part_off[p];
+    }
+    bool ok = upload(b->d_args32, a32) && upload(b->d_args64, a64) && upload(b->d_nbx, nbx) &&
+              upload(b->d_nch, nch) && upload(b->d_part_off, part_off) && b->d_item_off.ensure(2 * (b->nprob + 1) * 4);
+    if (!ok) return bfail(b, CELES_E_OOM, "batch upload failed");
+    hipMemcpy(b->d_item_off.p, item32.data(), (b->nprob + 1) * 4, hipMemcpyHostToDevice);
+    hipMemcpy((int*)b->d_item_off.p + (b->nprob + 1), item64.data(), (b->nprob + 1) * 4, hipMemcpyHostToDevice);
+    return CELES_OK;
+}
+
+celes::BatchGeom batch_geom(const celes_batch* b, bool fp64) {
+    celes::BatchGeom g;
+    g.elem_off = b->d_elem_off.as<int64_t>();
+    g.half_off = b->d_half_off.as<int64_t>();
+    g.n = b->d_n.as<int>();
+    g.nrhs = b->d_nrhs.as<int>();
+    g.nchunk = b->d_nch.as<int>();
+    g.part_off = b->d_part_off.as<int64_t>();
+    g.tq = (const void* const*)(fp64 ? b->d_tq64.p : b->d_tq32.p);
+    g.nprob = b->nprob;
+    g.half = b->half;
+    g.L = b->L;
+    g.host_elems = b->total;
+    return g;
+}
+
+// y = M x (epilogue) for every system; x = V + slot, y = Y + slot' (slots
+// from *kstep when kstep is given)
+template <typename T>
+int batch_matvec(celes_batch* b, const cx<T>* V, const int* kstep, int kin, cx<T>* Y, int kout, int epilogue,
+                 hipStream_t s) {
+    const bool f64 = sizeof(T) == 8;
+    celes::BatchGeom g = batch_geom(b, f64);
+    // partial-sum offsets are element offsets of cx<double>; the FP32 kernel uses the same element offsets
+    celes::bk_zero_int(b->d_counter.as<int>(), 1, s);
+    celes::bk_prep<T>(g, V, b->total, kstep, kin, (cx<T>*)b->d_xsd.p, s);
+    const int* item_off = (const int*)b->d_item_off.p + (f64 ? b->nprob + 1 : 0);
+    int rc = celes::wx_batch_run<T>(b->L, (const celes::WxArgs<T>*)(f64 ? b->d_args64.p : b->d_args32.p), item_off,
+                                    b->d_nbx.as<int>(), b->d_nch.as<int>(), b->nprob, b->d_counter.as<int>(),
+                                    b->persist_blocks, f64 ? b->kb64 : b->kb32,
+                                    b->opt.hankel == CELES_HANKEL_DIRECT ? 1 : 0, s);
+    if (rc != 0) return bfail(b, CELES_E_DEVICE, "batch mat-vec launch failed");
+    celes::bk_finish<T>(g, (const cx<T>*)b->d_part.p, V, b->total, kstep, kin, kout, Y, epilogue, s);
+    return CELES_OK;
+}
+
+template <typename T>
+void record_arnoldi_step(celes_batch* b, cx<T>* V, double tol, hipStream_t s) {
+    const int* k = b->d_k.as<int>();
+    const int ld = b->m + 1;
+    batch_matvec<T>(b, V, k, 0, V, 1, 1, s);                                  // V_{k+1} = M V_k
+    celes::bk_dots<T>(b->si, V, b->total, V, k, 1, 1, 0, b->st.active, b->d_partial.as<cx<double>>(), ld,
+                      b->st.h1, ld, s);                                       // h1 = V^H V_{k+1}
+    celes::bk_gemv<T>(b->si, V, b->total, b->st.h1, ld, k, 1, nullptr, b->st.active, V, 1, -1.0, s);
+    celes::bk_dots<T>(b->si, V, b->total, V, k, 1, 1, 0, b->st.active, b->d_partial.as<cx<double>>(), ld,
+                      b->st.h2, ld, s);                                       // second pass
+    celes::bk_gemv<T>(b->si, V, b->total, b->st.h2, ld, k, 1, nullptr, b->st.active, V, 1, -1.0, s);
+    celes::bk_dots<T>(b->si, V, b->total, V, k, 0, 1, 1, b->st.active, b->d_partial.as<cx<double>>(), ld,
+                      b->st.hn, ld, s);                                       // ||V_{k+1}||^2
+    celes::bk_givens(b->st, k, tol, s);
+    celes::bk_scale<T>(b->si, V, b->total, k, 1, b->st.scale, s);
+    celes::bk_incr(b->d_k.as<int>(), s);
+}
+
+// GMRES(m) cycles on M d = rhs (precision T) for the enabled systems, from
+// d = 0, to relative tolerance tol (relative to each system's ||rhs||, taken
+// from st.bnorm).  Returns the number of cycles.
+template <typename T>
+int batch_gmres(celes_batch* b, const cx<T>* rhs, cx<T>* d, cx<T>* tmp, double tol, int max_cycles, bool use_graph,
+                int* rc_out) {
+    hipStream_t s = b->stream;
+    cx<T>* V = (cx<T>*)b->d_V.p;
+    hipGraphExec_t& graph = sizeof(T) == 8 ? b->graph64 : b->graph32;
+    const int nsys = b->nsys, m = b->m;
+    *rc_out = CELES_OK;
+    celes::bk_zero<T>(d, b->total, s);
+    int cycle = 0;
+    std::vector<int> act(nsys);
+    for (; cycle < max_cycles; ++cycle) {
+        // V_0 = rhs - M d  (d = 0 on the first cycle), beta = ||V_0||, V_0 /= beta
+        if (cycle == 0) {
+            celes::bk_copy_scaled<T>(b->si, rhs, V, nullptr, s);
+        } else {
+            if ((*rc_out = batch_matvec<T>(b, d, nullptr, 0, tmp, 0, 1, s)) != CELES_OK) return cycle;
+            celes::bk_sub<T>(rhs, tmp, V, b->total, s);
+        }
+        celes::bk_dots<T>(b->si, nullptr, b->total, V, nullptr, 0, 0, 1, nullptr, b->d_partial.as<cx<double>>(),
+                          m + 1, b->st.hn, m + 1, s);
+        celes::bk_cycle_start(b->st, tol, s);
+        celes::bk_copy_scaled<T>(b->si, V, V, b->st.scale, s);
+        celes::bk_zero_int(b->d_k.as<int>(), 1, s);
+        for (int k = 0; k < m; ++k) {
+            if (use_graph) {
+                if (!graph) {
+                    hipGraph_t gr;
+                    hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+                    record_arnoldi_step<T>(b, V, tol, s);
+                    hipStreamEndCapture(s, &gr);
+                    if (hipGraphInstantiate(&graph, gr, nullptr, nullptr, 0) != hipSuccess) {
+                        graph = nullptr;
+                        use_graph = false;
+                    }
+                    hipGraphDestroy(gr);
+                }
+                if (graph) hipGraphLaunch(graph, s);
+                else record_arnoldi_step<T>(b, V, tol, s);
+            } else {
+                record_arnoldi_step<T>(b, V, tol, s);
+            }
+            if ((k & 7) == 7 || k == m - 1) {
+                hipMemcpyAsync(act.data(), b->st.active, nsys * sizeof(int), hipMemcpyDeviceToHost, s);
+                hipStreamSynchronize(s);
+                bool any = false;
+                for (int v : act) any = any || v;
+                if (!any) break;
+            }
+        }
+        // d += V y over each system's used steps
+        celes::bk_backsolve(b->st, s);
+        celes::bk_gemv<T>(b->si, V, b->total, b->st.y, m + 1, nullptr, 0, b->st.used, nullptr, d, 0, 1.0, s);
+        std::vector<double> est(nsys);
+        std::vector<int> en(nsys);
+        hipMemcpyAsync(est.data(), b->st.est, nsys * 8, hipMemcpyDeviceToHost, s);
+        hipMemcpyAsync(en.data(), b->st.enabled, nsys * 4, hipMemcpyDeviceToHost, s);
+        hipStreamSynchronize(s);
+        double worst = 0;
+        for (int i = 0; i < nsys; ++i)
+            if (en[i]) worst = std::max(worst, est[i]);
+        if (!(worst > tol)) {
+            ++cycle;
+            break;
+        }
+    }
+    return cycle;
+}
+
+}  // namespace
+
+extern "C" {
+
+int celes_batch_create(celes_batch** out, int nprob, celes_handle* const* probs, const celes_options* opt) {
+    if (!out) return bfail(nullptr, CELES_E_ARG, "null batch pointer");
+    *out = nullptr;
+    if (nprob < 1 || !probs) return bfail(nullptr, CELES_E_ARG, "empty batch");
+    std::unique_ptr<celes_batch> b(new celes_batch());
+    if (opt) b->opt = *opt;
+    else celes_default_options(&b->opt);
+    b->nprob = nprob;
+    b->probs.assign(probs, probs + nprob);
+    b->L = probs[0]->L;
+    b->nmax = probs[0]->nmax;
+    b->half = probs[0]->half;
+    b->m = std::max(1, b->opt.restart);
+    b->elem_off.assign(nprob + 1, 0);
+    b->sys0.assign(nprob + 1, 0);
+    for (int p = 0; p < nprob; ++p) {
+        celes_handle* h = probs[p];
+        if (!h || h->L != b->L) return bfail(nullptr, CELES_E_ARG, "all problems of a batch need the same lmax");
+        if (h->K < 1) return bfail(nullptr, CELES_E_STATE, "problem without incident field");
+        b->elem_off[p + 1] = b->elem_off[p] + (int64_t)h->K * h->N * h->nmax;
+        b->sys0[p + 1] = b->sys0[p] + h->K;
+        for (int k = 0; k < h->K; ++k) b->sys_prob.push_back(p);
+    }
+    b->nsys = b->sys0[nprob];
+    b->total = b->elem_off[nprob];
+    if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess)
+        return bfail(nullptr, CELES_E_DEVICE, "stream creation failed");
+    // per-problem descriptors
+    std::vector<int64_t> half_off(nprob + 1);
+    std::vector<int> n(nprob), nrhs(nprob);
+    std::vector<const void*> tq32(nprob), tq64(nprob);
+    for (int p = 0; p <= nprob; ++p) half_off[p] = b->elem_off[p] / 2;
+    for (int p = 0; p < nprob; ++p) {
+        n[p] = (int)probs[p]->N;
+        nrhs[p] = probs[p]->K;
+        tq32[p] = probs[p]->d_tq32.p;
+        tq64[p] = probs[p]->d_tq64.p;
+    }
+    // right-hand-side blocks that divide every problem's K
+    auto kb_for = [&](int mx) {
+        for (int kb = mx; kb > 1; kb /= 2) {
+            bool ok = true;
+            for (int p = 0; p < nprob; ++p) ok = ok && (nrhs[p] % kb == 0);
+            if (ok) return kb;
+        }
+        return 1;
+    };
+    b->kb32 = kb_for(celes::wx_max_kb<float>(b->L));
+    b->kb64 = kb_for(celes::wx_max_kb<double>(b->L));
+    // segmented-reduction blocks: slices of at most 8192 elements per system
+    const int64_t SLICE = 8192;
+    std::vector<int> bseg, sblk(b->nsys + 1, 0);
+    std::vector<int64_t> blo, bhi;
+    int64_t maxblk = 0;
+    for (int sy = 0; sy < b->nsys; ++sy) {
+        const int p = b->sys_prob[sy];
+        const int64_t len = probs[p]->N * b->nmax;
+        const int64_t base = b->elem_off[p] + (int64_t)(sy - b->sys0[p]) * len;
+        sblk[sy] = (int)bseg.size();
+        for (int64_t o = 0; o < len; o += SLICE) {
+            bseg.push_back(sy);
+            blo.push_back(base + o);
+            bhi.push_back(base + std::min(len, o + SLICE));
+            maxblk = std::max(maxblk, std::min(len, o + SLICE) - o);
+        }
+    }
+    sblk[b->nsys] = (int)bseg.size();
+    const int nsys = b->nsys, m = b->m;
+    const size_t tot = (size_t)b->total;
+    bool ok = upload(b->d_elem_off, b->elem_off) && upload(b->d_half_off, half_off) && upload(b->d_n, n) &&
+              upload(b->d_nrhs, nrhs) && upload(b->d_tq32, tq32) && upload(b->d_tq64, tq64) &&
+              upload(b->d_bseg, bseg) && upload(b->d_blo, blo) && upload(b->d_bhi, bhi) && upload(b->d_sblk, sblk) &&
+              b->d_counter.ensure(64) && b->d_k.ensure(64) &&
+              b->d_rhs64.ensure(tot * 16) && b->d_x64.ensure(tot * 16) && b->d_r64.ensure(tot * 16) &&
+              b->d_t64.ensure(tot * 16) &&
+              b->d_partial.ensure((size_t)bseg.size() * (m + 1) * sizeof(cx<double>)) &&
+              b->st_H.ensure((size_t)nsys * (m + 1) * m * 16) && b->st_cs.ensure((size_t)nsys * m * 16) &&
+              b->st_sn.ensure((size_t)nsys * m * 16) && b->st_g.ensure((size_t)nsys * (m + 1) * 16) &&
+              b->st_y.ensure((size_t)nsys * (m + 1) * 16) && b->st_h1.ensure((size_t)nsys * (m + 1) * 16) &&
+              b->st_h2.ensure((size_t)nsys * (m + 1) * 16) && b->st_hn.ensure((size_t)nsys * (m + 1) * 16) &&
+              b->st_bn.ensure(nsys * 8) && b->st_est.ensure(nsys * 8) && b->st_sc.ensure(nsys * 8) &&
+              b->st_act.ensure(nsys * 4) && b->st_en.ensure(nsys * 4) && b->st_used.ensure(nsys * 4) &&
+              b->st_it.ensure(nsys * 4);
+    if (!ok) return bfail(nullptr, CELES_E_OOM, "batch allocation failed");
+    b->si = {nsys, (int)bseg.size(), maxblk, b->d_bseg.as<int>(), b->d_blo.as<int64_t>(), b->d_bhi.as<int64_t>(),
+             b->d_sblk.as<int>()};
+    b->st = {nsys, m, b->st_H.as<cx<double>>(), b->st_cs.as<cx<double>>(), b->st_sn.as<cx<double>>(),
+             b->st_g.as<cx<double>>(), b->st_y.as<cx<double>>(), b->st_h1.as<cx<double>>(),
+             b->st_h2.as<cx<double>>(), b->st_hn.as<cx<double>>(), b->st_bn.as<double>(), b->st_est.as<double>(),
+             b->st_sc.as<double>(), b->st_act.as<int>(), b->st_en.as<int>(), b->st_used.as<int>(),
+             b->st_it.as<int>()};
+    std::vector<int> ones(nsys, 1);
+    upload(b->st_act, ones);
+    int rc = batch_configure(b.get());
+    if (rc != CELES_OK) {
+        g_create_error = b->err;
+        return rc;
+    }
+    *out = b.release();
+    return CELES_OK;
+}
+
+void celes_batch_destroy(celes_batch* b) { delete b; }
+
+int celes_batch_num_systems(const celes_batch* b) { return b ? b->nsys : 0; }
+
+const char* celes_batch_last_error(const celes_batch* b) { return b ? b->err.c_str() : g_create_error.c_str(); }
+
+int celes_batch_apply_M(celes_batch* b, int precision, const void* x_dev, void* y_dev, void* stream) {
+    if (!b || !x_dev || !y_dev) return bfail(b, CELES_E_ARG, "null argument");
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<int> ones(b->nsys, 1);
+    upload(b->st_act, ones);
+    if (precision == CELES_FP64) return batch_matvec<double>(b, (const cx<double>*)x_dev, nullptr, 0, (cx<double>*)y_dev, 0, 1, s);
+    if (precision == CELES_MIXED) return batch_matvec<float>(b, (const cx<float>*)x_dev, nullptr, 0, (cx<float>*)y_dev, 0, 1, s);
+    return bfail(b, CELES_E_ARG, "unknown precision");
+}
+
+int celes_batch_autotune(celes_batch* b, int precision, double* best_ms, int* best_chunk, int* best_kb) {
+    if (!b) return CELES_E_ARG;
+    const bool f64 = precision == CELES_FP64;
+    const int mxkb = f64 ? celes::wx_max_kb<double>(b->L) : celes::wx_max_kb<float>(b->L);
+    hipStream_t s = b->stream;
+    std::vector<int> ones(b->nsys, 1);
+    upload(b->st_act, ones);
+    double best = 1e300;
+    int bc = b->chunk_len, bk = f64 ? b->kb64 : b->kb32;
+    hipEvent_t e0, e1;
+    hipEventCreate(&e0);
+    hipEventCreate(&e1);
+    const int chunks[] = {64, 128, 256, 512, 1024};
+    for (int kb = 1; kb <= mxkb; kb *= 2) {
+        bool divides = true;
+        for (int p = 0; p < b->nprob; ++p) divides = divides && ((b->sys0[p + 1] - b->sys0[p]) % kb == 0);
+        if (!divides) continue;
+        for (int cl : chunks) {
+            b->chunk_len = cl;
+            if (f64) b->kb64 = kb;
+            else b->kb32 = kb;
+            if (batch_configure(b) != CELES_OK) continue;
+            auto run = [&]() {
+                if (f64) batch_matvec<double>(b, b->d_x64.as<cx<double>>(), nullptr, 0, b->d_t64.as<cx<double>>(), 0, 1, s);
+                else batch_matvec<float>(b, (cx<float>*)b->d_x64.p, nullptr, 0, (cx<float>*)b->d_t64.p, 0, 1, s);
+            };
+            run();
+            hipEventRecord(e0, s);
+            run();
+            run();
+            hipEventRecord(e1, s);
+            hipEventSynchronize(e1);
+            float ms = 0;
+            hipEventElapsedTime(&ms, e0, e1);
+            ms *= 0.5f;
+            if (ms < best) {
+                best = ms;
+                bc = cl;
+                bk = kb;
+            }
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    b->chunk_len = bc;
+    if (f64) b->kb64 = bk;
+    else b->kb32 = bk;
+    if (b->graph32) { hipGraphExecDestroy(b->graph32); b->graph32 = nullptr; }
+    if (b->graph64) { hipGraphExecDestroy(b->graph64); b->graph64 = nullptr; }
+    int rc = batch_configure(b);
+    if (best_ms) *best_ms = best;
+    if (best_chunk) *best_chunk = bc;
+    if (best_kb) *best_kb = bk;
+    return rc;
+}
+
+int celes_batch_solve(celes_batch* b, celes_solve_info* infos, celes_solve_info* summary) {
+    if (!b) return CELES_E_ARG;
+    hipStream_t s = b->stream;
+    const int nsys = b->nsys;
+    const int64_t tot = b->total;
+    auto t0 = std::chrono::steady_clock::now();
+    // rhs = T a_in and x0 = 0, system by system in the flat layout
+    std::vector<cx<double>> rhs(tot);
+    std::vector<double> bn(nsys, 0.0);
+    for (int p = 0; p < b->nprob; ++p) {
+        celes_handle* h = b->probs[p];
+        const int64_t n = h->N * h->nmax;
+        for (int k = 0; k < h->K; ++k) {
+            double acc = 0;
+            for (int64_t i = 0; i < h->N; ++i)
+                for (int tau = 0; tau < 2; ++tau)
+                    for (int c = 0; c < h->half; ++c) {
+                        int l = (int)std::floor(std::sqrt((double)(c + 1)));
+                        while (l * (l + 2) < c + 1) ++l;
+                        while ((l - 1) * (l + 1) >= c + 1) --l;
+                        const cplx q = h->tq[((size_t)i * 2 + tau) * h->L + (l - 1)];
+                        const cplx v = q * h->a_in[((size_t)k * h->N + i) * h->nmax + tau * h->half + c];
+                        rhs[b->elem_off[p] + k * n + i * h->nmax + tau * h->half + c] = {v.real(), v.imag()};
+                        acc += std::norm(v);
+                    }
+            bn[b->sys0[p] + k] = std::sqrt(acc);
+        }
+    }
+    if (hipMemcpy(b->d_rhs64.p, rhs.data(), tot * 16, hipMemcpyHostToDevice) != hipSuccess)
+        return bfail(b, CELES_E_DEVICE, "copy failed");
+    const bool mixed = b->opt.precision == CELES_MIXED;
+    const size_t vbytes = (size_t)(b->m + 1) * tot * (mixed ? 8 : 16);
+    if (!b->d_V.ensure(vbytes) || !b->d_d32.ensure(tot * 16) || !b->d_rhs32.ensure(tot * 16) ||
+        !b->d_t32.ensure(tot * 16))
+        return bfail(b, CELES_E_OOM, "cannot allocate the Krylov basis");
+    if (b->graph_V != b->d_V.p) {
+        if (b->graph32) { hipGraphExecDestroy(b->graph32); b->graph32 = nullptr; }
+        if (b->graph64) { hipGraphExecDestroy(b->graph64); b->graph64 = nullptr; }
+        b->graph_V = b->d_V.p;
+    }
+    celes::bk_zero<double>(b->d_x64.as<cx<double>>(), tot, s);
+    std::vector<int> iters_total(nsys, 0);
+    std::vector<double> res(nsys, 1.0);
+    int refinements = 0, status = CELES_OK, matvecs = 0;
+    const double tol = b->opt.tol;
+    const bool use_graph = std::getenv("CELES_NO_GRAPH") == nullptr;
+    for (int it = 0; it <= b->opt.max_refinements; ++it) {
+        // FP64 residual r = rhs - M x, per-system norms
+        std::vector<int> ones(nsys, 1);
+        upload(b->st_act, ones);
+        int rc = batch_matvec<double>(b, b->d_x64.as<cx<double>>(), nullptr, 0, b->d_t64.as<cx<double>>(), 0, 1, s);
+        if (rc != CELES_OK) return rc;
+        ++matvecs;
+        celes::bk_sub<double>(b->d_rhs64.as<cx<double>>(), b->d_t64.as<cx<double>>(), b->d_r64.as<cx<double>>(), tot, s);
+        celes::bk_dots<double>(b->si, nullptr, tot, b->d_r64.as<cx<double>>(), nullptr, 0, 0, 1, nullptr,
+                               b->d_partial.as<cx<double>>(), b->m + 1, b->st.hn, b->m + 1, s);
+        std::vector<cx<double>> hn((size_t)nsys * (b->m + 1));
+        hipMemcpyAsync(hn.data(), b->st.hn, hn.size() * 16, hipMemcpyDeviceToHost, s);
+        hipStreamSynchronize(s);
+        std::vector<int> en(nsys);
+        std::vector<double> rn(nsys);
+        bool any = false;
+        double worst = 0;
+        for (int sy = 0; sy < nsys; ++sy) {
+            rn[sy] = std::sqrt(std::max(0.0, hn[(size_t)sy * (b->m + 1)].re));
+            res[sy] = bn[sy] > 0 ? rn[sy] / bn[sy] : 0.0;
+            en[sy] = res[sy] > tol ? 1 : 0;
+            any = any || en[sy];
+            worst = std::max(worst, res[sy]);
+        }
+        if (!any || it == b->opt.max_refinements) break;
+        upload(b->st_en, en);
+        upload(b->st_bn, rn);
+        // inner solve on M d = r, relative tolerance against ||r||
+        double inner = mixed ? std::max(b->opt.inner_tol, 0.5 * tol / worst) : 0.5 * tol / worst;
+        int cycles_left = std::max(1, b->opt.maxiter / b->m);
+        int cyc;
+        if (mixed) {
+            celes::bk_to32(b->d_r64.as<cx<double>>(), b->d_rhs32.as<cx<float>>(), tot, s);
+            cyc = batch_gmres<float>(b, b->d_rhs32.as<cx<float>>(), b->d_d32.as<cx<float>>(),
+                                     b->d_t32.as<cx<float>>(), inner, cycles_left, use_graph, &rc);
+            if (rc != CELES_OK) return rc;
+            celes::bk_acc32(b->d_d32.as<cx<float>>(), b->d_x64.as<cx<double>>(), tot, s);
+        } else {
+            cyc = batch_gmres<double>(b, b->d_r64.as<cx<double>>(), b->d_d32.as<cx<double>>(),
+                                      b->d_t32.as<cx<double>>(), inner, cycles_left, use_graph, &rc);
+            if (rc != CELES_OK) return rc;
+            celes::bk_add<double>(b->d_x64.as<cx<double>>(), b->d_d32.as<cx<double>>(), b->d_x64.as<cx<double>>(), tot, s);
+        }
+        (void)cyc;
+        ++refinements;
+        if (b->opt.verbose) std::fprintf(stderr, "batch refinement %d: worst residual %.3e\n", it, worst);
+    }
+    hipStreamSynchronize(s);
+    std::vector<int> its(nsys);
+    hipMemcpy(its.data(), b->st.iters, nsys * 4, hipMemcpyDeviceToHost);
+    // solutions back into the handles
+    std::vector<cx<double>> x(tot);
+    hipMemcpy(x.data(), b->d_x64.p, tot * 16, hipMemcpyDeviceToHost);
+    double worst = 0;
+    for (int p = 0; p < b->nprob; ++p) {
+        celes_handle* h = b->probs[p];
+        const int64_t n = (int64_t)h->K * h->N * h->nmax;
+        h->b.resize(n);
+        for (int64_t i = 0; i < n; ++i) h->b[i] = cplx(x[b->elem_off[p] + i].re, x[b->elem_off[p] + i].im);
+        h->have_solution = true;
+    }
+    auto t1 = std::chrono::steady_clock::now();
+    int total_its = 0;
+    for (int sy = 0; sy < nsys; ++sy) {
+        worst = std::max(worst, res[sy]);
+        total_its += its[sy];
+        if (!std::isfinite(res[sy])) status = CELES_E_BREAKDOWN;
+        else if (res[sy] > tol && status == CELES_OK) status = CELES_E_NOCONV;
+        if (infos) {
+            infos[sy] = celes_solve_info{};
+            infos[sy].status = std::isfinite(res[sy]) ? (res[sy] <= tol ? CELES_OK : CELES_E_NOCONV) : CELES_E_BREAKDOWN;
+            infos[sy].iterations = its[sy];
+            infos[sy].refinements = refinements;
+            infos[sy].rel_residual = res[sy];
+        }
+    }
+    if (summary) {
+        *summary = celes_solve_info{};
+        summary->status = status;
+        summary->iterations = total_its;
+        summary->refinements = refinements;
+        summary->matvecs = matvecs;
+        summary->rel_residual = worst;
+        summary->seconds = std::chrono::duration<double>(t1 - t0).count();
+    }
+    // reset per-system iteration counters for the next solve
+    std::vector<int> zeros(nsys, 0);
+    upload(b->st_it, zeros);
+    if (status == CELES_E_NOCONV) b->err = "batched solve did not reach the tolerance";
+    return status;
+}
+
+int celes_get_solution(const celes_handle* h, double* b_out) {
+    if (!h || !b_out) return CELES_E_ARG;
+    if (!h->have_solution) return CELES_E_STATE;
+    std::memcpy(b_out, h->b.data(), h->b.size() * sizeof(cplx));
+    return CELES_OK;
+}
+
+}  // extern "C"

@@ -202,14 +202,13 @@ __device__ __forceinline__ void pass_store(const WxArgs<T>& a, int chunk, int k0
 // per pair and shared by the passes of the group
 // ---------------------------------------------------------------------------
 template <typename T, int L, int KB, int HMODE, int MA, int MB>
-__device__ __forceinline__ void wx_group(const WxArgs<T>& a, cx<T>* tile, int k0) {
+__device__ __forceinline__ void wx_group(const WxArgs<T>& a, cx<T>* tile, int k0, int bx, int chunk) {
     constexpr int HALF = L * (L + 2);
     constexpr int P2 = 2 * L;
     constexpr bool HASB = MB >= 0;
     constexpr int MUMAX = HASB ? imax(mu_max(L, MA), mu_max(L, MB)) : mu_max(L, MA);
 
-    const int i = blockIdx.x * WX_BLOCK + threadIdx.x;
-    const int chunk = blockIdx.y;
+    const int i = bx * WX_BLOCK + threadIdx.x;
     const bool active = i < a.n;
     const double xi = active ? a.px[i] : 0.0;
     const double yi = active ? a.py[i] : 0.0;
@@ -323,8 +322,64 @@ __global__ __launch_bounds__(WX_BLOCK) void wx_fused_kernel(WxArgs<T> a) {
     const int k0 = (blockIdx.z / Groups<L>::n) * KB;
     sfor<0, Groups<L>::n>([&](auto G_) {
         constexpr int gi = decltype(G_)::value;
-        if (g == gi) wx_group<T, L, KB, HMODE, Groups<L>::a[gi], Groups<L>::b[gi]>(a, tile, k0);
+        if (g == gi) wx_group<T, L, KB, HMODE, Groups<L>::a[gi], Groups<L>::b[gi]>(a, tile, k0, blockIdx.x, blockIdx.y);
     });
+}
+
+// Persistent multi-problem variant: the grid is sized to the machine and
+// every block repeatedly claims the next work item (problem p, receiver
+// tile, source chunk, pass group, right-hand-side block) from a counter.
+// Items of problem p are numbered [item_off[p], item_off[p+1]); the counter
+// must be zero at launch.  Every block exits once the counter passes the
+// last item.
+template <typename T, int L, int KB, int HMODE>
+__global__ __launch_bounds__(WX_BLOCK) void wx_batch_kernel(const WxArgs<T>* __restrict__ args,
+                                                            const int* __restrict__ item_off,
+                                                            const int* __restrict__ nbx,
+                                                            const int* __restrict__ nchunk, int nprob,
+                                                            int* __restrict__ counter) {
+    constexpr int HALF = L * (L + 2);
+    constexpr int G = Groups<L>::n;
+    __shared__ cx<T> tile[WX_TILE * KB * 2 * HALF];
+    __shared__ int s_item;
+    const int total = item_off[nprob];
+    while (true) {
+        __syncthreads();
+        if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
+        __syncthreads();
+        const int item = s_item;
+        if (item >= total) break;
+        int p = 0;
+        while (item_off[p + 1] <= item) ++p;
+        const int local = item - item_off[p];
+        const int bxn = nbx[p], chn = nchunk[p];
+        const int bx = local % bxn;
+        const int chunk = (local / bxn) % chn;
+        const int z = local / (bxn * chn);
+        const int g = z % G, k0 = (z / G) * KB;
+        const WxArgs<T> a = args[p];
+        if (a.active) {
+            bool any = false;
+#pragma unroll
+            for (int kb = 0; kb < KB; ++kb) any = any || a.active[a.sys0 + k0 + kb] != 0;
+            if (!any) continue;
+        }
+        sfor<0, G>([&](auto G_) {
+            constexpr int gi = decltype(G_)::value;
+            if (g == gi) wx_group<T, L, KB, HMODE, Groups<L>::a[gi], Groups<L>::b[gi]>(a, tile, k0, bx, chunk);
+        });
+    }
+}
+
+template <typename T, int L, int KB>
+static void launch_batch_kb(const WxArgs<T>* args, const int* item_off, const int* nbx, const int* nchunk,
+                            int nprob, int* counter, int nblocks, int hmode, hipStream_t s) {
+    if (hmode == 0)
+        hipLaunchKernelGGL((wx_batch_kernel<T, L, KB, 0>), dim3(nblocks), dim3(WX_BLOCK), 0, s, args, item_off, nbx,
+                           nchunk, nprob, counter);
+    else
+        hipLaunchKernelGGL((wx_batch_kernel<T, L, KB, 1>), dim3(nblocks), dim3(WX_BLOCK), 0, s, args, item_off, nbx,
+                           nchunk, nprob, counter);
 }
 
 // right-hand-side block widths compiled per precision and cut-off
@@ -355,6 +410,22 @@ void wx_run_L(const WxArgs<T>& a, int hmode, int nchunk, hipStream_t s) {
     }
     launch_kb<T, L, 1>(a, hmode, nchunk, s);
 }
+
+template <typename T, int L>
+void wx_batch_run_L(const WxArgs<T>* args, const int* item_off, const int* nbx, const int* nchunk, int nprob,
+                    int* counter, int nblocks, int kb, int hmode, hipStream_t s) {
+    if constexpr (max_kb<T, L>() >= 4) {
+        if (kb == 4) return launch_batch_kb<T, L, 4>(args, item_off, nbx, nchunk, nprob, counter, nblocks, hmode, s);
+    }
+    if constexpr (max_kb<T, L>() >= 2) {
+        if (kb == 2) return launch_batch_kb<T, L, 2>(args, item_off, nbx, nchunk, nprob, counter, nblocks, hmode, s);
+    }
+    launch_batch_kb<T, L, 1>(args, item_off, nbx, nchunk, nprob, counter, nblocks, hmode, s);
+}
+template void wx_batch_run_L<double, CELES_WX_L>(const WxArgs<double>*, const int*, const int*, const int*, int, int*,
+                                                 int, int, int, hipStream_t);
+template void wx_batch_run_L<float, CELES_WX_L>(const WxArgs<float>*, const int*, const int*, const int*, int, int*,
+                                                int, int, int, hipStream_t);
 
 template <typename T, int L>
 int wx_max_kb_L() { return max_kb<T, L>(); }

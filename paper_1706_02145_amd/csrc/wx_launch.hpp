@@ -28,6 +28,8 @@ struct WxArgs {
     int ldp;             // leading dimension of part (>= n)
     int nrhs;            // right-hand sides in xsd / part
     int kb;              // right-hand sides per kernel block (1, 2 or 4; divides nrhs)
+    const int* active;   // batch only: per-system flags; items whose systems are all inactive are skipped
+    int sys0;            // batch only: system index of this problem's first right-hand side
 };
 
 // per-L pass launcher (defined in wx_kernels.hip, one translation unit per L)
@@ -37,6 +39,13 @@ void wx_run_L(const WxArgs<T>& a, int hmode, int nchunk, hipStream_t s);
 template <int L>
 int wx_num_groups_L();
 int wx_num_groups(int L);
+// persistent multi-problem launcher (one launch, all problems' work items)
+template <typename T, int L>
+void wx_batch_run_L(const WxArgs<T>* args, const int* item_off, const int* nbx, const int* nchunk, int nprob,
+                    int* counter, int nblocks, int kb, int hmode, hipStream_t s);
+template <typename T>
+int wx_batch_run(int L, const WxArgs<T>* args, const int* item_off, const int* nbx, const int* nchunk, int nprob,
+                 int* counter, int nblocks, int kb, int hmode, hipStream_t s);
 // largest compiled right-hand-side block of cut-off L
 template <typename T, int L>
 int wx_max_kb_L();

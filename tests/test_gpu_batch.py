@@ -1,0 +1,103 @@
+"""Batched solves (many problems and right-hand sides in one persistent
+launch per Arnoldi step) against individual solves and the oracle."""
+import os
+
+import numpy as np
+import pytest
+
+import paper_1706_02145_amd as P
+from celes_inputs import workload, random_coefficients
+from oracle.solve import master_matrix, solve_dense
+from oracle.incident import plane_wave_coefficients
+from tests.gpu_helpers import k_of, rel
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+ANGLES = {"slab300_l3": ([0.0, 0.3, 0.6, 1.0], [0.0, 0.5, 1.0, 2.0], [1, 2, 1, 2]),
+          "slab64_l3": ([0.0, 0.8], [0.0, 0.4], [1, 2]),
+          "cube8_l3": ([0.2, 0.2], [0.1, 0.1], [1, 2])}
+
+
+def _problems(names, **opts):
+    out = []
+    for nm in names:
+        w = workload(nm)
+        p = P.Problem(w.positions, w.radii, w.n_sphere, w.n0, w.wavelength, w.lmax, hankel=1, **opts)
+        b, a, pol = ANGLES[nm]
+        p.set_plane_waves(b, a, pol)
+        out.append((w, p))
+    return out
+
+
+def test_batch_apply_M_matches_single_problem_launches():
+    probs = _problems(["slab300_l3", "slab64_l3", "cube8_l3"])
+    print("[batch] apply_M 3 problems", flush=True)
+    bt = P.Batch([p for _, p in probs])
+    assert bt.num_systems == 8
+    xs = [random_coefficients(20 + i, p.num_rhs, w.N, w.nmax) for i, (w, p) in enumerate(probs)]
+    flat = np.concatenate([x.reshape(-1) for x in xs])
+    for prec, dt, tolr in ((P.CELES_FP64, torch.complex128, 1e-13), (P.CELES_MIXED, torch.complex64, 1e-5)):
+        xd = torch.from_numpy(flat).to("cuda", dt)
+        yd = torch.empty_like(xd)
+        bt.apply_M(xd, yd, prec)
+        torch.cuda.synchronize()
+        y = yd.cpu().numpy().astype(np.complex128)
+        off = 0
+        for (w, p), x in zip(probs, xs):
+            xi = torch.from_numpy(x).to("cuda", dt)
+            yi = torch.empty_like(xi)
+            p.apply_M(xi, yi, prec, K=p.num_rhs)
+            torch.cuda.synchronize()
+            ref = yi.cpu().numpy().astype(np.complex128).reshape(-1)
+            assert rel(y[off:off + ref.size], ref) <= tolr
+            off += ref.size
+
+
+@pytest.mark.parametrize("precision", [P.CELES_MIXED, P.CELES_FP64])
+def test_batch_solve_matches_individual_and_dense(precision):
+    names = ["slab300_l3", "slab64_l3", "cube8_l3"]
+    probs = _problems(names, tol=1e-10)
+    print(f"[batch] solve precision={precision}", flush=True)
+    bt = P.Batch([p for _, p in probs], tol=1e-9, precision=precision, inner_tol=1e-4, restart=60)
+    per, summ = bt.solve()
+    assert summ["status"] == 0 and summ["rel_residual"] <= 1e-9
+    assert all(i["rel_residual"] <= 1e-9 for i in per)
+    for w, p in probs:
+        bb = p.solution()
+        q = P.Problem(w.positions, w.radii, w.n_sphere, w.n0, w.wavelength, w.lmax, hankel=1, tol=1e-11)
+        bq, a, pol = ANGLES[w.name]
+        q.set_plane_waves(bq, a, pol)
+        ref, _ = q.solve()
+        assert rel(bb, ref) <= 1e-6
+    # smallest problem against the oracle's dense LU
+    w, p = probs[2]
+    M, W, t = master_matrix(w.positions, w.radii, w.n_sphere, w.n0, w.wavelength, w.lmax)
+    bq, a, pol = ANGLES[w.name]
+    for k in range(2):
+        ain = plane_wave_coefficients(w.positions, k_of(w), w.lmax, bq[k], a[k], pol[k])
+        ref = solve_dense(M, t * ain.reshape(-1))
+        assert rel(p.solution()[k].reshape(-1), ref) <= 1e-7
+
+
+def test_batch_graph_replay_equals_eager_and_autotune():
+    names = ["slab300_l3", "slab64_l3"]
+    probs = _problems(names)
+    bt = P.Batch([p for _, p in probs], tol=1e-8, precision=P.CELES_MIXED, restart=40)
+    _, s1 = bt.solve()
+    sol1 = [p.solution() for _, p in probs]
+    os.environ["CELES_NO_GRAPH"] = "1"
+    try:
+        _, s2 = bt.solve()
+    finally:
+        os.environ.pop("CELES_NO_GRAPH")
+    sol2 = [p.solution() for _, p in probs]
+    for a, b in zip(sol1, sol2):
+        assert rel(a, b) <= 1e-12      # identical kernel sequence: bitwise up to launch order
+    assert s1["iterations"] == s2["iterations"]
+    t = bt.autotune(P.CELES_MIXED)
+    print("[batch] autotune", t, flush=True)
+    assert t["ms"] > 0 and t["chunk_len"] in (64, 128, 256, 512, 1024) and t["kb"] in (1, 2, 4)
+    _, s3 = bt.solve()
+    for (w, p), a in zip(probs, sol1):
+        assert rel(p.solution(), a) <= 1e-6
