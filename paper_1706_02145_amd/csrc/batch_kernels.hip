@@ -98,6 +98,11 @@ __global__ void batch_finish(const BatchGeom g, const cx<T>* __restrict__ part, 
     y[b2] = y2;
 }
 
+__global__ void copy_int(const int* __restrict__ a, int* __restrict__ b, int n) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) b[t] = a[t];
+}
+
 __global__ void zero_int(int* p, int n) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t < n) p[t] = 0;
@@ -351,6 +356,9 @@ void bk_finish(const BatchGeom& g, const cx<T>* part, const cx<T>* V, int64_t to
 }
 void bk_zero_int(int* p, int n, hipStream_t s) {
     hipLaunchKernelGGL(zero_int, dim3((n + 255) / 256), dim3(256), 0, s, p, n);
+}
+void bk_copy_int(const int* a, int* b, int n, hipStream_t s) {
+    hipLaunchKernelGGL(copy_int, dim3((n + 255) / 256), dim3(256), 0, s, a, b, n);
 }
 void bk_incr(int* p, hipStream_t s) { hipLaunchKernelGGL(incr_int, dim3(1), dim3(64), 0, s, p); }
 

@@ -60,6 +60,7 @@ void bk_finish(const BatchGeom& g, const cx<T>* part, const cx<T>* V, int64_t to
                int kout, cx<T>* Y, int epilogue, hipStream_t s);
 void bk_zero_int(int* p, int n, hipStream_t s);
 void bk_incr(int* p, hipStream_t s);
+void bk_copy_int(const int* a, int* b, int n, hipStream_t s);
 template <typename T>
 void bk_dots(const SegInfo& si, const cx<T>* V, int64_t total, const cx<T>* W, const int* kstep, int kadd, int wadd,
              int selfdot, const int* active, cx<double>* partial, int ldp, cx<double>* out, int ldo, hipStream_t s);

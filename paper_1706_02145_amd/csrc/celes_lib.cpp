@@ -1272,6 +1272,9 @@ int batch_gmres(celes_batch* b, const cx<T>* rhs, cx<T>* d, cx<T>* tmp, double t
         if (cycle == 0) {
             celes::bk_copy_scaled<T>(b->si, rhs, V, nullptr, s);
         } else {
+            // every system is inactive at the end of a cycle: re-enable the
+            // participating ones so that the mat-vec computes their residuals
+            celes::bk_copy_int(b->st.enabled, b->st.active, nsys, s);
             if ((*rc_out = batch_matvec<T>(b, d, nullptr, 0, tmp, 0, 1, s)) != CELES_OK) return cycle;
             celes::bk_sub<T>(rhs, tmp, V, b->total, s);
         }
@@ -1544,6 +1547,7 @@ int celes_batch_solve(celes_batch* b, celes_solve_info* infos, celes_solve_info*
         b->graph_V = b->d_V.p;
     }
     celes::bk_zero<double>(b->d_x64.as<cx<double>>(), tot, s);
+    celes::bk_zero_int(b->st.iters, nsys, s);
     std::vector<int> iters_total(nsys, 0);
     std::vector<double> res(nsys, 1.0);
     int refinements = 0, status = CELES_OK, matvecs = 0;
@@ -1634,9 +1638,6 @@ int celes_batch_solve(celes_batch* b, celes_solve_info* infos, celes_solve_info*
         summary->rel_residual = worst;
         summary->seconds = std::chrono::duration<double>(t1 - t0).count();
     }
-    // reset per-system iteration counters for the next solve
-    std::vector<int> zeros(nsys, 0);
-    upload(b->st_it, zeros);
     if (status == CELES_E_NOCONV) b->err = "batched solve did not reach the tolerance";
     return status;
 }
