@@ -81,6 +81,7 @@ typedef struct celes_solve_info {
     double rel_residual;    /* final true relative residual, evaluated in FP64                 */
     double seconds;         /* wall time of the solve (excludes preconditioner set-up)         */
     double matvec_seconds;  /* part of `seconds` spent in the coupling mat-vec kernels         */
+    int x0_used;            /* 1 if the given initial guess was kept (its residual < ||rhs||)  */
 } celes_solve_info;
 
 /* Fill *opt with defaults: FP64, LUT, lut_dr = 1, tol = 1e-8, inner_tol = 1e-4,
@@ -143,7 +144,9 @@ int celes_build_preconditioner(celes_handle* h, double cuboid_edge);
 /* Solve the master equation M b = T a_in (Section 2.2, eqs. masterequation
  * and M) for every right-hand side by right-preconditioned restarted GMRES
  * (Section 3.2), W applied on the fly on the device.  x0 [K][N][nmax]
- * complex128 is the initial guess (NULL: zero).  b_out [K][N][nmax]
+ * complex128 is the initial guess (NULL: zero; the custom initial condition
+ * of Section 4.2): it is kept only if its relative residual is below 1,
+ * otherwise the solve starts from zero (info->x0_used tells which).  b_out [K][N][nmax]
  * receives the scattered-field coefficients (may be NULL: kept internally
  * for celes_cross_sections / celes_far_field).  info may be NULL.
  * Returns CELES_OK, CELES_E_NOCONV (b_out holds the best iterate),
@@ -255,6 +258,63 @@ int celes_batch_autotune(celes_batch* b, int precision, double* best_ms, int* be
  * summary (may be NULL) totals and wall time.  Returns CELES_OK,
  * CELES_E_NOCONV, CELES_E_BREAKDOWN, CELES_E_OOM or CELES_E_DEVICE. */
 int celes_batch_solve(celes_batch* b, celes_solve_info* infos, celes_solve_info* summary);
+
+/* ---------------------------------------------------------------------------
+ * Learned initial guess.  A small network predicts every sphere's scattered
+ * coefficients from its own and its 16 nearest neighbours' radii, relative
+ * positions and incident coefficients (all in the sphere's incident-phase
+ * frame, scaled by ||a_in^i||); the prediction is passed to celes_solve as
+ * x0 (the custom initial condition the paper's solver accepts, Section 4.2).
+ * Layers: in_pad -> 128 -> 128 -> 128 -> out_pad, SiLU, bf16 weights and
+ * activations with FP32 accumulation, FP32 master weights, Adam.  It is
+ * trained on coefficients the solver produced.  Intended for training sets
+ * and problems of one lmax; only the first right-hand side is used.
+ * ------------------------------------------------------------------------- */
+typedef struct celes_nn celes_nn;
+
+/* Create a network for cut-off lmax with weights drawn from `seed`
+ * (SplitMix64 counters, uniform in +-1/sqrt(fan_in)).  Errors: CELES_E_ARG,
+ * CELES_E_OOM. */
+int celes_nn_create(celes_nn** net, int lmax, uint64_t seed);
+void celes_nn_destroy(celes_nn* net);
+const char* celes_nn_last_error(const celes_nn* net);
+
+/* Feature width (real and padded), hidden width, output width (real, padded:
+ * 2 nmax reals), number of parameters.  Any output may be NULL. */
+int celes_nn_dims(const celes_nn* net, int* in_dim, int* in_pad, int* hidden, int* out_dim, int* out_pad,
+                  int64_t* nparam);
+
+/* FP32 master parameters, flat: for each layer W [in][out] row-major then b
+ * [out].  set also resets the optimiser state.  Errors: CELES_E_ARG. */
+int celes_nn_get_params(const celes_nn* net, float* params);
+int celes_nn_set_params(celes_nn* net, const float* params);
+
+/* Features X [N][in_pad] (as the network sees them, bf16 values) and, if the
+ * problem is solved, targets Y [N][out_pad] of a problem.  Either may be
+ * NULL.  Errors: CELES_E_ARG, CELES_E_STATE. */
+int celes_nn_features(celes_nn* net, celes_handle* h, float* X, float* Y);
+
+/* Mean-squared loss and its gradient (flat, like the parameters) on M rows
+ * of host data X [M][in_pad], Y [M][out_pad] (X rounded to bf16).  For
+ * gradient checks.  Errors: CELES_E_ARG, CELES_E_OOM. */
+int celes_nn_loss_grad(celes_nn* net, int64_t M, const float* X, const float* Y, double* loss, float* grad);
+
+/* Network output Z [M][out_pad] for host features X [M][in_pad]. */
+int celes_nn_forward(celes_nn* net, int64_t M, const float* X, float* Z);
+
+/* Append a solved problem's features and targets to the training set. */
+int celes_nn_add_training_problem(celes_nn* net, celes_handle* h);
+
+/* Train for `epochs` passes over the training set in shuffled minibatches
+ * (SplitMix64 from `seed`), Adam with a cosine learning-rate schedule from
+ * lr.  *loss receives the mean loss of the last epoch.  Errors:
+ * CELES_E_ARG, CELES_E_STATE (no data), CELES_E_OOM, CELES_E_DEVICE. */
+int celes_nn_train(celes_nn* net, int epochs, int batch, double lr, uint64_t seed, double* loss);
+
+/* Predicted scattered coefficients x0 [N][nmax] complex128 of a problem's
+ * first right-hand side (pass to celes_solve as x0).  Errors: CELES_E_ARG,
+ * CELES_E_STATE, CELES_E_OOM, CELES_E_DEVICE. */
+int celes_nn_predict(celes_nn* net, celes_handle* h, double* x0);
 
 #ifdef __cplusplus
 }

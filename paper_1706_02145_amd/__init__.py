@@ -12,7 +12,7 @@ import numpy as np
 from ._capi import (CELES_FP64, CELES_HANKEL_DIRECT, CELES_HANKEL_LUT, CELES_MIXED, ERRORS, Options,
                     SolveInfo, lib, LIB_PATH)
 
-__all__ = ["Problem", "Batch", "CelesError", "default_options", "mie_coefficients", "translation_tables", "version",
+__all__ = ["Problem", "Batch", "Network", "CelesError", "default_options", "mie_coefficients", "translation_tables", "version",
            "CELES_FP64", "CELES_MIXED", "CELES_HANKEL_LUT", "CELES_HANKEL_DIRECT", "LIB_PATH"]
 
 
@@ -255,3 +255,85 @@ class Batch:
             _bcheck(rc, self._b)
         per = [{f: getattr(i, f) for f, _ in SolveInfo._fields_} for i in infos]
         return per, {f: getattr(summ, f) for f, _ in SolveInfo._fields_}
+
+
+def _fptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+class Network:
+    """Learned initial guess (celes_nn_*): 16-neighbour features, three
+    hidden layers of 128, bf16 weights, FP32 accumulation, trained on the
+    solver's own output."""
+
+    def __init__(self, lmax, seed=0):
+        self._n = C.c_void_p()
+        rc = lib().celes_nn_create(C.byref(self._n), int(lmax), C.c_uint64(seed))
+        if rc != 0:
+            raise CelesError(rc, "celes_nn_create failed")
+        a = [C.c_int() for _ in range(5)]
+        npar = C.c_int64()
+        lib().celes_nn_dims(self._n, *[C.byref(x) for x in a], C.byref(npar))
+        self.in_dim, self.in_pad, self.hidden, self.out_dim, self.out_pad = [x.value for x in a]
+        self.nparam = npar.value
+        self.lmax = lmax
+
+    def _check(self, rc):
+        if rc != 0:
+            msg = lib().celes_nn_last_error(self._n)
+            raise CelesError(rc, msg.decode() if msg else "")
+
+    def close(self):
+        if getattr(self, "_n", None):
+            lib().celes_nn_destroy(self._n)
+            self._n = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def params(self):
+        p = np.zeros(self.nparam, dtype=np.float32)
+        self._check(lib().celes_nn_get_params(self._n, _fptr(p)))
+        return p
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        assert p.size == self.nparam
+        self._check(lib().celes_nn_set_params(self._n, _fptr(p)))
+
+    def features(self, problem, targets=True):
+        X = np.zeros((problem.N, self.in_pad), dtype=np.float32)
+        Y = np.zeros((problem.N, self.out_pad), dtype=np.float32) if targets else None
+        self._check(lib().celes_nn_features(self._n, problem._h, _fptr(X), _fptr(Y) if Y is not None else None))
+        return X, Y
+
+    def loss_grad(self, X, Y):
+        X = np.ascontiguousarray(X, dtype=np.float32)
+        Y = np.ascontiguousarray(Y, dtype=np.float32)
+        g = np.zeros(self.nparam, dtype=np.float32)
+        loss = C.c_double()
+        self._check(lib().celes_nn_loss_grad(self._n, X.shape[0], _fptr(X), _fptr(Y), C.byref(loss), _fptr(g)))
+        return loss.value, g
+
+    def forward(self, X):
+        X = np.ascontiguousarray(X, dtype=np.float32)
+        Z = np.zeros((X.shape[0], self.out_pad), dtype=np.float32)
+        self._check(lib().celes_nn_forward(self._n, X.shape[0], _fptr(X), _fptr(Z)))
+        return Z
+
+    def add_training_problem(self, problem):
+        self._check(lib().celes_nn_add_training_problem(self._n, problem._h))
+
+    def train(self, epochs, batch=1024, lr=1e-3, seed=0):
+        loss = C.c_double()
+        self._check(lib().celes_nn_train(self._n, int(epochs), int(batch), float(lr), C.c_uint64(seed),
+                                         C.byref(loss)))
+        return loss.value
+
+    def predict(self, problem):
+        x0 = np.zeros((problem.N, problem.nmax), dtype=np.complex128)
+        self._check(lib().celes_nn_predict(self._n, problem._h, _dptr(x0.view(np.float64))))
+        return x0

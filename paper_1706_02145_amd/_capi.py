@@ -25,7 +25,8 @@ class Options(C.Structure):
 
 class SolveInfo(C.Structure):
     _fields_ = [("status", C.c_int), ("iterations", C.c_int), ("refinements", C.c_int), ("matvecs", C.c_int),
-                ("rel_residual", C.c_double), ("seconds", C.c_double), ("matvec_seconds", C.c_double)]
+                ("rel_residual", C.c_double), ("seconds", C.c_double), ("matvec_seconds", C.c_double),
+                ("x0_used", C.c_int)]
 
 
 _dp = C.POINTER(C.c_double)
@@ -63,6 +64,19 @@ SIGNATURES = {
     "celes_batch_apply_M": (C.c_int, [_h, C.c_int, _vp, _vp, _vp]),
     "celes_batch_autotune": (C.c_int, [_h, C.c_int, _dp, _ip, _ip]),
     "celes_batch_solve": (C.c_int, [_h, C.POINTER(SolveInfo), C.POINTER(SolveInfo)]),
+    "celes_nn_create": (C.c_int, [C.POINTER(_h), C.c_int, C.c_uint64]),
+    "celes_nn_destroy": (None, [_h]),
+    "celes_nn_last_error": (C.c_char_p, [_h]),
+    "celes_nn_dims": (C.c_int, [_h, _ip, _ip, _ip, _ip, _ip, C.POINTER(C.c_int64)]),
+    "celes_nn_get_params": (C.c_int, [_h, C.POINTER(C.c_float)]),
+    "celes_nn_set_params": (C.c_int, [_h, C.POINTER(C.c_float)]),
+    "celes_nn_features": (C.c_int, [_h, _h, C.POINTER(C.c_float), C.POINTER(C.c_float)]),
+    "celes_nn_loss_grad": (C.c_int, [_h, C.c_int64, C.POINTER(C.c_float), C.POINTER(C.c_float), _dp,
+                                     C.POINTER(C.c_float)]),
+    "celes_nn_forward": (C.c_int, [_h, C.c_int64, C.POINTER(C.c_float), C.POINTER(C.c_float)]),
+    "celes_nn_add_training_problem": (C.c_int, [_h, _h]),
+    "celes_nn_train": (C.c_int, [_h, C.c_int, C.c_int, C.c_double, C.c_uint64, _dp]),
+    "celes_nn_predict": (C.c_int, [_h, _h, _dp]),
 }
 
 _lib = None

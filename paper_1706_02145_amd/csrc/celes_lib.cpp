@@ -17,6 +17,7 @@
 #include "../../include/celes.h"
 #include "device_common.hpp"
 #include "host_math.hpp"
+#include "internal.hpp"
 #include "precond.hpp"
 #include "vec_kernels.hpp"
 #include "wx_launch.hpp"
@@ -28,74 +29,9 @@ using celes::cx;
 namespace {
 
 thread_local std::string g_create_error;
-
-struct DevBuf {
-    void* p = nullptr;
-    size_t bytes = 0;
-    DevBuf() = default;
-    DevBuf(const DevBuf&) = delete;
-    DevBuf& operator=(const DevBuf&) = delete;
-    ~DevBuf() { release(); }
-    void release() {
-        if (p) hipFree(p);
-        p = nullptr;
-        bytes = 0;
-    }
-    bool ensure(size_t b) {
-        if (b <= bytes && p) return true;
-        release();
-        if (hipMalloc(&p, b) != hipSuccess) {
-            p = nullptr;
-            return false;
-        }
-        bytes = b;
-        return true;
-    }
-    template <typename T>
-    T* as() const { return static_cast<T*>(p); }
-};
-
-struct Err {
-    int code;
-    std::string msg;
-};
+using celes::DevBuf;
 
 }  // namespace
-
-struct celes_handle {
-    celes_options opt;
-    int64_t N = 0;
-    int L = 0, nmax = 0, half = 0;
-    double n0 = 1, wavelength = 0, k = 0;
-    std::vector<double> pos;     // [N][3]
-    std::vector<double> radius;  // [N]
-    std::vector<cplx> nsph;      // [N]
-    std::vector<cplx> tq;        // [N][2][L]
-    // Hankel table
-    double lut_lo = 0, lut_dr = 1;
-    int64_t lut_n = 0;
-    // device data
-    DevBuf d_px, d_py, d_pz, d_tq64, d_tq32, d_lut64, d_lut32;
-    DevBuf d_xsd, d_part;        // mat-vec scratch
-    // incident field / solution (host, canonical layout [K][N][nmax])
-    int K = 0;
-    std::vector<cplx> a_in;
-    // incident description (for the near field): plane waves or one Gaussian beam
-    bool gaussian = false;
-    std::vector<double> pw_beta, pw_alpha;
-    std::vector<int> pw_pol;
-    std::vector<cplx> pw_E0;
-    double g_waist = 0, g_focus[3] = {0, 0, 0}, g_alpha = 0;
-    cplx g_E0 = 1.0;
-    std::vector<cplx> b;
-    bool have_solution = false;
-    // solver scratch
-    DevBuf d_V, d_w, d_z, d_r, d_x, d_rhs, d_h, d_partial, d_V32, d_w32, d_z32, d_r32, d_x32;
-    // preconditioner
-    std::unique_ptr<celes::BlockPrecond> pre;
-    int target_blocks = 0;       // mat-vec work split (0: default); set by the autotuner
-    std::string err;
-};
 
 namespace {
 
@@ -796,6 +732,19 @@ int celes_solve(celes_handle* h, const double* x0, double* b_out, celes_solve_in
         HIPCHK(h, hipMemcpy(drhs, rhs.data(), n * sizeof(cx<double>), hipMemcpyHostToDevice));
         HIPCHK(h, hipMemcpy(dx, x.data(), n * sizeof(cx<double>), hipMemcpyHostToDevice));
         double final_res = 0;
+        if (x0 && rn > 0) {
+            // an initial guess is only used if it beats x0 = 0 (residual below ||rhs||)
+            double mv = 0;
+            int rc0 = CELES_OK;
+            const double r0 = residual64(h, drhs, dx, h->d_r.as<cx<double>>(), s, &rc0, &mv) / rn;
+            inf.matvecs++;
+            if (rc0 != CELES_OK) return rc0;
+            if (!(r0 < 1.0)) {
+                HIPCHK(h, hipMemset(dx, 0, n * sizeof(cx<double>)));
+            } else {
+                inf.x0_used = 1;
+            }
+        }
         if (rn == 0) {
             HIPCHK(h, hipMemset(dx, 0, n * sizeof(cx<double>)));
         } else if (!mixed) {
