@@ -101,6 +101,131 @@ def measured_traffic(N, L, hankel):
     return t["bytes_per_launch"]
 
 
+def _realisation(args):
+    seed, n = args
+    from celes_inputs import workload
+    w = workload("slab5000_l3", seed=seed, n=n)
+    return w.positions, w.radii
+
+
+def batched_mode(a):
+    """Batched workload: one 10,000-sphere slab (lmax 3) with 64 right-hand
+    sides (32 polar angles 0..60 deg x TE/TM) plus 32 disorder realisations
+    of uneven N in [500, 5000] (2 right-hand sides each, normal incidence),
+    all advanced together by the batched solver (complex64 inner GMRES, FP64
+    refinement, autotuned mat-vec work split)."""
+    import numpy as np
+    import torch
+    import paper_1706_02145_amd as P
+    from celes_inputs import workload
+    from concurrent.futures import ProcessPoolExecutor
+    t0 = time.perf_counter()
+    w = workload("slab10000_l3")
+    rng = np.random.Generator(np.random.PCG64(40))
+    sizes = [int(v) for v in rng.integers(500, 5001, size=a.realisations)]
+    with ProcessPoolExecutor(min(16, os.cpu_count() or 1)) as ex:
+        reals = list(ex.map(_realisation, [(4001 + r, n) for r, n in enumerate(sizes)]))
+    t_gen = time.perf_counter() - t0
+    probs = []
+    big = P.Problem(w.positions, w.radii, w.n_sphere, w.n0, w.wavelength, 3, hankel=P.CELES_HANKEL_LUT)
+    betas = np.repeat(np.arange(32) * (np.pi / 3) / 31, 2)
+    big.set_plane_waves(betas, np.zeros(64), np.tile([1, 2], 32))
+    probs.append(big)
+    for pos, rad in reals:
+        q = P.Problem(pos, rad, 1.52, 1.0, 550.0, 3, hankel=P.CELES_HANKEL_LUT)
+        q.set_plane_waves([0.0, 0.0], [0.0, 0.0], [1, 2])
+        probs.append(q)
+    updates = sum(q.N * (q.N - 1) * q.nmax ** 2 * q.num_rhs for q in probs)
+    bt = P.Batch(probs, precision=P.CELES_MIXED, tol=a.batch_tol, inner_tol=1e-3, restart=60, maxiter=3000)
+    tune = bt.autotune(P.CELES_MIXED)
+    # one batched M x in complex64 over every system (HIP events on the caller's stream)
+    n_total = sum(q.N * q.nmax * q.num_rhs for q in probs)
+    x = torch.randn(n_total, dtype=torch.complex64, device="cuda")
+    y = torch.empty_like(x)
+    bt.apply_M(x, y, P.CELES_MIXED)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(3):
+        bt.apply_M(x, y, P.CELES_MIXED)
+    ev1.record()
+    torch.cuda.synchronize()
+    mv_ms = ev0.elapsed_time(ev1) / 3
+    t1 = time.perf_counter()
+    per, summ = bt.solve(check=False)
+    t_solve = time.perf_counter() - t1
+    its = [i["iterations"] for i in per]
+    print(json.dumps({
+        "metric": "batched pair-multipole updates/s of W·b (complex64) and batched time to residual",
+        "value": updates / (mv_ms * 1e-3), "unit": "updates/s", "n_gpus": 1, "dtype": "f32 (FP64 refinement)",
+        "data": "synthetic",
+        "config": {"workload": f"slab10000_l3 (N={w.N}, 64 RHS: 32 polar angles 0-60 deg x TE/TM) + "
+                               f"{a.realisations} realisations N in [500,5000] x 2 RHS, lmax 3, LUT 1 nm",
+                   "realisation_sizes": sizes},
+        "systems": bt.num_systems, "updates_per_batched_matvec": updates, "batched_matvec_ms": mv_ms,
+        "autotune": tune, "solve_seconds": t_solve, "solve_status": summ["status"],
+        "worst_rel_residual": summ["rel_residual"], "tol": a.batch_tol,
+        "iterations_max": max(its), "iterations_mean": float(np.mean(its)), "refinements": summ["refinements"],
+        "geometry_seconds": t_gen}))
+
+
+def warmstart_mode(a):
+    """Learned initial guess: train on solver output of several slabs
+    (lmax 3, N = a.train_n each), evaluate on a larger unseen slab: GMRES
+    iterations and time to residual 1e-6 from x0 = 0, x0 = T a_in and the
+    network's prediction."""
+    import numpy as np
+    import torch
+    import paper_1706_02145_amd as P
+    from celes_inputs import workload
+    from concurrent.futures import ProcessPoolExecutor
+    net = P.Network(3, seed=11)
+    with ProcessPoolExecutor(min(16, os.cpu_count() or 1)) as ex:
+        geos = list(ex.map(_realisation, [(5001 + s, a.train_n) for s in range(a.train_slabs)]))
+    t0 = time.perf_counter()
+    for pos, rad in geos:
+        q = P.Problem(pos, rad, 1.52, 1.0, 550.0, 3, tol=1e-6, hankel=P.CELES_HANKEL_LUT)
+        q.set_plane_waves([0.0], [0.0], [2])
+        q.solve()
+        net.add_training_problem(q)
+        q.close()
+    t_data = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    loss = net.train(epochs=a.epochs, batch=2048, lr=2e-3, seed=3)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    pos, rad = _realisation((5000, a.eval_n))
+    p = P.Problem(pos, rad, 1.52, 1.0, 550.0, 3, tol=1e-6, hankel=P.CELES_HANKEL_LUT, restart=100, maxiter=4000)
+    p.set_plane_waves([0.0], [0.0], [2])
+    a_in = p.incident()
+    # single-scattering guess T a_in (per-sphere Mie coefficients from the library)
+    tq = np.stack([P.mie_coefficients(3, 2 * np.pi / 550.0 * r, 1.52) for r in rad])   # [N][2][L]
+    ls = [l for t in (0, 1) for l in range(1, 4) for m in range(-l, l + 1)]
+    ts = [t for t in (0, 1) for l in range(1, 4) for m in range(-l, l + 1)]
+    tvec = tq[:, ts, [l - 1 for l in ls]]
+    res = {}
+    for name, x0 in (("zero", None), ("T_a_in", (tvec * a_in[0])[None]), ("network", None)):
+        if name == "network":
+            t1 = time.perf_counter()
+            x0 = net.predict(p)[None]
+            t_pred = time.perf_counter() - t1
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, info = p.solve(x0=x0)
+        dt = time.perf_counter() - t1
+        res[name] = {"iterations": info["iterations"], "seconds": dt, "x0_used": info["x0_used"],
+                     "rel_residual": info["rel_residual"]}
+    res["network"]["predict_seconds"] = t_pred
+    print(json.dumps({
+        "metric": "GMRES iterations and time to residual 1e-6 with a learned initial guess",
+        "value": res["network"]["seconds"], "unit": "s", "higher_is_better": False, "n_gpus": 1,
+        "dtype": "f64 solve, bf16/f32 network", "data": "synthetic",
+        "config": {"workload": f"train {a.train_slabs} slabs N={a.train_n}, evaluate N={a.eval_n}, lmax 3, "
+                               f"vf 0.3, t=2 um, normal incidence x-pol, LUT 1 nm"},
+        "results": res, "training_loss": loss, "training_rows": a.train_slabs * a.train_n,
+        "data_generation_seconds": t_data, "training_seconds": t_train}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -114,11 +239,22 @@ def main():
     ap.add_argument("--cuboid-edge", type=float, default=1500.0)
     ap.add_argument("--hankel", choices=["lut", "direct"], default="lut")
     ap.add_argument("--profile", action="store_true", help="mat-vec launches only (for rocprofv3)")
+    ap.add_argument("--mode", choices=["solve", "batched", "warmstart"], default="solve")
+    ap.add_argument("--realisations", type=int, default=32)
+    ap.add_argument("--batch-tol", type=float, default=1e-6)
+    ap.add_argument("--train-slabs", type=int, default=40)
+    ap.add_argument("--train-n", type=int, default=2000)
+    ap.add_argument("--eval-n", type=int, default=20000)
+    ap.add_argument("--epochs", type=int, default=40)
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
               file=sys.stderr)
         sys.exit(2)
+    if a.mode == "batched":
+        return batched_mode(a)
+    if a.mode == "warmstart":
+        return warmstart_mode(a)
 
     import numpy as np
     import torch

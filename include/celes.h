@@ -228,7 +228,8 @@ typedef struct celes_batch celes_batch;
  * incident field set).  The handles stay owned by the caller and must
  * outlive the batch; opt (precision, tol, inner_tol, restart, maxiter,
  * max_refinements, hankel) applies to the whole batch (NULL: defaults).
- * Errors: CELES_E_ARG, CELES_E_STATE, CELES_E_OOM, CELES_E_DEVICE. */
+ * Batches are compiled for lmax <= 4.  Errors: CELES_E_ARG, CELES_E_STATE,
+ * CELES_E_UNSUPPORTED, CELES_E_OOM, CELES_E_DEVICE. */
 int celes_batch_create(celes_batch** b, int nprob, celes_handle* const* probs, const celes_options* opt);
 
 /* Release the batch (not the problems).  NULL is allowed. */

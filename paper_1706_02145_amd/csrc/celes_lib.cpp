@@ -1291,6 +1291,7 @@ int celes_batch_create(celes_batch** out, int nprob, celes_handle* const* probs,
     b->nprob = nprob;
     b->probs.assign(probs, probs + nprob);
     b->L = probs[0]->L;
+    if (b->L > 4) return bfail(nullptr, CELES_E_UNSUPPORTED, "batches are compiled for lmax <= 4");
     b->nmax = probs[0]->nmax;
     b->half = probs[0]->half;
     b->m = std::max(1, b->opt.restart);

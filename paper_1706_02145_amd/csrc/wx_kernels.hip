@@ -411,9 +411,14 @@ void wx_run_L(const WxArgs<T>& a, int hmode, int nchunk, hipStream_t s) {
     launch_kb<T, L, 1>(a, hmode, nchunk, s);
 }
 
+// batches are compiled for cut-offs up to 4 (the persistent kernel would
+// double the compile time of the larger cut-offs)
 template <typename T, int L>
 void wx_batch_run_L(const WxArgs<T>* args, const int* item_off, const int* nbx, const int* nchunk, int nprob,
                     int* counter, int nblocks, int kb, int hmode, hipStream_t s) {
+    if constexpr (L > 4) {
+        return;
+    } else {
     if constexpr (max_kb<T, L>() >= 4) {
         if (kb == 4) return launch_batch_kb<T, L, 4>(args, item_off, nbx, nchunk, nprob, counter, nblocks, hmode, s);
     }
@@ -421,6 +426,7 @@ void wx_batch_run_L(const WxArgs<T>* args, const int* item_off, const int* nbx, 
         if (kb == 2) return launch_batch_kb<T, L, 2>(args, item_off, nbx, nchunk, nprob, counter, nblocks, hmode, s);
     }
     launch_batch_kb<T, L, 1>(args, item_off, nbx, nchunk, nprob, counter, nblocks, hmode, s);
+    }
 }
 template void wx_batch_run_L<double, CELES_WX_L>(const WxArgs<double>*, const int*, const int*, const int*, int, int*,
                                                  int, int, int, hipStream_t);
