@@ -119,13 +119,18 @@ def batched_mode(a):
     import paper_1706_02145_amd as P
     from celes_inputs import workload
     from concurrent.futures import ProcessPoolExecutor
+    def log(msg):
+        print(f"[batched] {msg} ({time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
+
     t0 = time.perf_counter()
     w = workload("slab10000_l3")
+    log("10,000-sphere slab generated")
     rng = np.random.Generator(np.random.PCG64(40))
     sizes = [int(v) for v in rng.integers(500, 5001, size=a.realisations)]
     with ProcessPoolExecutor(min(16, os.cpu_count() or 1)) as ex:
         reals = list(ex.map(_realisation, [(4001 + r, n) for r, n in enumerate(sizes)]))
     t_gen = time.perf_counter() - t0
+    log(f"{len(reals)} realisations generated")
     probs = []
     big = P.Problem(w.positions, w.radii, w.n_sphere, w.n0, w.wavelength, 3, hankel=P.CELES_HANKEL_LUT)
     betas = np.repeat(np.arange(32) * (np.pi / 3) / 31, 2)
@@ -136,8 +141,11 @@ def batched_mode(a):
         q.set_plane_waves([0.0, 0.0], [0.0, 0.0], [1, 2])
         probs.append(q)
     updates = sum(q.N * (q.N - 1) * q.nmax ** 2 * q.num_rhs for q in probs)
-    bt = P.Batch(probs, precision=P.CELES_MIXED, tol=a.batch_tol, inner_tol=1e-3, restart=60, maxiter=3000)
+    log(f"{len(probs)} problems set up, {updates:.3e} updates per batched mat-vec")
+    bt = P.Batch(probs, precision=P.CELES_MIXED, tol=a.batch_tol, inner_tol=1e-3, restart=60,
+                 maxiter=a.batch_maxiter, max_refinements=4, verbose=1)
     tune = bt.autotune(P.CELES_MIXED)
+    log(f"autotuned: {tune}")
     # one batched M x in complex64 over every system (HIP events on the caller's stream)
     n_total = sum(q.N * q.nmax * q.num_rhs for q in probs)
     x = torch.randn(n_total, dtype=torch.complex64, device="cuda")
@@ -151,8 +159,10 @@ def batched_mode(a):
     ev1.record()
     torch.cuda.synchronize()
     mv_ms = ev0.elapsed_time(ev1) / 3
+    log(f"batched M x: {mv_ms:.1f} ms")
     t1 = time.perf_counter()
     per, summ = bt.solve(check=False)
+    log("solve done")
     t_solve = time.perf_counter() - t1
     its = [i["iterations"] for i in per]
     print(json.dumps({
@@ -179,22 +189,32 @@ def warmstart_mode(a):
     import paper_1706_02145_amd as P
     from celes_inputs import workload
     from concurrent.futures import ProcessPoolExecutor
+    tw = time.perf_counter()
+
+    def log(msg):
+        print(f"[warmstart] {msg} ({time.perf_counter() - tw:.1f} s)", file=sys.stderr, flush=True)
+
     net = P.Network(3, seed=11)
     with ProcessPoolExecutor(min(16, os.cpu_count() or 1)) as ex:
         geos = list(ex.map(_realisation, [(5001 + s, a.train_n) for s in range(a.train_slabs)]))
+    log(f"{len(geos)} training geometries")
     t0 = time.perf_counter()
-    for pos, rad in geos:
+    for gi, (pos, rad) in enumerate(geos):
         q = P.Problem(pos, rad, 1.52, 1.0, 550.0, 3, tol=1e-6, hankel=P.CELES_HANKEL_LUT)
         q.set_plane_waves([0.0], [0.0], [2])
         q.solve()
         net.add_training_problem(q)
         q.close()
+        if gi % 5 == 4:
+            log(f"solved {gi + 1} training slabs")
     t_data = time.perf_counter() - t0
     t0 = time.perf_counter()
     loss = net.train(epochs=a.epochs, batch=2048, lr=2e-3, seed=3)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
+    log(f"trained, loss {loss:.3e}")
     pos, rad = _realisation((5000, a.eval_n))
+    log("evaluation geometry generated")
     p = P.Problem(pos, rad, 1.52, 1.0, 550.0, 3, tol=1e-6, hankel=P.CELES_HANKEL_LUT, restart=100, maxiter=4000)
     p.set_plane_waves([0.0], [0.0], [2])
     a_in = p.incident()
@@ -215,6 +235,7 @@ def warmstart_mode(a):
         dt = time.perf_counter() - t1
         res[name] = {"iterations": info["iterations"], "seconds": dt, "x0_used": info["x0_used"],
                      "rel_residual": info["rel_residual"]}
+        log(f"x0 = {name}: {info['iterations']} iterations, {dt:.2f} s")
     res["network"]["predict_seconds"] = t_pred
     print(json.dumps({
         "metric": "GMRES iterations and time to residual 1e-6 with a learned initial guess",
@@ -242,6 +263,7 @@ def main():
     ap.add_argument("--mode", choices=["solve", "batched", "warmstart"], default="solve")
     ap.add_argument("--realisations", type=int, default=32)
     ap.add_argument("--batch-tol", type=float, default=1e-6)
+    ap.add_argument("--batch-maxiter", type=int, default=600)
     ap.add_argument("--train-slabs", type=int, default=40)
     ap.add_argument("--train-n", type=int, default=2000)
     ap.add_argument("--eval-n", type=int, default=20000)

@@ -1269,6 +1269,7 @@ int batch_gmres(celes_batch* b, const cx<T>* rhs, cx<T>* d, cx<T>* tmp, double t
         double worst = 0;
         for (int i = 0; i < nsys; ++i)
             if (en[i]) worst = std::max(worst, est[i]);
+        if (b->opt.verbose) std::fprintf(stderr, "batch cycle %d: worst inner estimate %.3e\n", cycle, worst);
         if (!(worst > tol)) {
             ++cycle;
             break;
@@ -1412,7 +1413,7 @@ int celes_batch_autotune(celes_batch* b, int precision, double* best_ms, int* be
     hipEvent_t e0, e1;
     hipEventCreate(&e0);
     hipEventCreate(&e1);
-    const int chunks[] = {64, 128, 256, 512, 1024};
+    const int chunks[] = {128, 256, 512, 1024};
     for (int kb = 1; kb <= mxkb; kb *= 2) {
         bool divides = true;
         for (int p = 0; p < b->nprob; ++p) divides = divides && ((b->sys0[p + 1] - b->sys0[p]) % kb == 0);
