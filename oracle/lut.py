@@ -12,6 +12,14 @@ library):
     n_int = ceil((d_max - d_lo) / dr) + 1,         d_max = |bounding-box diagonal of the centres|
     nodes d_k = d_lo + k dr, k = 0..n_int.
 Interval index q = floor((d - d_lo)/dr), local t = (d - d_lo)/dr - q.
+
+Two tables are defined here.  HankelLUT tabulates every order p = 0..2L, as
+the paper describes.  HankelLUT01 tabulates only h_0 and h_1 and obtains the
+higher orders from the three-term recurrence of the spherical Bessel family,
+    h_{p+1}(x) = (2p + 1)/x h_p(x) - h_{p-1}(x),   x = k d,
+which holds exactly for every solution of the spherical Bessel equation and
+is stable upward for h_p (the y_p part dominates); the library's lookup-table
+mode computes this second form.
 """
 import math
 
@@ -54,6 +62,29 @@ class HankelLUT:
         return h00 * v[q] + h10 * g[q] + h01 * v[q + 1] + h11 * g[q + 1]
 
 
+class HankelLUT01:
+    """Hermite-interpolated h_0(k d) and h_1(k d) on the grid above; orders
+    p >= 2 by the upward recurrence h_{p+1} = (2p+1)/x h_p - h_{p-1}."""
+
+    def __init__(self, k, pmax, d_lo, dr, n_int):
+        self.k, self.pmax = k, pmax
+        self.d_lo, self.dr, self.n_int = d_lo, dr, n_int
+        self.table = HankelLUT(k, 1, d_lo, dr, n_int)
+
+    def __call__(self, p, kd):
+        if p > self.pmax:
+            raise ValueError("order above the table's cut-off")
+        x = np.asarray(kd, dtype=np.float64)
+        h_prev, h = self.table(0, x), self.table(1, x)
+        if p == 0:
+            return h_prev
+        for q in range(1, p):
+            h_prev, h = h, (2 * q + 1) / x * h - h_prev
+        return h
+
+
 def lut_for(positions, radii, k, L, dr):
+    """The table the library's lookup-table mode evaluates (two tabulated
+    orders plus the recurrence)."""
     d_lo, n_int = lut_grid(positions, radii, dr)
-    return HankelLUT(k, 2 * L, d_lo, dr, n_int)
+    return HankelLUT01(k, 2 * L, d_lo, dr, n_int)

@@ -134,6 +134,28 @@ def test_lut_error_within_hermite_bound():
             assert np.all(np.abs(got - ex) <= 1.5 * bound + 1e-13 * np.abs(ex))
 
 
+def test_two_order_table_recurrence_keeps_relative_error():
+    # h_0, h_1 interpolated (bounded by the test above); the upward recurrence
+    # for p >= 2 follows the dominant y_p, so the relative error of h_p stays
+    # at the level of h_0 and h_1.  A wrong recurrence coefficient gives an
+    # O(1) error here.
+    from oracle.lut import HankelLUT01
+    k = 2 * math.pi / 550
+    pos = np.array([[0, 0, 0], [3000.0, 0, 0], [0, 2500.0, 900.0]])
+    radii = np.array([100.0, 100.0, 100.0])
+    for dr in (1.0, 5.0):
+        d_lo, n = lut_grid(pos, radii, dr)
+        lut = HankelLUT01(k, 8, d_lo, dr, n)
+        x = k * np.linspace(d_lo + 0.01, d_lo + (n - 0.01) * dr, 4001)
+        base = max(np.max(np.abs(lut(p, x) - sph_h1(p, x)) / np.abs(sph_h1(p, x))) for p in (0, 1))
+        assert base <= (1e-10 if dr == 1.0 else 1e-7)
+        for p in range(2, 9):
+            ex = sph_h1(p, x)
+            assert np.max(np.abs(lut(p, x) - ex) / np.abs(ex)) <= 2 * base + 1e-14
+        with pytest.raises(ValueError):
+            lut(9, x)
+
+
 def test_lut_matvec_close_to_exact():
     from oracle.lut import lut_for
     k = 2 * math.pi / 550
