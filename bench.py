@@ -51,7 +51,9 @@ def flops_per_pair(L, hankel_lut=True):
     total = 0
     for M0 in range(L + 1):
         f = 19                                             # geometry
-        f += (4 + 12 * (P + 1)) if hankel_lut else (4 + 6 + 5 * (P - 1))
+        # Hankel: table index + Horner for h_0, h_1 (24) + 1/(kd) (1), or
+        # sincos + 1/(kd) + h_0, h_1 (6); then the recurrence, 5 per order
+        f += (4 + 24 + 1 + 5 * (P - 1)) if hankel_lut else (4 + 6 + 5 * (P - 1))
         mumax = min(2 * L, L + M0)
         for mu in range(mumax + 1):
             if mu > 0:

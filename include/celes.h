@@ -52,8 +52,9 @@ extern "C" {
 #define CELES_MIXED 1           /* complex64 inner solve, FP64 residual/refinement  */
 
 /* spherical Hankel evaluation inside the mat-vec */
-#define CELES_HANKEL_LUT 0      /* cubic-Hermite lookup table at spacing lut_dr (Section 3.2.2) */
-#define CELES_HANKEL_DIRECT 1   /* upward three-term recurrence from h_0, h_1 per pair          */
+#define CELES_HANKEL_LUT 0      /* h_0, h_1 from a cubic-Hermite table at spacing lut_dr (Section
+                                 * 3.2.2), higher orders by the upward three-term recurrence   */
+#define CELES_HANKEL_DIRECT 1   /* h_0, h_1 from sin/cos per pair, then the same recurrence    */
 
 #define CELES_MAX_LMAX 6
 

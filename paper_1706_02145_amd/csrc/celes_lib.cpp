@@ -93,7 +93,9 @@ bool find_overlap(int64_t N, const double* pos, const double* rad, int64_t* a, i
 }
 
 // ---------------------------------------------------------------------------
-// Hankel lookup table: cubic Hermite per interval, Horner coefficients in t
+// Hankel lookup table: cubic Hermite per interval for h_0 and h_1, Horner
+// coefficients in t, [n_int][2][4]; the kernels build the higher orders
+// with the upward recurrence
 // ---------------------------------------------------------------------------
 void lut_geometry(const celes_handle* h, double dr, double* lo, int64_t* n) {
     double rmin = *std::min_element(h->radius.begin(), h->radius.end());
@@ -111,7 +113,7 @@ void lut_geometry(const celes_handle* h, double dr, double* lo, int64_t* n) {
 }
 
 int build_lut(celes_handle* h) {
-    const int P = 2 * h->L;
+    const int P = 1;   // highest tabulated order
     lut_geometry(h, h->opt.lut_dr, &h->lut_lo, &h->lut_n);
     h->lut_dr = h->opt.lut_dr;
     const int64_t nn = h->lut_n + 1;
@@ -126,15 +128,15 @@ int build_lut(celes_handle* h) {
             der[(size_t)q * (P + 1) + p] = h->k * h->lut_dr * dh[p];  // d/dt = dr * d/dd
         }
     }
-    std::vector<cx<double>> c64((size_t)h->lut_n * (P + 1) * 4);
+    std::vector<cx<double>> c64((size_t)h->lut_n * 2 * 4);
     std::vector<cx<float>> c32(c64.size());
     for (int64_t q = 0; q < h->lut_n; ++q)
-        for (int p = 0; p <= P; ++p) {
+        for (int p = 0; p <= 1; ++p) {
             cplx h0 = val[(size_t)q * (P + 1) + p], h1 = val[(size_t)(q + 1) * (P + 1) + p];
             cplx g0 = der[(size_t)q * (P + 1) + p], g1 = der[(size_t)(q + 1) * (P + 1) + p];
             cplx c[4] = {h0, g0, 3.0 * (h1 - h0) - 2.0 * g0 - g1, 2.0 * (h0 - h1) + g0 + g1};
             for (int t = 0; t < 4; ++t) {
-                size_t o = ((size_t)q * (P + 1) + p) * 4 + t;
+                size_t o = ((size_t)q * 2 + p) * 4 + t;
                 c64[o] = {c[t].real(), c[t].imag()};
                 c32[o] = {(float)c[t].real(), (float)c[t].imag()};
             }
@@ -168,7 +170,7 @@ int matvec(celes_handle* h, const cx<T>* x, cx<T>* y, int K, int epilogue, hipSt
     const int kb = pick_kb<T>(h->L, K);
     int64_t nbx = (N + celes::WX_BLOCK_SIZE - 1) / celes::WX_BLOCK_SIZE * celes::wx_num_groups(h->L) * (K / kb);
     const char* env = std::getenv("CELES_WX_TARGET_BLOCKS");
-    const int target = env ? std::max(1, std::atoi(env)) : (h->target_blocks > 0 ? h->target_blocks : 1024);
+    const int target = env ? std::max(1, std::atoi(env)) : (h->target_blocks > 0 ? h->target_blocks : 4096);
     int64_t nchunk = (target + nbx - 1) / nbx;
     nchunk = std::max<int64_t>(1, std::min<int64_t>(nchunk, (N + celes::WX_TILE_SIZE - 1) / celes::WX_TILE_SIZE));
     int64_t chunk_len = (N + nchunk - 1) / nchunk;
@@ -186,6 +188,7 @@ int matvec(celes_handle* h, const cx<T>* x, cx<T>* y, int K, int epilogue, hipSt
     a.lut.coef = (sizeof(T) == 8) ? (const cx<T>*)h->d_lut64.p : (const cx<T>*)h->d_lut32.p;
     a.lut.d_lo = h->lut_lo;
     a.lut.inv_dr = 1.0 / h->lut_dr;
+    a.lut.inv_k = 1.0 / h->k;
     a.lut.n_int = (int)h->lut_n;
     a.k = h->k;
     a.n = (int)N;
@@ -1113,6 +1116,7 @@ int batch_configure(celes_batch* b) {
             a.pz = h->d_pz.as<double>();
             a.lut.d_lo = h->lut_lo;
             a.lut.inv_dr = 1.0 / h->lut_dr;
+            a.lut.inv_k = 1.0 / h->k;
             a.lut.n_int = (int)h->lut_n;
             a.k = h->k;
             a.n = (int)N;

@@ -45,7 +45,7 @@ struct AsmArgs {
     const cx<double>* tq;       // [N][2][L]
     const double* a5;           // [L][2L+1][L][2L+1][2L+1]
     const double* b5;
-    const cx<double>* lut;      // [n_int][2L+1][4]
+    const cx<double>* lut;      // [n_int][2][4]: h_0, h_1 Horner coefficients
     double lut_lo, lut_inv_dr;
     int lut_n;
     double k;
@@ -60,10 +60,15 @@ __device__ inline void hankel_row(const AsmArgs& g, double d, cx<double>* h) {
         int q = (int)s;
         q = q < 0 ? 0 : (q >= g.lut_n ? g.lut_n - 1 : q);
         double t = s - q;
-        const cx<double>* c = g.lut + (size_t)q * (P + 1) * 4;
-        for (int p = 0; p <= P; ++p) {
+        const cx<double>* c = g.lut + (size_t)q * 8;
+        for (int p = 0; p <= 1; ++p) {
             h[p].re = ((c[4 * p + 3].re * t + c[4 * p + 2].re) * t + c[4 * p + 1].re) * t + c[4 * p].re;
             h[p].im = ((c[4 * p + 3].im * t + c[4 * p + 2].im) * t + c[4 * p + 1].im) * t + c[4 * p].im;
+        }
+        const double inv = 1.0 / (g.k * d);
+        for (int p = 1; p < P; ++p) {
+            double f = (2.0 * p + 1.0) * inv;
+            h[p + 1] = {f * h[p].re - h[p - 1].re, f * h[p].im - h[p - 1].im};
         }
     } else {
         double x = g.k * d, s, cc;

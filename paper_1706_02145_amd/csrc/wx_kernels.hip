@@ -82,18 +82,26 @@ __device__ __forceinline__ void hankel_direct(double kd, cx<T> (&h)[P + 1]) {
 }
 
 template <typename T, int P>
-__device__ __forceinline__ void hankel_lut(double d, const LutView<T>& lut, cx<T> (&h)[P + 1]) {
-    // cubic Hermite on [d_q, d_q + dr], coefficients in Horner order c0..c3 of t
+__device__ __forceinline__ void hankel_lut(double d, double inv_kd, const LutView<T>& lut, cx<T> (&h)[P + 1]) {
+    // h_0 and h_1: cubic Hermite on [d_q, d_q + dr], coefficients in Horner
+    // order c0..c3 of t (one 128-byte row per interval in FP64); higher
+    // orders by the upward recurrence, as in hankel_direct
     double s = (d - lut.d_lo) * lut.inv_dr;
     int q = (int)s;
     q = q < 0 ? 0 : (q >= lut.n_int ? lut.n_int - 1 : q);
     T t = (T)(s - (double)q);
-    const cx<T>* c = lut.coef + (size_t)q * (P + 1) * 4;
+    const cx<T>* c = lut.coef + (size_t)q * 8;
 #pragma unroll
-    for (int p = 0; p <= P; ++p) {
+    for (int p = 0; p <= (P < 1 ? P : 1); ++p) {
         cx<T> c0 = c[4 * p], c1 = c[4 * p + 1], c2 = c[4 * p + 2], c3 = c[4 * p + 3];
         h[p].re = fma(fma(fma(c3.re, t, c2.re), t, c1.re), t, c0.re);
         h[p].im = fma(fma(fma(c3.im, t, c2.im), t, c1.im), t, c0.im);
+    }
+    const T fi = (T)inv_kd;
+#pragma unroll
+    for (int p = 1; p < P; ++p) {
+        T f = (T)(2 * p + 1) * fi;
+        h[p + 1] = {f * h[p].re - h[p - 1].re, f * h[p].im - h[p - 1].im};
     }
 }
 
@@ -257,7 +265,7 @@ __device__ __forceinline__ void wx_group(const WxArgs<T>& a, cx<T>* tile, int k0
             // ---- radial functions ----
             cx<T> h[P2 + 1];
             if constexpr (HMODE == 0)
-                hankel_lut<T, P2>(r, a.lut, h);
+                hankel_lut<T, P2>(r, inv_r * a.lut.inv_k, a.lut, h);
             else
                 hankel_direct<T, P2>(a.k * r, h);
 
@@ -300,17 +308,20 @@ __device__ __forceinline__ void wx_group(const WxArgs<T>& a, cx<T>* tile, int k0
     if constexpr (HASB) pass_store<T, L, KB, MB>(a, chunk, k0, i, bP, bM, bPm, bMm);
 }
 
-// Pass groups per cut-off, heaviest first (blockIdx.z indexes the group).
-// Groups share one pair set-up; they are sized so that each stays within
-// 256 VGPRs in FP64 (two waves per SIMD).
+// Pass groups per cut-off, heaviest first (blockIdx.z indexes the group, so
+// the heaviest blocks are dispatched first).  Groups share one pair set-up;
+// each combines passes so that the groups carry about equal work and no more
+// accumulators than the |m| = 1 pass alone (FP64: within 256 VGPRs, two
+// waves per SIMD).  Per-pair work of pass M0 at L = 4, in flops: 3036, 5648,
+// 4428, 3120, 1816 for M0 = 0..4, hence {0,3}, {2,4}, {1}.
 template <int L>
 struct Groups;
 template <> struct Groups<1> { static constexpr int n = 1; static constexpr int a[1] = {0}; static constexpr int b[1] = {1}; };
-template <> struct Groups<2> { static constexpr int n = 2; static constexpr int a[2] = {1, 0}; static constexpr int b[2] = {-1, 2}; };
-template <> struct Groups<3> { static constexpr int n = 3; static constexpr int a[3] = {1, 2, 0}; static constexpr int b[3] = {-1, 3, -1}; };
-template <> struct Groups<4> { static constexpr int n = 4; static constexpr int a[4] = {1, 2, 0, 3}; static constexpr int b[4] = {-1, -1, -1, 4}; };
-template <> struct Groups<5> { static constexpr int n = 5; static constexpr int a[5] = {1, 2, 3, 0, 4}; static constexpr int b[5] = {-1, -1, -1, -1, 5}; };
-template <> struct Groups<6> { static constexpr int n = 6; static constexpr int a[6] = {1, 2, 3, 0, 4, 5}; static constexpr int b[6] = {-1, -1, -1, -1, -1, 6}; };
+template <> struct Groups<2> { static constexpr int n = 2; static constexpr int a[2] = {0, 1}; static constexpr int b[2] = {2, -1}; };
+template <> struct Groups<3> { static constexpr int n = 3; static constexpr int a[3] = {1, 0, 2}; static constexpr int b[3] = {-1, 3, -1}; };
+template <> struct Groups<4> { static constexpr int n = 3; static constexpr int a[3] = {2, 0, 1}; static constexpr int b[3] = {4, 3, -1}; };
+template <> struct Groups<5> { static constexpr int n = 4; static constexpr int a[4] = {3, 2, 1, 0}; static constexpr int b[4] = {4, 5, -1, -1}; };
+template <> struct Groups<6> { static constexpr int n = 4; static constexpr int a[4] = {3, 2, 0, 1}; static constexpr int b[4] = {5, 6, 4, -1}; };
 
 // blockIdx.z = g + G * kblock: pass group g, right-hand sides kblock*KB .. +KB
 template <typename T, int L, int KB, int HMODE>

@@ -7,9 +7,10 @@ namespace celes {
 
 template <typename T>
 struct LutView {
-    const cx<T>* coef;   // [n_int][2L+1][4] Horner coefficients in t
+    const cx<T>* coef;   // [n_int][2][4]: Horner coefficients in t of h_0 and h_1
     double d_lo;
     double inv_dr;
+    double inv_k;        // 1 / k (orders >= 2 come from the recurrence in 1/(k d))
     int n_int;
 };
 
