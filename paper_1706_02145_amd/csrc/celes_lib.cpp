@@ -21,6 +21,7 @@
 #include "precond.hpp"
 #include "vec_kernels.hpp"
 #include "wx_launch.hpp"
+#include "wx_mfma.hpp"
 #include "batch_kernels.hpp"
 
 using celes::cplx;
@@ -32,6 +33,67 @@ thread_local std::string g_create_error;
 using celes::DevBuf;
 
 }  // namespace
+
+namespace celes {
+// Records of the reduced block entries for the matrix-core mat-vec.  Entry
+// (n, n'), receiving n = (l, m), source n' = (l', m'), mu = |m' - m|; one
+// record per mirror pair {(m, m'), (-m, -m')}, kept for m > 0 or m = 0 <= m':
+//   [0]    p_A offset mu (4L+1) + p_A | p_B offset << 10 | (m' - m + 2L) << 20
+//          | mirror flag << 30                                  (int bits)
+//   [1, 2] LDS offsets of the real-form positions (n, n'), (n+H, n'+H) and
+//          (n, n'+H), (n+H, n'), 16 bits each                   (int bits)
+//   [3, 4] the same for the mirror entry
+//   [5 .. 5+L]      a5(l',m'|l,m|p), p = p_A, p_A + 2, ...  (zero-padded)
+//   [6+L .. 5+2L]   b5(l',m'|l,m|p) / i, p = p_B, p_B + 2, ...
+// p_A is the least p >= max(|l-l'|, mu) with l+l'+p even and p_B the least
+// p >= max(|l-l'|+1, mu) with l+l'+p odd (Appendix A.2 selection rules); an
+// empty B sum points at a zero slot.  Operand position (r, c) of the real
+// form, R = 2 HALF rounded up to 16, KS = R / 4, sits at
+// (r / 16) 64 KS + (r % 16) KS + 16 KS (c % 4) + c / 4.
+void wx_mfma_records(int L, std::vector<float>* rec) {
+    const int half = L * (L + 2), hs = 4 * L + 1, ta = L + 1, tb = L;
+    const int R = (2 * half + 15) / 16 * 16, KS = R / 4;
+    rec->clear();
+    auto F = [&](int r) { return (r / 16) * 64 * KS + (r % 16) * KS; };
+    auto G = [&](int c) { return 16 * KS * (c % 4) + c / 4; };
+    auto as_float = [](int v) {
+        float f;
+        std::memcpy(&f, &v, sizeof(float));
+        return f;
+    };
+    auto pos = [&](int n, int np, float* w) {
+        w[0] = as_float(F(n) + G(np) | (F(n + half) + G(np + half)) << 16);
+        w[1] = as_float(F(n) + G(np + half) | (F(n + half) + G(np)) << 16);
+    };
+    for (int l = 1; l <= L; ++l)
+        for (int m = 0; m <= l; ++m)
+            for (int lp = 1; lp <= L; ++lp)
+                for (int mp = -lp; mp <= lp; ++mp) {
+                    if (m == 0 && mp < 0) continue;
+                    float r[WXM_REC] = {};
+                    const int mu = std::abs(mp - m);
+                    int pa = std::max(std::abs(l - lp), mu);
+                    if ((l + lp + pa) & 1) ++pa;
+                    int pb = std::max(std::abs(l - lp) + 1, mu);
+                    if (!((l + lp + pb) & 1)) ++pb;
+                    const int hA = mu * hs + pa;
+                    const int hB = pb <= l + lp - 1 ? mu * hs + pb : mu * hs + 2 * L + 1;
+                    const bool mirror = !(m == 0 && mp == 0);
+                    r[0] = as_float(hA | hB << 10 | (mp - m + 2 * L) << 20 | (mirror ? 1 : 0) << 30);
+                    pos(lm_index(l, m), lm_index(lp, mp), r + 1);
+                    pos(lm_index(l, -m), lm_index(lp, -mp), r + 3);
+                    for (int q = 0; q < ta; ++q) {
+                        const int p = pa + 2 * q;
+                        r[5 + q] = p <= l + lp ? (float)a5_coef(lp, mp, l, m, p) : 0.f;
+                    }
+                    for (int q = 0; q < tb; ++q) {
+                        const int p = pb + 2 * q;
+                        r[5 + ta + q] = p <= l + lp - 1 ? (float)b5im_coef(lp, mp, l, m, p) : 0.f;
+                    }
+                    rec->insert(rec->end(), r, r + WXM_REC);
+                }
+}
+}  // namespace celes
 
 namespace {
 
@@ -162,10 +224,68 @@ int pick_kb(int L, int K) {
     return 1;
 }
 
+
+// complex64 mat-vec of K = a multiple of 16 right-hand sides on the matrix
+// cores (lmax <= 4)
+static int matvec_mfma(celes_handle* h, const cx<float>* x, cx<float>* y, int K, int width, int epilogue,
+                       hipStream_t s) {
+    const int64_t N = h->N;
+    const int64_t nbx = (N + 3) / 4 * (K / width);
+    const char* env = std::getenv("CELES_WXM_TARGET_BLOCKS");
+    const int target = env ? std::max(1, std::atoi(env)) : 2048;
+    int64_t nchunk = std::max<int64_t>(1, std::min<int64_t>((target + nbx - 1) / nbx, (N + 1) / 2));
+    int64_t chunk_len = (N + nchunk - 1) / nchunk;
+    chunk_len += chunk_len & 1;
+    const int nchunk_eff = (int)((N + chunk_len - 1) / chunk_len);
+    if (!h->d_xsd.ensure(celes::wx_mfma_xb_floats(h->L, N, K) * sizeof(float)) ||
+        !h->d_part.ensure((size_t)nchunk_eff * K * h->nmax * N * sizeof(cx<float>)))
+        return fail(h, CELES_E_OOM, "cannot allocate mat-vec scratch");
+    celes::WxMfmaArgs a;
+    a.px = h->d_px.as<double>();
+    a.py = h->d_py.as<double>();
+    a.pz = h->d_pz.as<double>();
+    a.x = x;
+    a.kstep = nullptr;
+    a.kin = 0;
+    a.slot_stride = 0;
+    a.active = nullptr;
+    a.sys0 = 0;
+    a.xb = h->d_xsd.as<float>();
+    a.part = h->d_part.as<cx<float>>();
+    a.rec = h->d_mrec.as<float>();
+    a.lut.coef = h->d_lut32.as<cx<float>>();
+    a.lut.d_lo = h->lut_lo;
+    a.lut.inv_dr = 1.0 / h->lut_dr;
+    a.lut.inv_k = 1.0 / h->k;
+    a.lut.n_int = (int)h->lut_n;
+    a.k = h->k;
+    a.n = (int)N;
+    a.chunk_len = (int)chunk_len;
+    a.ldp = (int)N;
+    a.nrhs = K;
+    const int rc = celes::wx_launch_mfma(a, h->L, width, h->opt.hankel == CELES_HANKEL_DIRECT ? 1 : 0, nchunk_eff, x,
+                                         h->d_tq32.as<cx<float>>(), y, epilogue, s);
+    if (rc != 0) return fail(h, CELES_E_DEVICE, "matrix-core mat-vec launch failed");
+    return CELES_OK;
+}
+
+// matrix-core path for K right-hand sides in complex64?  CELES_WXM=0 turns
+// it off, CELES_WXM=2 takes it for every applicable width (tests)
+static int mfma_width(const celes_handle* h, int K) {
+    const char* env = std::getenv("CELES_WXM");
+    const int mode = env ? std::atoi(env) : 1;
+    if (mode == 0) return 0;
+    return celes::wx_mfma_block(h->L, K, mode == 2);
+}
+
 // y = W x (epilogue 0) or x - T W x (epilogue 1) for K right-hand sides,
 // x, y: [K][N][nmax] device buffers of precision T
 template <typename T>
 int matvec(celes_handle* h, const cx<T>* x, cx<T>* y, int K, int epilogue, hipStream_t s) {
+    if constexpr (sizeof(T) == 4) {
+        const int width = mfma_width(h, K);
+        if (width > 0) return matvec_mfma(h, x, y, K, width, epilogue, s);
+    }
     const int64_t N = h->N;
     const int kb = pick_kb<T>(h->L, K);
     int64_t nbx = (N + celes::WX_BLOCK_SIZE - 1) / celes::WX_BLOCK_SIZE * celes::wx_num_groups(h->L) * (K / kb);
@@ -505,6 +625,13 @@ int celes_create(celes_handle** out, int64_t N, const double* pos, const double*
     if (rc != CELES_OK) {
         g_create_error = hp->err;
         return rc;
+    }
+    if (lmax <= celes::WXM_MAX_L) {
+        std::vector<float> rec;
+        celes::wx_mfma_records(lmax, &rec);
+        if (!hp->d_mrec.ensure(rec.size() * sizeof(float)) ||
+            hipMemcpy(hp->d_mrec.p, rec.data(), rec.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
+            return fail(nullptr, CELES_E_DEVICE, "cannot upload the block-entry records");
     }
     *out = h.release();
     return CELES_OK;
@@ -1053,6 +1180,10 @@ struct celes_batch {
     std::vector<int> sys_prob;       // [nsys]
     // mat-vec configuration (set by celes_batch_autotune or defaults)
     int chunk_len = 256, kb32 = 1, kb64 = 1, persist_blocks = 2048;
+    // complex64 mat-vec of problems whose right-hand sides fill matrix-core blocks
+    std::vector<int> mf_prob, mf_width, mf_nch;
+    std::vector<celes::WxMfmaArgs> mf_args;
+    DevBuf d_xb;
     // device buffers
     DevBuf d_elem_off, d_half_off, d_n, d_nrhs, d_nchunk, d_part_off, d_tq32, d_tq64;
     DevBuf d_args32, d_args64, d_item_off, d_nbx, d_nch, d_counter;
@@ -1108,7 +1239,8 @@ int batch_configure(celes_batch* b) {
         nch[p] = (int)((N + cl - 1) / cl);
         part_off[p] = poff;
         poff += (int64_t)nch[p] * K * b->nmax * N;
-        item32[p + 1] = item32[p] + nbx[p] * nch[p] * G * (K / b->kb32);
+        const int mw = mfma_width(h, K);
+        item32[p + 1] = item32[p] + (mw > 0 ? 0 : nbx[p] * nch[p] * G * (K / b->kb32));
         item64[p + 1] = item64[p] + nbx[p] * nch[p] * G * (K / b->kb64);
         auto fill = [&](auto& a) {
             a.px = h->d_px.as<double>();
@@ -1138,6 +1270,52 @@ int batch_configure(celes_batch* b) {
     if (!b->d_xsd.ensure((size_t)b->total * sizeof(cx<double>)) ||
         !b->d_part.ensure((size_t)std::max<int64_t>(1, poff) * sizeof(cx<double>)))
         return bfail(b, CELES_E_OOM, "cannot allocate batch mat-vec scratch");
+    // matrix-core problems: same source chunks as the VALU path (the finish
+    // kernel reduces nch[p] partial sums), operand-ordered sources in d_xb
+    b->mf_prob.clear();
+    b->mf_width.clear();
+    b->mf_nch.clear();
+    b->mf_args.clear();
+    size_t xb_floats = 0;
+    std::vector<size_t> xb_off;
+    for (int p = 0; p < b->nprob; ++p) {
+        celes_handle* h = b->probs[p];
+        const int K = b->sys0[p + 1] - b->sys0[p];
+        const int mw = mfma_width(h, K);
+        if (mw == 0) continue;
+        b->mf_prob.push_back(p);
+        b->mf_width.push_back(mw);
+        b->mf_nch.push_back(nch[p]);
+        xb_off.push_back(xb_floats);
+        xb_floats += celes::wx_mfma_xb_floats(b->L, h->N, K);
+    }
+    if (!b->mf_prob.empty() && !b->d_xb.ensure(xb_floats * sizeof(float)))
+        return bfail(b, CELES_E_OOM, "cannot allocate batch matrix-core scratch");
+    for (size_t q = 0; q < b->mf_prob.size(); ++q) {
+        const int p = b->mf_prob[q];
+        celes_handle* h = b->probs[p];
+        celes::WxMfmaArgs m{};
+        m.px = h->d_px.as<double>();
+        m.py = h->d_py.as<double>();
+        m.pz = h->d_pz.as<double>();
+        m.xb = b->d_xb.as<float>() + xb_off[q];
+        m.part = (cx<float>*)b->d_part.p + part_off[p];
+        m.rec = h->d_mrec.as<float>();
+        m.lut.coef = h->d_lut32.as<cx<float>>();
+        m.lut.d_lo = h->lut_lo;
+        m.lut.inv_dr = 1.0 / h->lut_dr;
+        m.lut.inv_k = 1.0 / h->k;
+        m.lut.n_int = (int)h->lut_n;
+        m.k = h->k;
+        m.n = (int)h->N;
+        m.chunk_len = a32[p].chunk_len;
+        m.ldp = (int)h->N;
+        m.nrhs = b->sys0[p + 1] - b->sys0[p];
+        m.slot_stride = b->total;
+        m.active = b->st_act.as<int>();
+        m.sys0 = b->sys0[p];
+        b->mf_args.push_back(m);
+    }
     for (int p = 0; p < b->nprob; ++p) {
         a32[p].xsd = (const cx<float>*)b->d_xsd.p + b->elem_off[p];
         a64[p].xsd = (const cx<double>*)b->d_xsd.p + b->elem_off[p];
@@ -1184,6 +1362,17 @@ int batch_matvec(celes_batch* b, const cx<T>* V, const int* kstep, int kin, cx<T
                                     b->persist_blocks, f64 ? b->kb64 : b->kb32,
                                     b->opt.hankel == CELES_HANKEL_DIRECT ? 1 : 0, s);
     if (rc != 0) return bfail(b, CELES_E_DEVICE, "batch mat-vec launch failed");
+    if constexpr (sizeof(T) == 4) {
+        for (size_t q = 0; q < b->mf_prob.size(); ++q) {
+            celes::WxMfmaArgs m = b->mf_args[q];
+            m.x = (const cx<float>*)V + b->elem_off[b->mf_prob[q]];
+            m.kstep = kstep;
+            m.kin = kin;
+            if (celes::wx_mfma_launch(m, b->L, b->mf_width[q], b->opt.hankel == CELES_HANKEL_DIRECT ? 1 : 0,
+                                      b->mf_nch[q], s) != 0)
+                return bfail(b, CELES_E_DEVICE, "batch matrix-core mat-vec launch failed");
+        }
+    }
     celes::bk_finish<T>(g, (const cx<T>*)b->d_part.p, V, b->total, kstep, kin, kout, Y, epilogue, s);
     return CELES_OK;
 }

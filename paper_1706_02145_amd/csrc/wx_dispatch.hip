@@ -5,6 +5,7 @@
 
 #include "device_common.hpp"
 #include "wx_launch.hpp"
+#include "wx_mfma.hpp"
 
 namespace celes {
 
@@ -124,6 +125,17 @@ switch (L) {
     }
 
     hipLaunchKernelGGL(wx_finish_kernel<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, a.part, nchunk,
+                       a.ldp, a.n, L, a.nrhs, x, tq, y, epilogue);
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+int wx_launch_mfma(const WxMfmaArgs& a, int L, int width, int hmode, int nchunk, const cx<float>* x,
+                   const cx<float>* tq, cx<float>* y, int epilogue, hipStream_t s) {
+    const int half = L * (L + 2);
+    const int64_t tot = (int64_t)a.n * half * a.nrhs;
+    const int rc = wx_mfma_launch(a, L, width, hmode, nchunk, s);
+    if (rc != 0) return rc;
+    hipLaunchKernelGGL(wx_finish_kernel<float>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, a.part, nchunk,
                        a.ldp, a.n, L, a.nrhs, x, tq, y, epilogue);
     return hipGetLastError() == hipSuccess ? 0 : -2;
 }

@@ -1,0 +1,472 @@
+// Coupling mat-vec W x for a block of right-hand sides on the matrix cores
+// (paper, Section 2.2 eq. a and Section 3.2.2; complex64, lmax <= 4).
+//
+// Mapping.  One wave = one receiving sphere i; the four waves of a block share
+// the LDS-staged source vectors of a tile of sources.  For every pair (i, j)
+// the wave
+//   1. evaluates the pair geometry, h_p(kd), the Legendre columns and the
+//      azimuthal phases once (wave-uniform) and leaves H_p^mu = h_p P_p^mu and
+//      e^{ik phi} in a wave-private LDS area;
+//   2. builds the two reduced HALF x HALF blocks
+//        P = e^{i(m'-m) phi} (A~ + i B~),   Q = e^{i(m'-m) phi} (A~ - i B~),
+//      A~ = sum_p a5(l',m'|l,m|p) H_p^{|m'-m|}, B~ likewise with b5 / i,
+//      lane-parallel from a host-built record table, and writes them in real
+//      form [[Re, -Im], [Im, Re]] into LDS in matrix-core operand order.  One
+//      record serves an entry and its mirror (m, m' -> -m, -m'): a5 is even
+//      and b5 odd under the mirror (Appendix A.2), so with Y = A~ + i B~ and
+//      X = A~ - i B~ the mirror entry has P = conj(ph) X and Q = conj(ph) Y;
+//   3. applies P to the source's s = x1 + x2 and Q to d = x1 - x2 for all the
+//      block's right-hand sides: two (R x R) x (R x KN) real products,
+//      R = 2 HALF rounded up to 16, with v_mfma_f32_16x16x4f32, accumulating
+//      in registers over the source chunk.
+// The partial sums go to the layout of the VALU kernels and are reduced by the
+// same finish kernel.
+#include <hip/hip_runtime.h>
+#include <type_traits>
+
+#include "device_common.hpp"
+#include "wx_plan.hpp"
+#include "wx_mfma.hpp"
+
+namespace celes {
+
+using namespace plan;
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+namespace {
+
+template <int B, int E, typename F>
+__device__ __forceinline__ void mfor(F&& f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        mfor<B + 1, E>(f);
+    }
+}
+
+template <int L>
+struct MShape {
+    static constexpr int HALF = L * (L + 2);
+    static constexpr int R = (2 * HALF + 15) / 16 * 16;   // real-form order, padded to the MFMA tile
+    static constexpr int MT = R / 16;                      // 16-row tiles
+    static constexpr int KS = R / 4;                       // k-steps of 4
+    static constexpr int KQ = KS / 4;                      // float4 groups of k-steps
+    static constexpr int E = HALF * HALF;                  // reduced block entries
+    static constexpr int P2 = 2 * L;
+    static constexpr int HS = 4 * L + 1;                   // H row stride: p = 0..4L, zero above 2L
+    static constexpr int NPH = 4 * L + 1;                  // e^{ik phi}, k = -2L..2L
+    static constexpr int TA = L + 1, TB = L;               // padded term counts of A~ and B~
+    static constexpr int EC = (E + L * L) / 2;             // records: entry pairs under the mirror
+    static_assert(KS % 4 == 0, "k-steps come in float4 groups");
+    static_assert(5 + TA + TB <= WXM_REC, "record too short");
+    static_assert(2 * MT * 64 * KS <= 65536, "operand offsets must fit 16 bits");
+};
+
+// h_p(kd), p = 0..2L, in FP32 from the FP64 distance: h_0, h_1 from the
+// two-order table (HMODE 0) or from sin/cos (HMODE 1), higher orders by the
+// upward recurrence h_{p+1} = (2p+1)/x h_p - h_{p-1}
+template <int L, int HMODE>
+__device__ __forceinline__ void pair_hankel(double r, double inv_r, const WxMfmaArgs& a, cx<float> (&h)[2 * L + 1]) {
+    constexpr int P = 2 * L;
+    float fi;
+    if constexpr (HMODE == 0) {
+        const double s = (r - a.lut.d_lo) * a.lut.inv_dr;
+        int q = (int)s;
+        q = q < 0 ? 0 : (q >= a.lut.n_int ? a.lut.n_int - 1 : q);
+        const float t = (float)(s - (double)q);
+        const cx<float>* c = a.lut.coef + (size_t)q * 8;
+#pragma unroll
+        for (int p = 0; p <= 1; ++p) {
+            const cx<float> c0 = c[4 * p], c1 = c[4 * p + 1], c2 = c[4 * p + 2], c3 = c[4 * p + 3];
+            h[p].re = fmaf(fmaf(fmaf(c3.re, t, c2.re), t, c1.re), t, c0.re);
+            h[p].im = fmaf(fmaf(fmaf(c3.im, t, c2.im), t, c1.im), t, c0.im);
+        }
+        fi = (float)(inv_r * a.lut.inv_k);
+    } else {
+        const double kd = a.k * r;
+        double s, c;
+        sincos(kd, &s, &c);
+        const double inv = 1.0 / kd;
+        const double h0r = s * inv, h0i = -c * inv;
+        h[0] = {(float)h0r, (float)h0i};
+        h[1] = {(float)((h0r - c) * inv), (float)((h0i - s) * inv)};
+        fi = (float)inv;
+    }
+#pragma unroll
+    for (int p = 1; p < P; ++p) {
+        const float f = (float)(2 * p + 1) * fi;
+        h[p + 1] = {f * h[p].re - h[p - 1].re, f * h[p].im - h[p - 1].im};
+    }
+}
+
+// one block-entry record, decoded: H offsets of the first A~ / B~ terms,
+// phase index, mirror flag, packed operand offsets, coefficients
+template <int L>
+struct EntryRec {
+    int head, w01, w23, m01, m23;
+    float c[2 * L + 1];
+};
+
+template <int L>
+__device__ __forceinline__ void load_rec(const float* r, EntryRec<L>& e) {
+    e.head = __float_as_int(r[0]);
+    e.w01 = __float_as_int(r[1]);
+    e.w23 = __float_as_int(r[2]);
+    e.m01 = __float_as_int(r[3]);
+    e.m23 = __float_as_int(r[4]);
+#pragma unroll
+    for (int q = 0; q <= 2 * L; ++q) e.c[q] = r[5 + q];
+}
+
+// P, Q of one record (and of its mirror) into the wave's real-form operands
+template <int L>
+__device__ __forceinline__ void build_entry(const EntryRec<L>& e, const cx<float>* sh, const cx<float>* sp, float* aP,
+                                            float* aQ) {
+    constexpr int TA = L + 1, TB = L;
+    const int hA = e.head & 1023, hB = (e.head >> 10) & 1023, iph = (e.head >> 20) & 1023;
+    cx<float> A = {0.f, 0.f}, B = {0.f, 0.f};
+#pragma unroll
+    for (int q = 0; q < TA; ++q) {
+        const cx<float> hh = sh[hA + 2 * q];
+        A.re = fmaf(e.c[q], hh.re, A.re);
+        A.im = fmaf(e.c[q], hh.im, A.im);
+    }
+#pragma unroll
+    for (int q = 0; q < TB; ++q) {
+        const cx<float> hh = sh[hB + 2 * q];
+        B.re = fmaf(e.c[TA + q], hh.re, B.re);
+        B.im = fmaf(e.c[TA + q], hh.im, B.im);
+    }
+    const cx<float> ph = sp[iph];
+    const cx<float> Y = {A.re - B.im, A.im + B.re};   // A~ + i B~
+    const cx<float> X = {A.re + B.im, A.im - B.re};   // A~ - i B~
+    // real-form positions (n, n'), (n+H, n'+H) <- Re; (n, n'+H) <- -Im; (n+H, n') <- Im
+    auto put = [&](int w01, int w23, cx<float> vp, cx<float> vq) {
+        const int o0 = w01 & 0xffff, o1 = (int)((unsigned)w01 >> 16);
+        const int o2 = w23 & 0xffff, o3 = (int)((unsigned)w23 >> 16);
+        aP[o0] = vp.re;
+        aP[o1] = vp.re;
+        aP[o2] = -vp.im;
+        aP[o3] = vp.im;
+        aQ[o0] = vq.re;
+        aQ[o1] = vq.re;
+        aQ[o2] = -vq.im;
+        aQ[o3] = vq.im;
+    };
+    put(e.w01, e.w23, cmul(ph, Y), cmul(ph, X));
+    if ((e.head >> 30) & 1) {
+        const cx<float> phc = {ph.re, -ph.im};
+        put(e.m01, e.m23, cmul(phc, X), cmul(phc, Y));
+    }
+}
+
+template <int L, int NT, int HMODE>
+__global__ __launch_bounds__(256) void wx_mfma_kernel(WxMfmaArgs a) {
+    using S = MShape<L>;
+    constexpr int HALF = S::HALF, MT = S::MT, KS = S::KS, KQ = S::KQ, P2 = S::P2;
+    constexpr int HS = S::HS, NPH = S::NPH, EC = S::EC;
+    constexpr int KN = 16 * NT;                 // right-hand sides per block
+    constexpr int TS = 2;                       // sources per tile: one per half-wave in the set-up
+    constexpr int AH = MT * 64 * KS;            // floats of one real-form block (R x R)
+    constexpr int XH = NT * 64 * KS;            // floats of one source half (R x KN)
+    constexpr int EPL = (EC + 63) / 64;         // records per lane
+    constexpr bool REGREC = EPL <= 2;           // records live in registers (lmax <= 3)
+    constexpr int HT = (P2 + 1) * HS;           // complex H entries per source
+
+    __shared__ __attribute__((aligned(16))) float s_rec[REGREC ? 4 : EC * WXM_REC];
+    __shared__ __attribute__((aligned(16))) float s_x[TS * 2 * XH];
+    __shared__ __attribute__((aligned(16))) float s_a[4 * 2 * AH];
+    __shared__ cx<float> s_h[4 * TS * HT];
+    __shared__ cx<float> s_ph[4 * TS * NPH];
+    __shared__ double s_pos[TS * 3];
+
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int i = blockIdx.x * 4 + wv;
+    const bool active = i < a.n;
+    const int chunk = blockIdx.y;
+    const int k0 = blockIdx.z * KN;
+    if (a.active) {
+        // batches: nothing to do once every system of this block has converged
+        int any = 0;
+        for (int c = 0; c < KN; ++c) any |= a.active[a.sys0 + k0 + c];
+        if (!any) return;
+    }
+
+    if constexpr (!REGREC)
+        for (int e = tid; e < EC * WXM_REC; e += 256) s_rec[e] = a.rec[e];
+    for (int e = tid; e < 4 * 2 * AH; e += 256) s_a[e] = 0.f;          // padding rows / columns stay zero
+    for (int e = tid; e < 4 * TS * HT; e += 256) s_h[e] = {0.f, 0.f};  // p > 2L stays zero
+
+    float* const sa = s_a + wv * 2 * AH;
+    cx<float>* const shw = s_h + wv * TS * HT;
+    cx<float>* const spw = s_ph + wv * TS * NPH;
+
+    // records of this lane (lmax <= 3): loaded once
+    EntryRec<L> rr[REGREC ? EPL : 1];
+    if constexpr (REGREC) {
+#pragma unroll
+        for (int t = 0; t < EPL; ++t) {
+            const int e = lane + 64 * t;
+            if (e < EC) load_rec<L>(a.rec + (size_t)e * WXM_REC, rr[t]);
+            else rr[t] = EntryRec<L>{};
+        }
+    }
+
+    // set-up lanes: half-wave g = lane / 32 serves source t0 + g of a tile;
+    // within it, lane gl = lane % 32 computes Legendre column mu = gl
+    // (gl <= 2L) or the phase e^{ik phi}, k = gl - 4L - 1 (2L < gl <= 6L + 1)
+    const int g = lane >> 5, gl = lane & 31;
+    float dg = 0.70710678118654752440f;
+    for (int v = 1; v <= gl && v <= P2; ++v) dg *= sqrtf((2.f * v + 1.f) / (2.f * v));
+    float la[P2 + 1], lb[P2 + 1];
+#pragma unroll
+    for (int p = 0; p <= P2; ++p) {
+        const float pf = (float)p, mf = (float)gl;
+        la[p] = p == gl + 1 ? sqrtf(2.f * mf + 3.f)
+                            : (p > gl + 1 ? sqrtf((4.f * pf * pf - 1.f) / (pf * pf - mf * mf)) : 0.f);
+        lb[p] = p > gl + 1 ? sqrtf((2.f * pf + 1.f) * ((pf - 1.f) * (pf - 1.f) - mf * mf) /
+                                   ((2.f * pf - 3.f) * (pf * pf - mf * mf)))
+                           : 0.f;
+    }
+    const int kph = gl - (P2 + 1) - 2 * L;
+
+    const double xi = active ? a.px[i] : 0.0;
+    const double yi = active ? a.py[i] : 0.0;
+    const double zi = active ? a.pz[i] : 0.0;
+
+    v4f acc[2][MT][NT];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) acc[h][mt][nt] = v4f{0.f, 0.f, 0.f, 0.f};
+
+    const int j0 = chunk * a.chunk_len;
+    const int j1 = min(a.n, j0 + a.chunk_len);
+    for (int t0 = j0; t0 < j1; t0 += TS) {
+        const int ntile = min(TS, j1 - t0);
+        __syncthreads();
+        // B operands of the tile (a contiguous copy of the operand-ordered
+        // records of the prep kernel) and the tile's centres
+        {
+            const float4* src = reinterpret_cast<const float4*>(a.xb + ((size_t)blockIdx.z * a.n + t0) * 2 * XH);
+            float4* dst = reinterpret_cast<float4*>(s_x);
+            for (int idx = tid; idx < ntile * 2 * XH / 4; idx += 256) dst[idx] = src[idx];
+            if (tid < 3 * ntile) {
+                const int jj = tid / 3, c = tid % 3;
+                s_pos[tid] = (c == 0 ? a.px : c == 1 ? a.py : a.pz)[t0 + jj];
+            }
+        }
+        __syncthreads();
+        // ---- set-up of the tile's pairs: geometry, h_p, H_p^mu = h_p P_p^mu, e^{ik phi} ----
+        if (active && g < ntile && t0 + g != i) {
+            const double dx = xi - s_pos[3 * g], dy = yi - s_pos[3 * g + 1], dz = zi - s_pos[3 * g + 2];
+            const double rho2 = dx * dx + dy * dy;
+            const double r = sqrt(rho2 + dz * dz);
+            const double inv_r = 1.0 / r;
+            const double rho = sqrt(rho2);
+            const float ct = (float)(dz * inv_r), st = (float)(rho * inv_r);
+            float cph = 1.f, sph = 0.f;
+            if (rho > 0.0) {
+                const double ir = 1.0 / rho;
+                cph = (float)(dx * ir);
+                sph = (float)(dy * ir);
+            }
+            cx<float> hv[P2 + 1];
+            pair_hankel<L, HMODE>(r, inv_r, a, hv);
+            cx<float>* sh = shw + g * HT;
+            float pw = 1.f;
+#pragma unroll
+            for (int q = 1; q <= P2; ++q) pw = q <= gl ? pw * st : pw;
+            float p1 = 0.f, p2 = 0.f;
+#pragma unroll
+            for (int p = 0; p <= P2; ++p) {
+                const float v = p == gl ? dg * pw : la[p] * ct * p1 - lb[p] * p2;
+                p2 = p1;
+                p1 = v;
+                if (gl <= P2) sh[gl * HS + p] = {hv[p].re * v, hv[p].im * v};
+            }
+            const int ak = kph < 0 ? -kph : kph;
+            cx<float> ep = {1.f, 0.f};
+            const cx<float> e1 = {cph, sph};
+#pragma unroll
+            for (int q = 1; q <= P2; ++q)
+                if (q <= ak) ep = cmul(ep, e1);
+            if (kph >= -2 * L && kph <= 2 * L)
+                spw[g * NPH + kph + 2 * L] = kph < 0 ? cx<float>{ep.re, -ep.im} : ep;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        for (int jj = 0; jj < ntile; ++jj) {
+            const int j = t0 + jj;
+            if (!active || j == i) continue;
+            const cx<float>* sh = shw + jj * HT;
+            const cx<float>* sp = spw + jj * NPH;
+            // ---- reduced block entries (record pairs), lane-parallel, into the real-form operands ----
+#pragma unroll
+            for (int t = 0; t < EPL; ++t) {
+                const int e = lane + 64 * t;
+                if (t < EPL - 1 || EC % 64 == 0 || e < EC) {
+                    if constexpr (REGREC) {
+                        build_entry<L>(rr[t], sh, sp, sa, sa + AH);
+                    } else {
+                        EntryRec<L> rc;
+                        load_rec<L>(s_rec + e * WXM_REC, rc);
+                        build_entry<L>(rc, sh, sp, sa, sa + AH);
+                    }
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            // ---- block products on the matrix cores ----
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const float* ab = sa + h * AH + lane * KS;
+                float af[MT][KS];
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                    for (int q = 0; q < KQ; ++q) {
+                        const float4 v = *(const float4*)(ab + mt * 64 * KS + 4 * q);
+                        af[mt][4 * q] = v.x;
+                        af[mt][4 * q + 1] = v.y;
+                        af[mt][4 * q + 2] = v.z;
+                        af[mt][4 * q + 3] = v.w;
+                    }
+                const float* xb = s_x + (jj * 2 + h) * XH + lane * KS;
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) {
+                    float bf[KS];
+#pragma unroll
+                    for (int q = 0; q < KQ; ++q) {
+                        const float4 v = *(const float4*)(xb + nt * 64 * KS + 4 * q);
+                        bf[4 * q] = v.x;
+                        bf[4 * q + 1] = v.y;
+                        bf[4 * q + 2] = v.z;
+                        bf[4 * q + 3] = v.w;
+                    }
+#pragma unroll
+                    for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+                        for (int mt = 0; mt < MT; ++mt)
+                            acc[h][mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[mt][ks], bf[ks], acc[h][mt][nt],
+                                                                                  0, 0, 0);
+                }
+            }
+        }
+    }
+    if (!active) return;
+    // lane holds C[16 mt + 4 (lane / 16) + t][16 nt + lane % 16]: real-form
+    // row -> (half h, entry (l, m), real or imaginary part), column -> RHS
+    float* pf = reinterpret_cast<float*>(a.part);
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int rr2 = 16 * mt + 4 * (lane >> 4) + t;
+                    if (rr2 < 2 * HALF) {
+                        const int e = rr2 < HALF ? rr2 : rr2 - HALF;
+                        const int col = 16 * nt + (lane & 15);
+                        const size_t o =
+                            (((size_t)chunk * a.nrhs + k0 + col) * (2 * HALF) + h * HALF + e) * a.ldp + i;
+                        pf[2 * o + (rr2 < HALF ? 0 : 1)] = acc[h][mt][nt][t];
+                    }
+                }
+}
+
+// x [K][N][nmax] (tau blocks, complex64) -> xb [K / KN][N][2][NT][64][KS]:
+// for right-hand-side block z and source j, the real form of s = x1 + x2
+// (h = 0) and d = x1 - x2 (h = 1) as B operands of v_mfma_f32_16x16x4f32:
+// real-form row k (Re of entry k < HALF, Im of entry k - HALF below 2 HALF,
+// zero padding above) of right-hand side col = 16 nt + c sits at lane
+// (k % 4) 16 + c, k-step k / 4
+template <int L, int NT>
+__global__ void wx_mfma_prep_kernel(const cx<float>* __restrict__ x0, const int* kstep, int kin, int64_t slot_stride,
+                                    float* __restrict__ xb, int n, int K) {
+    using S = MShape<L>;
+    constexpr int HALF = S::HALF, KS = S::KS, KN = 16 * NT;
+    constexpr int XH = NT * 64 * KS;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t total = (int64_t)(K / KN) * n * 2 * XH;
+    if (t >= total) return;
+    const cx<float>* x = x0 + (kstep ? (int64_t)(*kstep + kin) * slot_stride : 0);
+    const int ks = (int)(t % KS);
+    int64_t r = t / KS;
+    const int ln = (int)(r % 64);
+    r /= 64;
+    const int nt = (int)(r % NT);
+    r /= NT;
+    const int h = (int)(r % 2);
+    r /= 2;
+    const int j = (int)(r % n);
+    const int z = (int)(r / n);
+    const int k = 4 * ks + (ln >> 4);
+    const int col = z * KN + 16 * nt + (ln & 15);
+    float v = 0.f;
+    if (k < 2 * HALF) {
+        const int e = k < HALF ? k : k - HALF;
+        const cx<float>* xr = x + ((size_t)col * n + j) * 2 * HALF;
+        const cx<float> x1 = xr[e], x2 = xr[HALF + e];
+        const cx<float> sd = h == 0 ? cx<float>{x1.re + x2.re, x1.im + x2.im} : cx<float>{x1.re - x2.re, x1.im - x2.im};
+        v = k < HALF ? sd.re : sd.im;
+    }
+    xb[t] = v;
+}
+
+template <int L, int NT>
+void launch_nt(const WxMfmaArgs& a, int hmode, int nchunk, hipStream_t s) {
+    using S = MShape<L>;
+    const int64_t total = (int64_t)a.nrhs * a.n * 2 * S::KS * 64 / 16;
+    hipLaunchKernelGGL((wx_mfma_prep_kernel<L, NT>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, a.x,
+                       a.kstep, a.kin, a.slot_stride, a.xb, a.n, a.nrhs);
+    dim3 grid((unsigned)((a.n + 3) / 4), (unsigned)nchunk, (unsigned)(a.nrhs / (16 * NT)));
+    if (hmode == 0)
+        hipLaunchKernelGGL((wx_mfma_kernel<L, NT, 0>), grid, dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL((wx_mfma_kernel<L, NT, 1>), grid, dim3(256), 0, s, a);
+}
+
+template <int L>
+void launch_L(const WxMfmaArgs& a, int width, int hmode, int nchunk, hipStream_t s) {
+    if (width == 64) launch_nt<L, 4>(a, hmode, nchunk, s);
+    else if (width == 32) launch_nt<L, 2>(a, hmode, nchunk, s);
+    else launch_nt<L, 1>(a, hmode, nchunk, s);
+}
+
+}  // namespace
+
+size_t wx_mfma_xb_floats(int L, int64_t N, int K) {
+    const int R = (2 * L * (L + 2) + 15) / 16 * 16;
+    return (size_t)2 * K * N * R;
+}
+
+int wx_mfma_block(int L, int K, bool any) {
+    if (L < 1 || L > WXM_MAX_L || K <= 0) return 0;
+    if (K % 64 == 0) return 64;
+    // measured on MI355X: 32-wide blocks beat the VALU kernel only up to
+    // lmax 3, 16-wide blocks never (the per-pair block build is amortised
+    // over too few right-hand sides)
+    if (K % 32 == 0 && (any || L <= 3)) return 32;
+    if (K % 16 == 0 && any) return 16;
+    return 0;
+}
+
+int wx_mfma_launch(const WxMfmaArgs& a, int L, int width, int hmode, int nchunk, hipStream_t s) {
+    if (wx_mfma_block(L, a.nrhs, true) == 0 || (width != 16 && width != 32 && width != 64) || a.nrhs % width)
+        return -1;
+    switch (L) {
+        case 1: launch_L<1>(a, width, hmode, nchunk, s); break;
+        case 2: launch_L<2>(a, width, hmode, nchunk, s); break;
+        case 3: launch_L<3>(a, width, hmode, nchunk, s); break;
+        case 4: launch_L<4>(a, width, hmode, nchunk, s); break;
+        default: return -1;
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+}  // namespace celes

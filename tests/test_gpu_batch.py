@@ -101,3 +101,41 @@ def test_batch_graph_replay_equals_eager_and_autotune():
     _, s3 = bt.solve()
     for (w, p), a in zip(probs, sol1):
         assert rel(p.solution(), a) <= 1e-6
+
+
+def test_batch_with_matrix_core_problem():
+    # 32 incidence directions on one slab fill a 32-wide matrix-core block
+    # (lmax 3); the other problems stay on the VALU kernel in the same batch
+    w = workload("slab64_l3")
+    beta = np.repeat(np.linspace(0.0, np.pi / 3, 16), 2)
+    alpha = np.zeros(32)
+    pol = np.tile([1, 2], 16)
+    big = P.Problem(w.positions, w.radii, w.n_sphere, w.n0, w.wavelength, w.lmax, hankel=0, tol=1e-10)
+    big.set_plane_waves(beta, alpha, pol)
+    rest = _problems(["slab300_l3", "cube8_l3"], tol=1e-10)
+    bt = P.Batch([big] + [p for _, p in rest], tol=1e-9, precision=P.CELES_MIXED, inner_tol=1e-4, restart=60)
+    print("[batch] matrix-core problem K=32 + 2 VALU problems", flush=True)
+    # apply_M: batch vs single-problem launches of both precisions
+    x = random_coefficients(40, 32, w.N, w.nmax)
+    xs = [x] + [random_coefficients(41 + i, p.num_rhs, ww.N, ww.nmax) for i, (ww, p) in enumerate(rest)]
+    flat = np.concatenate([v.reshape(-1) for v in xs])
+    xd = torch.from_numpy(flat).to("cuda", torch.complex64)
+    yd = torch.empty_like(xd)
+    bt.apply_M(xd, yd, P.CELES_MIXED)
+    torch.cuda.synchronize()
+    y = yd.cpu().numpy().astype(np.complex128)
+    xi = torch.from_numpy(x).to("cuda", torch.complex128)
+    yi = torch.empty_like(xi)
+    big.apply_M(xi, yi, P.CELES_FP64, K=32)
+    torch.cuda.synchronize()
+    ref = yi.cpu().numpy().reshape(-1)
+    e = rel(y[:ref.size], ref)
+    print(f"[batch] matrix-core apply_M vs FP64 {e:.2e}", flush=True)
+    assert e <= 1e-5
+    # mixed solve of the whole batch against FP64 single solves
+    per, summ = bt.solve()
+    assert summ["status"] == 0 and summ["rel_residual"] <= 1e-9
+    q = P.Problem(w.positions, w.radii, w.n_sphere, w.n0, w.wavelength, w.lmax, hankel=0, tol=1e-11)
+    q.set_plane_waves(beta, alpha, pol)
+    ref_b, _ = q.solve()
+    assert rel(big.solution(), ref_b) <= 1e-6
