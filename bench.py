@@ -25,6 +25,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "pair-multipole updates/s of W·b; time-to-residual 1e-6, mixed vs FP64"
+PEAK_FP32_MFMA_TFLOPS = 157.3   # MI355X dense FP32 matrix
 PEAK_FP64_VALU_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
 
 
@@ -162,6 +163,20 @@ def batched_mode(a):
     torch.cuda.synchronize()
     mv_ms = ev0.elapsed_time(ev1) / 3
     log(f"batched M x: {mv_ms:.1f} ms")
+    # the 64-right-hand-side slab alone: its W x runs on the matrix cores
+    xb = torch.randn(big.num_rhs * big.N * big.nmax, dtype=torch.complex64, device="cuda")
+    yb = torch.empty_like(xb)
+    big.apply_W(xb, yb, P.CELES_MIXED, K=big.num_rhs)
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(3):
+        big.apply_W(xb, yb, P.CELES_MIXED, K=big.num_rhs)
+    ev1.record()
+    torch.cuda.synchronize()
+    big_ms = ev0.elapsed_time(ev1) / 3
+    big_pairs = big.N * (big.N - 1)
+    apply_flops = 4 * big.nmax ** 2 * big.num_rhs * big_pairs      # (A+-B) block products, all RHS
+    log(f"64-RHS slab W x: {big_ms:.1f} ms")
     t1 = time.perf_counter()
     per, summ = bt.solve(check=False)
     log("solve done")
@@ -175,6 +190,13 @@ def batched_mode(a):
                                f"{a.realisations} realisations N in [500,5000] x 2 RHS, lmax 3, LUT 1 nm",
                    "realisation_sizes": sizes},
         "systems": bt.num_systems, "updates_per_batched_matvec": updates, "batched_matvec_ms": mv_ms,
+        "roofline": {"kernel": "wx_mfma_kernel<3, 4, 0> (64-RHS slab alone, prep + finish included)",
+                     "bound": "mfma", "achieved": apply_flops / (big_ms * 1e-3) / 1e12,
+                     "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
+                     "frac": apply_flops / (big_ms * 1e-3) / 1e12 / PEAK_FP32_MFMA_TFLOPS,
+                     "flops_counted": "4 nmax^2 K per pair (the block products); the per-pair block build "
+                                      "runs on the VALU and is not counted",
+                     "matvec_ms": big_ms, "updates_per_s": big_pairs * big.nmax ** 2 * big.num_rhs / (big_ms * 1e-3)},
         "autotune": tune, "solve_seconds": t_solve, "solve_status": summ["status"],
         "worst_rel_residual": summ["rel_residual"], "tol": a.batch_tol,
         "iterations_max": max(its), "iterations_mean": float(np.mean(its)), "refinements": summ["refinements"],
