@@ -203,6 +203,63 @@ def batched_mode(a):
         "geometry_seconds": t_gen}))
 
 
+def mixed_mode(a):
+    """Mixed precision against all-FP64 on the 20,000-sphere slab (lmax 4,
+    Gaussian beam, block-diagonal preconditioner, same seed): complex64 inner
+    GMRES with FP64 residual refinement vs FP64 GMRES, each solved to 1e-8
+    (solutions compared) and to 1e-6 (time to residual)."""
+    import numpy as np
+    import torch
+    import paper_1706_02145_amd as P
+    from celes_inputs import workload
+
+    t0 = time.perf_counter()
+
+    def log(msg):
+        print(f"[mixed] {msg} ({time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
+
+    w = workload(a.mixed_workload)
+    il = w.illumination
+    log(f"{w.name} generated (N={w.N})")
+    results, sols = {}, {}
+    for tol in (1e-8, 1e-6):
+        for name, prec in (("fp64", P.CELES_FP64), ("mixed", P.CELES_MIXED)):
+            p = P.Problem(w.positions, w.radii, w.n_sphere, w.n0, w.wavelength, w.lmax, hankel=P.CELES_HANKEL_LUT,
+                          lut_dr=w.lut_dr, precision=prec, tol=tol, restart=100, maxiter=3000,
+                          inner_tol=1e-4 if tol < 1e-7 else 1e-3, max_refinements=8, verbose=1)
+            p.set_gaussian_beam(il["waist"], il["focus"], il["alpha_G"], il["E0"])
+            t1 = time.perf_counter()
+            p.build_preconditioner(a.cuboid_edge)
+            torch.cuda.synchronize()
+            t_pre = time.perf_counter() - t1
+            log(f"{name} tol {tol:g}: preconditioner built in {t_pre:.1f} s")
+            t1 = time.perf_counter()
+            b, info = p.solve()
+            torch.cuda.synchronize()
+            t_sol = time.perf_counter() - t1
+            log(f"{name} tol {tol:g}: solved in {t_sol:.1f} s, {info['iterations']} iterations")
+            results[f"{name}_tol_{tol:g}"] = {"seconds": t_sol, "iterations": info["iterations"],
+                                              "refinements": info["refinements"], "matvecs": info["matvecs"],
+                                              "rel_residual": info["rel_residual"], "status": info["status"],
+                                              "preconditioner_setup_s": t_pre}
+            if tol < 1e-7:
+                sols[name] = b
+            p.close()
+    diff = float(np.linalg.norm(sols["mixed"] - sols["fp64"]) / np.linalg.norm(sols["fp64"]))
+    t64, t32 = results["fp64_tol_1e-06"]["seconds"], results["mixed_tol_1e-06"]["seconds"]
+    print(json.dumps({
+        "metric": "time to residual 1e-6, mixed precision (complex64 inner GMRES, FP64 refinement) vs FP64",
+        "value": t32, "unit": "s", "n_gpus": 1, "higher_is_better": False, "dtype": "f32 / f64",
+        "data": "synthetic",
+        "config": {"workload": f"{w.name}: N={w.N} RSA slab, radii lognormal(150 nm, 10%), n=1.52, vf 0.3, "
+                               f"lmax={w.lmax}, Gaussian beam w=2 um, LUT 1 nm, block-diagonal preconditioner "
+                               f"(cuboid edge {a.cuboid_edge:g} nm), restart 100",
+                   "N": w.N, "lmax": w.lmax},
+        "speedup_mixed_vs_fp64_1e-6": t64 / t32,
+        "speedup_mixed_vs_fp64_1e-8": results["fp64_tol_1e-08"]["seconds"] / results["mixed_tol_1e-08"]["seconds"],
+        "solution_rel_diff_mixed_vs_fp64_at_1e-8": diff, "results": results}))
+
+
 def warmstart_mode(a):
     """Learned initial guess: train on solver output of several slabs
     (lmax 3, N = a.train_n each), evaluate on a larger unseen slab: GMRES
@@ -284,7 +341,8 @@ def main():
     ap.add_argument("--cuboid-edge", type=float, default=1500.0)
     ap.add_argument("--hankel", choices=["lut", "direct"], default="lut")
     ap.add_argument("--profile", action="store_true", help="mat-vec launches only (for rocprofv3)")
-    ap.add_argument("--mode", choices=["solve", "batched", "warmstart"], default="solve")
+    ap.add_argument("--mode", choices=["solve", "batched", "warmstart", "mixed"], default="solve")
+    ap.add_argument("--mixed-workload", default="slab20000_l4")
     ap.add_argument("--realisations", type=int, default=32)
     ap.add_argument("--batch-tol", type=float, default=1e-6)
     ap.add_argument("--batch-maxiter", type=int, default=600)
@@ -301,6 +359,8 @@ def main():
         return batched_mode(a)
     if a.mode == "warmstart":
         return warmstart_mode(a)
+    if a.mode == "mixed":
+        return mixed_mode(a)
 
     import numpy as np
     import torch

@@ -459,6 +459,9 @@ int gmres_device(celes_handle* h, const cx<T>* rhs, cx<T>* x, double tol, int ma
         }
         hipStreamSynchronize(s);
         out->restarts++;
+        if (h->opt.verbose)
+            std::fprintf(stderr, "gmres (%s) cycle %d: %d iterations, estimate %.3e\n",
+                         sizeof(T) == 8 ? "fp64" : "fp32", out->restarts, out->iterations, out->est);
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);

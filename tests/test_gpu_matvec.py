@@ -138,3 +138,45 @@ def test_apply_W_multi_rhs(name, precision, K):
         xk = X[k] if precision == P.CELES_FP64 else X[k].astype(np.complex64).astype(np.complex128)
         ref = apply_W_rows(w.positions, xk, k_of(w), w.lmax, rows)
         assert rel(Y[k][rows], ref) <= bar
+
+
+def test_full_size_slab20000_sampled_rows():
+    # the 20,000-sphere slab of the mixed-vs-FP64 comparison, both precisions,
+    # default launch configuration
+    w = workload("slab20000_l4")
+    print(f"[matvec] slab20000_l4 N={w.N} sampled rows", flush=True)
+    x = random_coefficients(105, 1, w.N, w.nmax)[0]
+    p = make_problem(w, hankel=0)
+    rng = np.random.default_rng(6)
+    rows = sorted(set(rng.choice(w.N, 3, replace=False).tolist() + [w.N - 1]))
+    ref = apply_W_rows(w.positions, x, k_of(w), w.lmax, rows, hankel=oracle_lut(w))
+    y64 = _gpu_W(p, x)
+    assert rel(y64[rows], ref) <= 1e-12
+    y32 = _gpu_W(p, x, precision=P.CELES_MIXED)
+    ref32 = apply_W_rows(w.positions, x.astype(np.complex64).astype(np.complex128), k_of(w), w.lmax, rows,
+                         hankel=oracle_lut(w))
+    e = rel(y32[rows], ref32)
+    print(f"[matvec fp32] slab20000_l4 sampled rows rel err {e:.2e}", flush=True)
+    assert e <= 1e-4
+
+
+def test_full_size_slab10000_64rhs_matrix_cores_sampled_rows():
+    # the 64-right-hand-side slab of the batched workload: complex64 mat-vec on
+    # the matrix cores, sampled rows of three right-hand sides against the oracle
+    w = workload("slab10000_l3")
+    K = 64
+    print(f"[matvec mfma] slab10000_l3 N={w.N} K={K} sampled rows", flush=True)
+    X = random_coefficients(106, K, w.N, w.nmax)
+    p = make_problem(w, hankel=0)
+    xd = _dev(X, torch.complex64)
+    yd = torch.empty_like(xd)
+    p.apply_W(xd, yd, P.CELES_MIXED, K=K)
+    torch.cuda.synchronize()
+    Y = yd.cpu().numpy().astype(np.complex128)
+    rows = [0, 4321, w.N - 1]
+    for k in (0, 31, 63):
+        xk = X[k].astype(np.complex64).astype(np.complex128)
+        ref = apply_W_rows(w.positions, xk, k_of(w), w.lmax, rows, hankel=oracle_lut(w))
+        e = rel(Y[k][rows], ref)
+        print(f"[matvec mfma] rhs {k} rel err {e:.2e}", flush=True)
+        assert e <= 1e-4
