@@ -172,8 +172,10 @@ __global__ void assemble_kernel(AsmArgs g, int64_t ntot) {
 // fixed order and scatters back to the caller's sphere order.
 constexpr int PA_ROWS = 256, PA_COLS = 256;
 
-template <typename T>
-__global__ void __launch_bounds__(PA_ROWS) apply_tiles(const cx<double>* __restrict__ inv,
+// T: vector precision; TM: matrix precision (FP64 inverse, or its FP32 copy
+// for complex64 vectors); accumulation in TM
+template <typename T, typename TM>
+__global__ void __launch_bounds__(PA_ROWS) apply_tiles(const cx<TM>* __restrict__ inv,
                                                        const int64_t* __restrict__ perm,
                                                        const int64_t* __restrict__ boff,
                                                        const int64_t* __restrict__ moff, int nmax,
@@ -191,36 +193,40 @@ __global__ void __launch_bounds__(PA_ROWS) apply_tiles(const cx<double>* __restr
         return;
     }
     const int ncol = (int)(dim - c0 < PA_COLS ? dim - c0 : PA_COLS);
-    __shared__ cx<double> xs[PA_COLS];
+    __shared__ cx<TM> xs[PA_COLS];
     if (threadIdx.x < ncol) {
         const int64_t c = c0 + threadIdx.x;
         const cx<T> v = in[perm[o + c / nmax] * nmax + c % nmax];
-        xs[threadIdx.x] = {(double)v.re, (double)v.im};
+        xs[threadIdx.x] = {(TM)v.re, (TM)v.im};
     }
     __syncthreads();
     if (r >= dim) return;
-    const cx<double>* M = inv + moff[j] + c0 * dim + r;
-    double re0 = 0, im0 = 0, re1 = 0, im1 = 0, re2 = 0, im2 = 0, re3 = 0, im3 = 0;
+    const cx<TM>* M = inv + moff[j] + c0 * dim + r;
+    // eight column loads in flight per thread, four accumulator pairs
+    TM re[4] = {0, 0, 0, 0}, im[4] = {0, 0, 0, 0};
     int c = 0;
-    for (; c + 4 <= ncol; c += 4) {
-        const cx<double> a0 = M[(int64_t)(c + 0) * dim], a1 = M[(int64_t)(c + 1) * dim];
-        const cx<double> a2 = M[(int64_t)(c + 2) * dim], a3 = M[(int64_t)(c + 3) * dim];
-        const cx<double> x0 = xs[c], x1 = xs[c + 1], x2 = xs[c + 2], x3 = xs[c + 3];
-        re0 = fma(a0.re, x0.re, fma(-a0.im, x0.im, re0));
-        im0 = fma(a0.re, x0.im, fma(a0.im, x0.re, im0));
-        re1 = fma(a1.re, x1.re, fma(-a1.im, x1.im, re1));
-        im1 = fma(a1.re, x1.im, fma(a1.im, x1.re, im1));
-        re2 = fma(a2.re, x2.re, fma(-a2.im, x2.im, re2));
-        im2 = fma(a2.re, x2.im, fma(a2.im, x2.re, im2));
-        re3 = fma(a3.re, x3.re, fma(-a3.im, x3.im, re3));
-        im3 = fma(a3.re, x3.im, fma(a3.im, x3.re, im3));
+    for (; c + 8 <= ncol; c += 8) {
+        cx<TM> a[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] = M[(int64_t)(c + u) * dim];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const cx<TM> x = xs[c + u];
+            re[u & 3] = fma(a[u].re, x.re, fma(-a[u].im, x.im, re[u & 3]));
+            im[u & 3] = fma(a[u].re, x.im, fma(a[u].im, x.re, im[u & 3]));
+        }
     }
     for (; c < ncol; ++c) {
-        const cx<double> a0 = M[(int64_t)c * dim], x0 = xs[c];
-        re0 = fma(a0.re, x0.re, fma(-a0.im, x0.im, re0));
-        im0 = fma(a0.re, x0.im, fma(a0.im, x0.re, im0));
+        const cx<TM> a0 = M[(int64_t)c * dim], x0 = xs[c];
+        re[0] = fma(a0.re, x0.re, fma(-a0.im, x0.im, re[0]));
+        im[0] = fma(a0.re, x0.im, fma(a0.im, x0.re, im[0]));
     }
-    dst[r] = {(re0 + re1) + (re2 + re3), (im0 + im1) + (im2 + im3)};
+    dst[r] = {(double)((re[0] + re[1]) + (re[2] + re[3])), (double)((im[0] + im[1]) + (im[2] + im[3]))};
+}
+
+__global__ void narrow_kernel(const cx<double>* __restrict__ a, cx<float>* __restrict__ b, int64_t n) {
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t < n) b[t] = {(float)a[t].re, (float)a[t].im};
 }
 
 // out[perm[t / nmax] nmax + t % nmax] = sum_s part[s][t], t in permuted order
@@ -243,6 +249,7 @@ BlockPrecond::~BlockPrecond() {
     if (d_boff_) hipFree(d_boff_);
     if (d_moff_) hipFree(d_moff_);
     if (d_inv_) hipFree(d_inv_);
+    if (d_inv32_) hipFree(d_inv32_);
     if (d_part_) hipFree(d_part_);
 }
 
@@ -342,6 +349,17 @@ int BlockPrecond::build(int64_t N, int L, const double* pos, double k, const cpl
             rc = CELES_E_DEVICE_INTERNAL;
         }
     }
+    // complex64 copy of the inverses for the complex64 inner solves (half the
+    // bytes of the HBM-bound apply); the factorisation itself is FP64
+    if (rc == 0) {
+        if (!dev((void**)&d_inv32_, mat_elems_ * sizeof(cx<float>))) {
+            *msg = "cannot allocate the complex64 preconditioner copy";
+            rc = CELES_E_OOM_INTERNAL;
+        } else {
+            hipLaunchKernelGGL(narrow_kernel, dim3((unsigned)((mat_elems_ + 255) / 256)), dim3(256), 0, 0, d_inv_,
+                               d_inv32_, (int64_t)mat_elems_);
+        }
+    }
     hipDeviceSynchronize();
     rocblas_destroy_handle(rb);
     hipFree(d_ipiv);
@@ -363,8 +381,12 @@ int BlockPrecond::apply(const cx<T>* in, cx<T>* out, hipStream_t s) const {
     const int nsplit = (max_dim_ + PA_COLS - 1) / PA_COLS;
     const int64_t n = N_ * nmax_;
     dim3 grid((unsigned)((max_dim_ + PA_ROWS - 1) / PA_ROWS), (unsigned)nsplit, (unsigned)nb);
-    hipLaunchKernelGGL(apply_tiles<T>, grid, dim3(PA_ROWS), 0, s, d_inv_, d_perm_, d_boff_, d_moff_, nmax_, in,
-                       d_part_, n);
+    if constexpr (sizeof(T) == 4)
+        hipLaunchKernelGGL((apply_tiles<T, float>), grid, dim3(PA_ROWS), 0, s, d_inv32_, d_perm_, d_boff_, d_moff_,
+                           nmax_, in, d_part_, n);
+    else
+        hipLaunchKernelGGL((apply_tiles<T, double>), grid, dim3(PA_ROWS), 0, s, d_inv_, d_perm_, d_boff_, d_moff_,
+                           nmax_, in, d_part_, n);
     hipLaunchKernelGGL(apply_reduce<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, d_part_, nsplit,
                        d_perm_, nmax_, n, out);
     return hipGetLastError() == hipSuccess ? 0 : CELES_E_DEVICE_INTERNAL;

@@ -24,14 +24,15 @@ class BlockPrecond {
     // pos [N][3], tq [N][2][L] (host); lut_dev: FP64 Hankel table (LUT mode)
     int build(int64_t N, int L, const double* pos, double k, const cplx* tq, double edge, int hmode,
               const void* lut_dev, double lut_lo, double lut_dr, int lut_n, std::string* msg);
-    // out = P^{-1} in (in, out: [N][nmax] device vectors, must not alias)
+    // out = P^{-1} in (in, out: [N][nmax] device vectors, must not alias);
+    // complex64 vectors use the complex64 copy of the inverses
     template <typename T>
     int apply(const cx<T>* in, cx<T>* out, hipStream_t s) const;
 
     int num_blocks() const { return (int)offsets_.size() - 1; }
     const std::vector<int64_t>& perm() const { return perm_; }
     const std::vector<int64_t>& offsets() const { return offsets_; }
-    size_t bytes() const { return mat_elems_ * 16; }
+    size_t bytes() const { return mat_elems_ * (16 + 8); }
 
    private:
     int L_ = 0, nmax_ = 0;
@@ -43,6 +44,7 @@ class BlockPrecond {
     int64_t* d_boff_ = nullptr;      // [nb+1] sphere offsets
     int64_t* d_moff_ = nullptr;      // [nb] matrix element offsets
     cx<double>* d_inv_ = nullptr;    // block inverses, column-major, concatenated
+    cx<float>* d_inv32_ = nullptr;   // complex64 copy (applied to complex64 vectors)
     cx<double>* d_part_ = nullptr;   // [column tiles][N nmax] partial sums of the apply
 };
 
