@@ -79,11 +79,13 @@ def flops_per_pair(L, hankel_lut=True):
 
 
 def kernel_source_digest():
-    """sha256 of the coupling-kernel sources (counters are only valid for them)."""
+    """sha256 of the coupling-kernel sources and of the host code that sizes
+    its launch (counters are only valid for them)."""
     import hashlib
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_1706_02145_amd", "csrc")
-    for f in ("wx_kernels.hip", "wx_plan.hpp", "wx_launch.hpp", "device_common.hpp"):
+    for f in ("wx_kernels.hip", "wx_plan.hpp", "wx_launch.hpp", "device_common.hpp", "wx_dispatch.hip",
+              "celes_lib.cpp"):
         with open(os.path.join(d, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -296,7 +298,8 @@ def warmstart_mode(a):
     log(f"trained, loss {loss:.3e}")
     pos, rad = _realisation((5000, a.eval_n))
     log("evaluation geometry generated")
-    p = P.Problem(pos, rad, 1.52, 1.0, 550.0, 3, tol=1e-6, hankel=P.CELES_HANKEL_LUT, restart=100, maxiter=4000)
+    p = P.Problem(pos, rad, 1.52, 1.0, 550.0, 3, tol=1e-6, hankel=P.CELES_HANKEL_LUT, restart=100, maxiter=4000,
+                  verbose=1)
     p.set_plane_waves([0.0], [0.0], [2])
     a_in = p.incident()
     # single-scattering guess T a_in (per-sphere Mie coefficients from the library)
