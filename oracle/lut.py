@@ -9,7 +9,7 @@ h_p(kd) at every node, so each interval depends only on its two end nodes.
 Grid (a deterministic function of the geometry, computed the same way by the
 library):
     d_lo = max(dr, (floor(d_min / dr) - 1) dr),   d_min = 2 min_i R_i
-    n_int = ceil((d_max - d_lo) / dr) + 1,         d_max = |bounding-box diagonal of the centres|
+    n_int = max(1, ceil((d_max - d_lo) / dr) + 1), d_max = |bounding-box diagonal of the centres|
     nodes d_k = d_lo + k dr, k = 0..n_int.
 Interval index q = floor((d - d_lo)/dr), local t = (d - d_lo)/dr - q.
 
@@ -34,7 +34,7 @@ def lut_grid(positions, radii, dr):
     ext = pos.max(axis=0) - pos.min(axis=0)
     d_max = float(np.sqrt(np.sum(ext * ext)))
     d_lo = max(dr, (math.floor(d_min / dr) - 1) * dr)
-    n_int = int(math.ceil((d_max - d_lo) / dr)) + 1
+    n_int = max(1, int(math.ceil((d_max - d_lo) / dr)) + 1)   # one sphere: no pairs, one interval
     return d_lo, n_int
 
 

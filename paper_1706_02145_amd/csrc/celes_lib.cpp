@@ -171,7 +171,8 @@ void lut_geometry(const celes_handle* h, double dr, double* lo, int64_t* n) {
                             (mx[2] - mn[2]) * (mx[2] - mn[2]));
     double dlo = std::max(dr, (std::floor(2.0 * rmin / dr) - 1.0) * dr);
     *lo = dlo;
-    *n = (int64_t)std::ceil((dmax - dlo) / dr) + 1;
+    // a single sphere has no pairs: one interval keeps the table well formed
+    *n = std::max<int64_t>(1, (int64_t)std::ceil((dmax - dlo) / dr) + 1);
 }
 
 int build_lut(celes_handle* h) {
@@ -541,7 +542,7 @@ int celes_version(void) { return CELES_VERSION; }
 
 const char* celes_last_error(const celes_handle* h) { return h ? h->err.c_str() : g_create_error.c_str(); }
 
-int celes_create(celes_handle** out, int64_t N, const double* pos, const double* radius, const double* n_sphere,
+static int celes_create_impl(celes_handle** out, int64_t N, const double* pos, const double* radius, const double* n_sphere,
                  double n0, double wavelength, int lmax, const celes_options* opt) {
     if (!out) return fail(nullptr, CELES_E_ARG, "null handle pointer");
     *out = nullptr;
@@ -639,6 +640,11 @@ int celes_create(celes_handle** out, int64_t N, const double* pos, const double*
     *out = h.release();
     return CELES_OK;
 }
+int celes_create(celes_handle** out, int64_t N, const double* pos, const double* radius, const double* n_sphere,
+                 double n0, double wavelength, int lmax, const celes_options* opt) {
+    return celes_guard([&] { return celes_create_impl(out, N, pos, radius, n_sphere, n0, wavelength, lmax, opt); });
+}
+
 
 void celes_destroy(celes_handle* h) { delete h; }
 
@@ -660,7 +666,7 @@ int celes_lut_info(const celes_handle* h, double* d_lo, double* dr, int64_t* n_i
 
 int celes_num_rhs(const celes_handle* h) { return h ? h->K : 0; }
 
-int celes_set_plane_waves(celes_handle* h, int K, const double* beta, const double* alpha, const int* pol,
+static int celes_set_plane_waves_impl(celes_handle* h, int K, const double* beta, const double* alpha, const int* pol,
                           const double* E0) {
     if (!h) return CELES_E_ARG;
     if (K < 1 || !beta || !alpha || !pol) return fail(h, CELES_E_ARG, "K < 1 or null array");
@@ -697,8 +703,13 @@ int celes_set_plane_waves(celes_handle* h, int K, const double* beta, const doub
     for (int kk = 0; kk < K; ++kk) h->pw_E0[kk] = E0 ? cplx(E0[2 * kk], E0[2 * kk + 1]) : cplx(1, 0);
     return CELES_OK;
 }
+int celes_set_plane_waves(celes_handle* h, int K, const double* beta, const double* alpha, const int* pol,
+                          const double* E0) {
+    return celes_guard([&] { return celes_set_plane_waves_impl(h, K, beta, alpha, pol, E0); });
+}
 
-int celes_set_gaussian_beam(celes_handle* h, double waist, const double* focus, double alpha_G, double E0_re,
+
+static int celes_set_gaussian_beam_impl(celes_handle* h, double waist, const double* focus, double alpha_G, double E0_re,
                             double E0_im, int n_beta) {
     if (!h) return CELES_E_ARG;
     if (!(waist > 0) || !focus) return fail(h, CELES_E_ARG, "waist must be positive and focus non-null");
@@ -783,15 +794,24 @@ int celes_set_gaussian_beam(celes_handle* h, double waist, const double* focus, 
     h->g_E0 = E0;
     return CELES_OK;
 }
+int celes_set_gaussian_beam(celes_handle* h, double waist, const double* focus, double alpha_G, double E0_re,
+                            double E0_im, int n_beta) {
+    return celes_guard([&] { return celes_set_gaussian_beam_impl(h, waist, focus, alpha_G, E0_re, E0_im, n_beta); });
+}
 
-int celes_get_incident(const celes_handle* h, double* a_out) {
+
+static int celes_get_incident_impl(const celes_handle* h, double* a_out) {
     if (!h || !a_out) return CELES_E_ARG;
     if (h->K < 1) return CELES_E_STATE;
     std::memcpy(a_out, h->a_in.data(), h->a_in.size() * sizeof(cplx));
     return CELES_OK;
 }
+int celes_get_incident(const celes_handle* h, double* a_out) {
+    return celes_guard([&] { return celes_get_incident_impl(h, a_out); });
+}
 
-int celes_apply_W(celes_handle* h, int precision, int K, const void* x_dev, void* y_dev, void* stream) {
+
+static int celes_apply_W_impl(celes_handle* h, int precision, int K, const void* x_dev, void* y_dev, void* stream) {
     if (!h) return CELES_E_ARG;
     if (K < 1 || !x_dev || !y_dev) return fail(h, CELES_E_ARG, "K < 1 or null device pointer");
     hipStream_t s = (hipStream_t)stream;
@@ -799,8 +819,12 @@ int celes_apply_W(celes_handle* h, int precision, int K, const void* x_dev, void
     if (precision == CELES_MIXED) return matvec<float>(h, (const cx<float>*)x_dev, (cx<float>*)y_dev, K, 0, s);
     return fail(h, CELES_E_ARG, "unknown precision");
 }
+int celes_apply_W(celes_handle* h, int precision, int K, const void* x_dev, void* y_dev, void* stream) {
+    return celes_guard([&] { return celes_apply_W_impl(h, precision, K, x_dev, y_dev, stream); });
+}
 
-int celes_apply_M(celes_handle* h, int precision, int K, const void* x_dev, void* y_dev, void* stream) {
+
+static int celes_apply_M_impl(celes_handle* h, int precision, int K, const void* x_dev, void* y_dev, void* stream) {
     if (!h) return CELES_E_ARG;
     if (K < 1 || !x_dev || !y_dev) return fail(h, CELES_E_ARG, "K < 1 or null device pointer");
     hipStream_t s = (hipStream_t)stream;
@@ -808,8 +832,12 @@ int celes_apply_M(celes_handle* h, int precision, int K, const void* x_dev, void
     if (precision == CELES_MIXED) return matvec<float>(h, (const cx<float>*)x_dev, (cx<float>*)y_dev, K, 1, s);
     return fail(h, CELES_E_ARG, "unknown precision");
 }
+int celes_apply_M(celes_handle* h, int precision, int K, const void* x_dev, void* y_dev, void* stream) {
+    return celes_guard([&] { return celes_apply_M_impl(h, precision, K, x_dev, y_dev, stream); });
+}
 
-int celes_build_preconditioner(celes_handle* h, double cuboid_edge) {
+
+static int celes_build_preconditioner_impl(celes_handle* h, double cuboid_edge) {
     if (!h) return CELES_E_ARG;
     h->pre.reset();
     if (!(cuboid_edge > 0)) return CELES_OK;
@@ -822,8 +850,12 @@ int celes_build_preconditioner(celes_handle* h, double cuboid_edge) {
     h->pre = std::move(p);
     return CELES_OK;
 }
+int celes_build_preconditioner(celes_handle* h, double cuboid_edge) {
+    return celes_guard([&] { return celes_build_preconditioner_impl(h, cuboid_edge); });
+}
 
-int celes_solve(celes_handle* h, const double* x0, double* b_out, celes_solve_info* info) {
+
+static int celes_solve_impl(celes_handle* h, const double* x0, double* b_out, celes_solve_info* info) {
     if (!h) return CELES_E_ARG;
     if (h->K < 1) return fail(h, CELES_E_STATE, "no incident field set");
     const bool mixed = h->opt.precision == CELES_MIXED;
@@ -945,8 +977,12 @@ int celes_solve(celes_handle* h, const double* x0, double* b_out, celes_solve_in
     if (status == CELES_E_BREAKDOWN) h->err = "GMRES breakdown (non-finite iterate)";
     return status;
 }
+int celes_solve(celes_handle* h, const double* x0, double* b_out, celes_solve_info* info) {
+    return celes_guard([&] { return celes_solve_impl(h, x0, b_out, info); });
+}
 
-int celes_mie_coefficients(int lmax, double kR, double m_re, double m_im, double* Q_out) {
+
+static int celes_mie_coefficients_impl(int lmax, double kR, double m_re, double m_im, double* Q_out) {
     if (lmax < 1 || !(kR > 0) || !Q_out) return CELES_E_ARG;
     std::vector<cplx> q1(lmax), q2(lmax);
     celes::mie_Q(lmax, kR, cplx(m_re, m_im), q1.data(), q2.data());
@@ -958,8 +994,12 @@ int celes_mie_coefficients(int lmax, double kR, double m_re, double m_im, double
     }
     return CELES_OK;
 }
+int celes_mie_coefficients(int lmax, double kR, double m_re, double m_im, double* Q_out) {
+    return celes_guard([&] { return celes_mie_coefficients_impl(lmax, kR, m_re, m_im, Q_out); });
+}
 
-int celes_translation_tables(int lmax, double* a5_out, double* b5im_out) {
+
+static int celes_translation_tables_impl(int lmax, double* a5_out, double* b5im_out) {
     if (lmax < 1 || lmax > CELES_MAX_LMAX || !a5_out || !b5im_out) return CELES_E_ARG;
     const int W = 2 * lmax + 1;
     for (int l = 1; l <= lmax; ++l)
@@ -974,6 +1014,10 @@ int celes_translation_tables(int lmax, double* a5_out, double* b5im_out) {
                     }
     return CELES_OK;
 }
+int celes_translation_tables(int lmax, double* a5_out, double* b5im_out) {
+    return celes_guard([&] { return celes_translation_tables_impl(lmax, a5_out, b5im_out); });
+}
+
 
 // ---------------------------------------------------------------------------
 // observables (Appendix D and the SVWF definitions of Appendix A.1)
@@ -1032,7 +1076,7 @@ static void svwf3(int L, double k, const double* r, int tau, int l, int m, cplx 
     }
 }
 
-int celes_far_field(celes_handle* h, int64_t ndir, const double* theta, const double* phi, double* F_out) {
+static int celes_far_field_impl(celes_handle* h, int64_t ndir, const double* theta, const double* phi, double* F_out) {
     if (!h) return CELES_E_ARG;
     if (!h->have_solution) return fail(h, CELES_E_STATE, "no solution");
     if (ndir < 0 || (ndir > 0 && (!theta || !phi || !F_out))) return fail(h, CELES_E_ARG, "bad direction arrays");
@@ -1049,8 +1093,12 @@ int celes_far_field(celes_handle* h, int64_t ndir, const double* theta, const do
     }
     return CELES_OK;
 }
+int celes_far_field(celes_handle* h, int64_t ndir, const double* theta, const double* phi, double* F_out) {
+    return celes_guard([&] { return celes_far_field_impl(h, ndir, theta, phi, F_out); });
+}
 
-int celes_cross_sections(celes_handle* h, double* C_ext, double* C_sca, double* C_abs) {
+
+static int celes_cross_sections_impl(celes_handle* h, double* C_ext, double* C_sca, double* C_abs) {
     if (!h) return CELES_E_ARG;
     if (!h->have_solution) return fail(h, CELES_E_STATE, "no solution");
     const int64_t N = h->N;
@@ -1099,8 +1147,12 @@ int celes_cross_sections(celes_handle* h, double* C_ext, double* C_sca, double* 
     }
     return CELES_OK;
 }
+int celes_cross_sections(celes_handle* h, double* C_ext, double* C_sca, double* C_abs) {
+    return celes_guard([&] { return celes_cross_sections_impl(h, C_ext, C_sca, C_abs); });
+}
 
-int celes_near_field(celes_handle* h, int64_t npt, const double* pts, int add_incident, double* E_out) {
+
+static int celes_near_field_impl(celes_handle* h, int64_t npt, const double* pts, int add_incident, double* E_out) {
     if (!h) return CELES_E_ARG;
     if (!h->have_solution) return fail(h, CELES_E_STATE, "no solution");
     if (npt < 0 || (npt > 0 && (!pts || !E_out))) return fail(h, CELES_E_ARG, "bad point arrays");
@@ -1166,6 +1218,10 @@ int celes_near_field(celes_handle* h, int64_t npt, const double* pts, int add_in
     }
     return CELES_OK;
 }
+int celes_near_field(celes_handle* h, int64_t npt, const double* pts, int add_incident, double* E_out) {
+    return celes_guard([&] { return celes_near_field_impl(h, npt, pts, add_incident, E_out); });
+}
+
 
 }  // extern "C"
 
@@ -1478,7 +1534,7 @@ int batch_gmres(celes_batch* b, const cx<T>* rhs, cx<T>* d, cx<T>* tmp, double t
 
 extern "C" {
 
-int celes_batch_create(celes_batch** out, int nprob, celes_handle* const* probs, const celes_options* opt) {
+static int celes_batch_create_impl(celes_batch** out, int nprob, celes_handle* const* probs, const celes_options* opt) {
     if (!out) return bfail(nullptr, CELES_E_ARG, "null batch pointer");
     *out = nullptr;
     if (nprob < 1 || !probs) return bfail(nullptr, CELES_E_ARG, "empty batch");
@@ -1580,6 +1636,10 @@ int celes_batch_create(celes_batch** out, int nprob, celes_handle* const* probs,
     *out = b.release();
     return CELES_OK;
 }
+int celes_batch_create(celes_batch** out, int nprob, celes_handle* const* probs, const celes_options* opt) {
+    return celes_guard([&] { return celes_batch_create_impl(out, nprob, probs, opt); });
+}
+
 
 void celes_batch_destroy(celes_batch* b) { delete b; }
 
@@ -1587,7 +1647,7 @@ int celes_batch_num_systems(const celes_batch* b) { return b ? b->nsys : 0; }
 
 const char* celes_batch_last_error(const celes_batch* b) { return b ? b->err.c_str() : g_create_error.c_str(); }
 
-int celes_batch_apply_M(celes_batch* b, int precision, const void* x_dev, void* y_dev, void* stream) {
+static int celes_batch_apply_M_impl(celes_batch* b, int precision, const void* x_dev, void* y_dev, void* stream) {
     if (!b || !x_dev || !y_dev) return bfail(b, CELES_E_ARG, "null argument");
     hipStream_t s = (hipStream_t)stream;
     std::vector<int> ones(b->nsys, 1);
@@ -1596,8 +1656,12 @@ int celes_batch_apply_M(celes_batch* b, int precision, const void* x_dev, void* 
     if (precision == CELES_MIXED) return batch_matvec<float>(b, (const cx<float>*)x_dev, nullptr, 0, (cx<float>*)y_dev, 0, 1, s);
     return bfail(b, CELES_E_ARG, "unknown precision");
 }
+int celes_batch_apply_M(celes_batch* b, int precision, const void* x_dev, void* y_dev, void* stream) {
+    return celes_guard([&] { return celes_batch_apply_M_impl(b, precision, x_dev, y_dev, stream); });
+}
 
-int celes_batch_autotune(celes_batch* b, int precision, double* best_ms, int* best_chunk, int* best_kb) {
+
+static int celes_batch_autotune_impl(celes_batch* b, int precision, double* best_ms, int* best_chunk, int* best_kb) {
     if (!b) return CELES_E_ARG;
     const bool f64 = precision == CELES_FP64;
     const int mxkb = f64 ? celes::wx_max_kb<double>(b->L) : celes::wx_max_kb<float>(b->L);
@@ -1652,8 +1716,12 @@ int celes_batch_autotune(celes_batch* b, int precision, double* best_ms, int* be
     if (best_kb) *best_kb = bk;
     return rc;
 }
+int celes_batch_autotune(celes_batch* b, int precision, double* best_ms, int* best_chunk, int* best_kb) {
+    return celes_guard([&] { return celes_batch_autotune_impl(b, precision, best_ms, best_chunk, best_kb); });
+}
 
-int celes_batch_solve(celes_batch* b, celes_solve_info* infos, celes_solve_info* summary) {
+
+static int celes_batch_solve_impl(celes_batch* b, celes_solve_info* infos, celes_solve_info* summary) {
     if (!b) return CELES_E_ARG;
     hipStream_t s = b->stream;
     const int nsys = b->nsys;
@@ -1788,12 +1856,20 @@ int celes_batch_solve(celes_batch* b, celes_solve_info* infos, celes_solve_info*
     if (status == CELES_E_NOCONV) b->err = "batched solve did not reach the tolerance";
     return status;
 }
+int celes_batch_solve(celes_batch* b, celes_solve_info* infos, celes_solve_info* summary) {
+    return celes_guard([&] { return celes_batch_solve_impl(b, infos, summary); });
+}
 
-int celes_get_solution(const celes_handle* h, double* b_out) {
+
+static int celes_get_solution_impl(const celes_handle* h, double* b_out) {
     if (!h || !b_out) return CELES_E_ARG;
     if (!h->have_solution) return CELES_E_STATE;
     std::memcpy(b_out, h->b.data(), h->b.size() * sizeof(cplx));
     return CELES_OK;
 }
+int celes_get_solution(const celes_handle* h, double* b_out) {
+    return celes_guard([&] { return celes_get_solution_impl(h, b_out); });
+}
+
 
 }  // extern "C"

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <memory>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -11,6 +12,20 @@
 #include "device_common.hpp"
 #include "host_math.hpp"
 #include "precond.hpp"
+
+// No C++ exception crosses the C ABI: every entry point that allocates on
+// the host runs its body through this guard (host allocation failure ->
+// CELES_E_OOM, anything else -> CELES_E_DEVICE).
+template <typename F>
+int celes_guard(F&& body) noexcept {
+    try {
+        return body();
+    } catch (const std::bad_alloc&) {
+        return CELES_E_OOM;
+    } catch (...) {
+        return CELES_E_DEVICE;
+    }
+}
 
 namespace celes {
 

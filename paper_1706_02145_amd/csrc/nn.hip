@@ -494,7 +494,7 @@ int nn_features(celes_nn* n, celes_handle* h, int64_t row0, unsigned short* X, f
 
 extern "C" {
 
-int celes_nn_create(celes_nn** out, int lmax, uint64_t seed) {
+static int celes_nn_create_impl(celes_nn** out, int lmax, uint64_t seed) {
     if (!out || lmax < 1 || lmax > CELES_MAX_LMAX) return CELES_E_ARG;
     std::unique_ptr<celes_nn> n(new celes_nn());
     n->L = lmax;
@@ -540,6 +540,10 @@ int celes_nn_create(celes_nn** out, int lmax, uint64_t seed) {
     *out = n.release();
     return CELES_OK;
 }
+int celes_nn_create(celes_nn** out, int lmax, uint64_t seed) {
+    return celes_guard([&] { return celes_nn_create_impl(out, lmax, seed); });
+}
+
 
 void celes_nn_destroy(celes_nn* n) { delete n; }
 
@@ -557,12 +561,16 @@ int celes_nn_dims(const celes_nn* n, int* in_dim, int* in_pad, int* hidden, int*
     return CELES_OK;
 }
 
-int celes_nn_get_params(const celes_nn* n, float* p) {
+static int celes_nn_get_params_impl(const celes_nn* n, float* p) {
     if (!n || !p) return CELES_E_ARG;
     return hipMemcpy(p, n->w32.p, n->nparam * 4, hipMemcpyDeviceToHost) == hipSuccess ? CELES_OK : CELES_E_DEVICE;
 }
+int celes_nn_get_params(const celes_nn* n, float* p) {
+    return celes_guard([&] { return celes_nn_get_params_impl(n, p); });
+}
 
-int celes_nn_set_params(celes_nn* n, const float* p) {
+
+static int celes_nn_set_params_impl(celes_nn* n, const float* p) {
     if (!n || !p) return CELES_E_ARG;
     if (hipMemcpy(n->w32.p, p, n->nparam * 4, hipMemcpyHostToDevice) != hipSuccess) return CELES_E_DEVICE;
     hipLaunchKernelGGL(to_bf16, dim3(nb(n->nparam)), dim3(256), 0, 0, n->w32.as<float>(), n->wbf.as<unsigned short>(),
@@ -572,8 +580,12 @@ int celes_nn_set_params(celes_nn* n, const float* p) {
     n->adam_t = 0;
     return hipDeviceSynchronize() == hipSuccess ? CELES_OK : CELES_E_DEVICE;
 }
+int celes_nn_set_params(celes_nn* n, const float* p) {
+    return celes_guard([&] { return celes_nn_set_params_impl(n, p); });
+}
 
-int celes_nn_loss_grad(celes_nn* n, int64_t M, const float* X, const float* Y, double* loss, float* grad) {
+
+static int celes_nn_loss_grad_impl(celes_nn* n, int64_t M, const float* X, const float* Y, double* loss, float* grad) {
     if (!n || M < 1 || !X || !Y) return CELES_E_ARG;
     const int64_t Mp = round_up((int)M, TM);
     std::vector<unsigned short> xb(Mp * n->in_pad, 0);
@@ -591,8 +603,12 @@ int celes_nn_loss_grad(celes_nn* n, int64_t M, const float* X, const float* Y, d
     if (grad) hipMemcpy(grad, n->grad.p, n->nparam * 4, hipMemcpyDeviceToHost);
     return hipGetLastError() == hipSuccess ? CELES_OK : CELES_E_DEVICE;
 }
+int celes_nn_loss_grad(celes_nn* n, int64_t M, const float* X, const float* Y, double* loss, float* grad) {
+    return celes_guard([&] { return celes_nn_loss_grad_impl(n, M, X, Y, loss, grad); });
+}
 
-int celes_nn_forward(celes_nn* n, int64_t M, const float* X, float* Z_out) {
+
+static int celes_nn_forward_impl(celes_nn* n, int64_t M, const float* X, float* Z_out) {
     if (!n || M < 1 || !X || !Z_out) return CELES_E_ARG;
     const int64_t Mp = round_up((int)M, TM);
     std::vector<unsigned short> xb(Mp * n->in_pad, 0);
@@ -607,8 +623,12 @@ int celes_nn_forward(celes_nn* n, int64_t M, const float* X, float* Z_out) {
     std::memcpy(Z_out, z.data(), M * n->out_pad * 4);
     return CELES_OK;
 }
+int celes_nn_forward(celes_nn* n, int64_t M, const float* X, float* Z_out) {
+    return celes_guard([&] { return celes_nn_forward_impl(n, M, X, Z_out); });
+}
 
-int celes_nn_features(celes_nn* n, celes_handle* h, float* X_out, float* Y_out) {
+
+static int celes_nn_features_impl(celes_nn* n, celes_handle* h, float* X_out, float* Y_out) {
     if (!n || !h || h->L != n->L) return CELES_E_ARG;
     celes::DevBuf dx, dy, fr, nbr;
     const int64_t N = h->N;
@@ -623,8 +643,12 @@ int celes_nn_features(celes_nn* n, celes_handle* h, float* X_out, float* Y_out) 
     if (Y_out && h->have_solution) hipMemcpy(Y_out, dy.p, N * n->out_pad * 4, hipMemcpyDeviceToHost);
     return CELES_OK;
 }
+int celes_nn_features(celes_nn* n, celes_handle* h, float* X_out, float* Y_out) {
+    return celes_guard([&] { return celes_nn_features_impl(n, h, X_out, Y_out); });
+}
 
-int celes_nn_add_training_problem(celes_nn* n, celes_handle* h) {
+
+static int celes_nn_add_training_problem_impl(celes_nn* n, celes_handle* h) {
     if (!n || !h || h->L != n->L) return CELES_E_ARG;
     const int64_t N = h->N;
     celes::DevBuf dx, dy, fr, nbr;
@@ -640,8 +664,12 @@ int celes_nn_add_training_problem(celes_nn* n, celes_handle* h) {
     n->dX.release();   // re-upload on the next train call
     return CELES_OK;
 }
+int celes_nn_add_training_problem(celes_nn* n, celes_handle* h) {
+    return celes_guard([&] { return celes_nn_add_training_problem_impl(n, h); });
+}
 
-int celes_nn_train(celes_nn* n, int epochs, int batch, double lr, uint64_t seed, double* loss_out) {
+
+static int celes_nn_train_impl(celes_nn* n, int epochs, int batch, double lr, uint64_t seed, double* loss_out) {
     if (!n || epochs < 1 || batch < TM) return CELES_E_ARG;
     if (n->rows < 1) return nn_fail(n, CELES_E_STATE, "no training data");
     batch = round_up(batch, TM);
@@ -691,8 +719,12 @@ int celes_nn_train(celes_nn* n, int epochs, int batch, double lr, uint64_t seed,
     if (loss_out) *loss_out = last;
     return hipGetLastError() == hipSuccess ? CELES_OK : nn_fail(n, CELES_E_DEVICE, "training kernels failed");
 }
+int celes_nn_train(celes_nn* n, int epochs, int batch, double lr, uint64_t seed, double* loss_out) {
+    return celes_guard([&] { return celes_nn_train_impl(n, epochs, batch, lr, seed, loss_out); });
+}
 
-int celes_nn_predict(celes_nn* n, celes_handle* h, double* x0_out) {
+
+static int celes_nn_predict_impl(celes_nn* n, celes_handle* h, double* x0_out) {
     if (!n || !h || !x0_out || h->L != n->L) return CELES_E_ARG;
     const int64_t N = h->N, Np = round_up((int)N, TM);
     celes::DevBuf dx, fr, nbr, x0;
@@ -706,5 +738,9 @@ int celes_nn_predict(celes_nn* n, celes_handle* h, double* x0_out) {
     if (hipMemcpy(x0_out, x0.p, N * h->nmax * 16, hipMemcpyDeviceToHost) != hipSuccess) return CELES_E_DEVICE;
     return CELES_OK;
 }
+int celes_nn_predict(celes_nn* n, celes_handle* h, double* x0_out) {
+    return celes_guard([&] { return celes_nn_predict_impl(n, h, x0_out); });
+}
+
 
 }  // extern "C"
