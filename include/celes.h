@@ -269,8 +269,7 @@ int celes_batch_solve(celes_batch* b, celes_solve_info* infos, celes_solve_info*
  * x0 (the custom initial condition the paper's solver accepts, Section 4.2).
  * Features of sphere i: R_i/lambda; a_in^i rotated into its own phase
  * frame and normalised; for each of the 16 nearest spheres the relative
- * position/lambda, R_j/lambda and a_in^j in sphere i's frame; the depth
- * (z_i - min z)/lambda below the ensemble's entry face (incidence along +z).
+ * position/lambda, R_j/lambda and a_in^j in sphere i's frame.
  * Layers: in_pad -> 128 -> 128 -> 128 -> out_pad, SiLU, bf16 weights and
  * activations with FP32 accumulation, FP32 master weights, Adam.  It is
  * trained on coefficients the solver produced.  Intended for training sets

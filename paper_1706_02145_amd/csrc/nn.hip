@@ -252,7 +252,6 @@ struct FeatArgs {
     const int* nbr;           // [N][16]
     int n, nmax, nref, in_dim, in_pad, out_pad;
     double inv_lambda;
-    double zmin;              // smallest centre z (depth origin)
     unsigned short* X;        // [rows][in_pad] bf16
     float* Y;                 // [rows][out_pad] fp32 (targets) or null
     cx<double>* frame;        // [N] c_i * ||a_in^i|| (to map predictions back)
@@ -283,7 +282,7 @@ __global__ void build_features(FeatArgs f) {
     } else if (col < self) {
         const int c = (col - 1) / 2;
         val = framed(ai, c, (col - 1) % 2);
-    } else if (col < self + NN_K * per) {
+    } else if (col < f.in_dim) {
         const int q = (col - self) / per, r = (col - self) % per;
         const int j = f.nbr[(int64_t)i * NN_K + q];
         if (j >= 0) {
@@ -296,9 +295,6 @@ __global__ void build_features(FeatArgs f) {
                 val = framed(f.ain + (int64_t)j * f.nmax, c, (r - 4) % 2);
             }
         }
-    } else if (col < f.in_dim) {
-        // depth below the ensemble's entry face z = min z (incidence along +z)
-        val = (f.pz[i] - f.zmin) * f.inv_lambda;
     }
     f.X[t] = f2bf((float)val);
     if (col < f.out_pad && f.Y) {
@@ -480,8 +476,6 @@ int nn_features(celes_nn* n, celes_handle* h, int64_t row0, unsigned short* X, f
     f.in_pad = n->in_pad;
     f.out_pad = n->out_pad;
     f.inv_lambda = n->L > 0 ? h->n0 / h->wavelength : 0.0;
-    f.zmin = h->pos[2];
-    for (int64_t i = 1; i < N; ++i) f.zmin = std::min(f.zmin, h->pos[3 * i + 2]);
     f.X = X + row0 * n->in_pad;
     f.Y = Y ? Y + row0 * n->out_pad : nullptr;
     f.frame = frame.as<cx<double>>();
@@ -499,7 +493,7 @@ static int celes_nn_create_impl(celes_nn** out, int lmax, uint64_t seed) {
     std::unique_ptr<celes_nn> n(new celes_nn());
     n->L = lmax;
     n->nmax = 2 * lmax * (lmax + 2);
-    n->in_dim = 1 + 2 * n->nmax + NN_K * (4 + 2 * n->nmax) + 1;
+    n->in_dim = 1 + 2 * n->nmax + NN_K * (4 + 2 * n->nmax);
     n->in_pad = round_up(n->in_dim, TM);
     n->out_dim = 2 * n->nmax;
     n->out_pad = round_up(n->out_dim, TN);
