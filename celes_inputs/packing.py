@@ -31,7 +31,7 @@ def _cell_key(c):
     return (int(c[0]), int(c[1]), int(c[2]))
 
 
-def rsa_box(seed, radii, box, max_attempts_per_sphere=1000, gap=0.0, inside=True):
+def rsa_box(seed, radii, box, max_attempts_per_sphere=1000, gap=0.0, inside=True, region=None):
     """Random sequential addition of spheres with the given radii into the
     axis-aligned box [0,bx] x [0,by] x [0,bz].  With inside=True every sphere
     lies fully inside the box; with inside=False only the centres do (spheres
@@ -40,7 +40,8 @@ def rsa_box(seed, radii, box, max_attempts_per_sphere=1000, gap=0.0, inside=True
 
     Spheres are placed in the given order.  A candidate centre is drawn
     uniformly in the shrunken box and rejected if it comes within
-    R_i + R_j + gap of an already placed sphere.  Raises RuntimeError after
+    R_i + R_j + gap of an already placed sphere, or if `region` (a predicate
+    on the centre) is given and returns False.  Raises RuntimeError after
     max_attempts_per_sphere * n total rejections.
     Returns positions [n, 3] (float64).
     """
@@ -65,6 +66,8 @@ def rsa_box(seed, radii, box, max_attempts_per_sphere=1000, gap=0.0, inside=True
             if tries > budget:
                 raise RuntimeError("random sequential addition did not finish")
             c = lo + (hi - lo) * rng.random(3)
+            if region is not None and not region(c):
+                continue
             ck = np.floor(c / cell).astype(np.int64)
             ok = True
             for dx in (-1, 0, 1):
@@ -95,3 +98,13 @@ def uniform_box(seed, n, radius, side, gap=0.0):
     """n equal spheres of the given radius, centres uniform with each sphere
     fully inside a cube of the given side, non-overlapping (by rejection)."""
     return rsa_box(seed, np.full(n, float(radius)), (side, side, side), gap=gap)
+
+
+def rsa_cylinder(seed, radii, rcyl, thickness, max_attempts_per_sphere=1000):
+    """Random sequential addition with centres uniform in the cylinder
+    x^2 + y^2 <= rcyl^2, 0 <= z <= thickness (axis z, spheres may protrude by
+    up to their radius).  Returns positions [n, 3] centred on the axis."""
+    side = 2.0 * rcyl
+    pos = rsa_box(seed, radii, (side, side, thickness), max_attempts_per_sphere, inside=False,
+                  region=lambda c: (c[0] - rcyl) ** 2 + (c[1] - rcyl) ** 2 <= rcyl * rcyl)
+    return pos - np.array([rcyl, rcyl, 0.0])

@@ -8,7 +8,7 @@ and the slab thickness, and derive the lateral side from them.
 from dataclasses import dataclass, field
 import numpy as np
 
-from .packing import rsa_box, uniform_box, lognormal_radii, slab_side_for_fraction
+from .packing import rsa_box, rsa_cylinder, uniform_box, lognormal_radii, slab_side_for_fraction
 
 
 @dataclass
@@ -48,6 +48,20 @@ def _slab(name, seed, n, thickness, lmax, n_sph, illumination, tol, vf=0.3,
                     illumination, tol, 1.0, box)
 
 
+def _cylinder(name, seed, n, vf, thickness=2000.0, radius=100.0):
+    """The application setting of the paper's Section 4: monodisperse spheres
+    (R = 100 nm, n = 1.5) at a given volume fraction in a cylindrical slab,
+    lambda = 532 nm, lmax 3, Gaussian beam (waist 4 um) focused on the centre
+    of the entry face, GMRES tolerance 1e-4.  The slab's thickness is not
+    stated there; 2 um is used and the cylinder radius follows from N and vf."""
+    rcyl = float(np.sqrt(n * 4.0 / 3.0 * np.pi * radius ** 3 / (vf * np.pi * thickness)))
+    radii = np.full(n, radius)
+    pos = rsa_cylinder(seed, radii, rcyl, thickness)
+    ill = {"kind": "gaussian", "waist": 4000.0, "focus": (0.0, 0.0, 0.0), "alpha_G": -np.pi / 2, "E0": 1.0}
+    return Workload(name, pos, radii, np.full(n, 1.5 + 0j), 1.0, 532.0, 3, ill, 1e-4, 1.0,
+                    (2 * rcyl, 2 * rcyl, thickness), {"cylinder_radius": rcyl})
+
+
 def _small_cube():
     n, r, side = 8, 100.0, 1000.0
     pos = uniform_box(1, n, r, side)
@@ -67,6 +81,8 @@ def _plane_normal():
 
 
 _BUILDERS = {
+    # the paper's run-time comparison setting (N = 2e4, vf 10 %, cylindrical slab)
+    "paper_cyl20000_vf10": lambda: _cylinder("paper_cyl20000_vf10", 6001, 20000, 0.10),
     # 8 spheres, R = 100 nm, n = 1.5+0.01i, lmax 3, x-polarised plane wave along +z
     "cube8_l3": _small_cube,
     # 2,000-sphere slab, t = 2 um, lmax 4, Gaussian beam w = 2 um, FP64 GMRES 1e-8

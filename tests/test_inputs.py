@@ -33,3 +33,19 @@ def test_rsa_reproducible():
 def test_random_coefficients_shape():
     x = random_coefficients(3, 2, 5, 30)
     assert x.shape == (2, 5, 30) and x.dtype == np.complex128
+
+
+def test_rsa_cylinder_inside_disjoint_and_at_volume_fraction():
+    from celes_inputs.packing import rsa_cylinder
+    radii = np.full(400, 100.0)
+    pos = rsa_cylinder(5, radii, 2000.0, 1000.0)
+    assert np.all(pos[:, 0] ** 2 + pos[:, 1] ** 2 <= 2000.0 ** 2 + 1e-6)
+    assert np.all((pos[:, 2] >= 0) & (pos[:, 2] <= 1000.0))
+    d = np.linalg.norm(pos[:, None] - pos[None], axis=-1) + np.eye(len(pos)) * 1e9
+    assert d.min() > 200.0
+    np.testing.assert_array_equal(pos, rsa_cylinder(5, radii, 2000.0, 1000.0))
+    # the named workload keeps N and vf 0.10 by construction of its radius
+    w = workload("paper_cyl20000_vf10")
+    rc, t = w.extra["cylinder_radius"], w.box[2]
+    vf = w.N * 4 / 3 * np.pi * 100.0 ** 3 / (np.pi * rc * rc * t)
+    assert abs(vf - 0.10) < 1e-9 and w.N == 20000 and w.wavelength == 532.0 and w.lmax == 3
