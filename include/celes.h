@@ -192,6 +192,14 @@ int celes_near_field(celes_handle* h, int64_t npt, const double* pts, int add_in
  * (Q_{1l}, Q_{2l}) complex.  Errors: CELES_E_ARG. */
 int celes_mie_coefficients(int lmax, double kR, double m_re, double m_im, double* Q_out);
 
+/* Kernel timing for measurement: enable = 1 starts recording HIP events on
+ * the launch stream right before and after every coupling kernel that
+ * celes_apply_W / celes_apply_M / celes_solve launch on this handle (the
+ * prep and finish kernels are outside); enable = 0 stops and returns the
+ * average kernel duration in ms and the number of launches (either output may
+ * be NULL).  Errors: CELES_E_ARG, CELES_E_DEVICE. */
+int celes_kernel_timing(celes_handle* h, int enable, double* avg_ms, int* count);
+
 /* Geometry of the Hankel lookup table (Section 3.2.2): nodes d_lo + q*dr,
  * q = 0..n_int; d_lo = max(dr, (floor(2 min R / dr) - 1) dr), n_int =
  * ceil((d_max - d_lo)/dr) + 1 with d_max the diagonal of the centres'

@@ -193,6 +193,13 @@ class Problem:
         _check(lib().celes_get_solution(self._h, _dptr(out.view(np.float64))), self._h)
         return out
 
+    def kernel_timing(self, enable):
+        """Start (enable=True) or stop kernel timing; stopping returns the
+        average coupling-kernel duration in ms and the launch count."""
+        ms, n = C.c_double(0.0), C.c_int(0)
+        _check(lib().celes_kernel_timing(self._h, 1 if enable else 0, C.byref(ms), C.byref(n)), self._h)
+        return None if enable else (ms.value, n.value)
+
     def lut_info(self):
         lo, dr, n = C.c_double(), C.c_double(), C.c_int64()
         _check(lib().celes_lut_info(self._h, C.byref(lo), C.byref(dr), C.byref(n)), self._h)

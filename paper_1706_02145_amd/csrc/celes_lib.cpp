@@ -226,6 +226,21 @@ int pick_kb(int L, int K) {
 }
 
 
+// events for the next coupling-kernel launch when kernel timing is on
+static const hipEvent_t* timing_events(celes_handle* h) {
+    if (!h->time_kernels) return nullptr;
+    if (h->tev_used + 2 > h->tev.size()) {
+        for (int q = 0; q < 2; ++q) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            h->tev.push_back(e);
+        }
+    }
+    const hipEvent_t* ev = h->tev.data() + h->tev_used;
+    h->tev_used += 2;
+    return ev;
+}
+
 // complex64 mat-vec of K = a multiple of 16 right-hand sides on the matrix
 // cores (lmax <= 4)
 static int matvec_mfma(celes_handle* h, const cx<float>* x, cx<float>* y, int K, int width, int epilogue,
@@ -265,7 +280,7 @@ static int matvec_mfma(celes_handle* h, const cx<float>* x, cx<float>* y, int K,
     a.ldp = (int)N;
     a.nrhs = K;
     const int rc = celes::wx_launch_mfma(a, h->L, width, h->opt.hankel == CELES_HANKEL_DIRECT ? 1 : 0, nchunk_eff, x,
-                                         h->d_tq32.as<cx<float>>(), y, epilogue, s);
+                                         h->d_tq32.as<cx<float>>(), y, epilogue, s, timing_events(h));
     if (rc != 0) return fail(h, CELES_E_DEVICE, "matrix-core mat-vec launch failed");
     return CELES_OK;
 }
@@ -321,7 +336,7 @@ int matvec(celes_handle* h, const cx<T>* x, cx<T>* y, int K, int epilogue, hipSt
     a.sys0 = 0;
     const cx<T>* tq = (sizeof(T) == 8) ? (const cx<T>*)h->d_tq64.p : (const cx<T>*)h->d_tq32.p;
     int rc = celes::wx_launch<T>(a, h->L, h->opt.hankel == CELES_HANKEL_DIRECT ? 1 : 0, nchunk_eff, x, tq, y,
-                                 epilogue, s);
+                                 epilogue, s, timing_events(h));
     if (rc == -1) return fail(h, CELES_E_UNSUPPORTED, "lmax not compiled");
     if (rc != 0) return fail(h, CELES_E_DEVICE, "mat-vec launch failed");
     return CELES_OK;
@@ -1860,6 +1875,29 @@ int celes_batch_solve(celes_batch* b, celes_solve_info* infos, celes_solve_info*
     return celes_guard([&] { return celes_batch_solve_impl(b, infos, summary); });
 }
 
+
+int celes_kernel_timing(celes_handle* h, int enable, double* avg_ms, int* count) {
+    if (!h) return CELES_E_ARG;
+    if (enable) {
+        h->time_kernels = true;
+        h->tev_used = 0;
+        return CELES_OK;
+    }
+    double sum = 0;
+    const int n = (int)(h->tev_used / 2);
+    for (int q = 0; q < n; ++q) {
+        float ms = 0;
+        if (hipEventSynchronize(h->tev[2 * q + 1]) != hipSuccess ||
+            hipEventElapsedTime(&ms, h->tev[2 * q], h->tev[2 * q + 1]) != hipSuccess)
+            return fail(h, CELES_E_DEVICE, "kernel timing events failed");
+        sum += ms;
+    }
+    h->time_kernels = false;
+    h->tev_used = 0;
+    if (avg_ms) *avg_ms = n ? sum / n : 0.0;
+    if (count) *count = n;
+    return CELES_OK;
+}
 
 static int celes_get_solution_impl(const celes_handle* h, double* b_out) {
     if (!h || !b_out) return CELES_E_ARG;

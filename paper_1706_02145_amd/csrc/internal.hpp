@@ -93,5 +93,12 @@ struct celes_handle {
     // preconditioner
     std::unique_ptr<celes::BlockPrecond> pre;
     int target_blocks = 0;       // mat-vec work split (0: default); set by the autotuner
+    // celes_kernel_timing: HIP events around each coupling-kernel launch
+    bool time_kernels = false;
+    std::vector<hipEvent_t> tev;  // pairs (begin, end), reused
+    size_t tev_used = 0;
     std::string err;
+    ~celes_handle() {
+        for (hipEvent_t e : tev) (void)hipEventDestroy(e);
+    }
 };

@@ -109,12 +109,13 @@ template int wx_batch_run<float>(int, const WxArgs<float>*, const int*, const in
 
 template <typename T>
 int wx_launch(const WxArgs<T>& a, int L, int hmode, int nchunk, const cx<T>* x, const cx<T>* tq,
-              cx<T>* y, int epilogue, hipStream_t s) {
+              cx<T>* y, int epilogue, hipStream_t s, const hipEvent_t* ev) {
     const int half = L * (L + 2);
     const int64_t tot = (int64_t)a.n * half * a.nrhs;
     hipLaunchKernelGGL(wx_prep_kernel<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, x,
                        const_cast<cx<T>*>(a.xsd), a.n, half, a.nrhs);
-switch (L) {
+    if (ev) hipEventRecord(ev[0], s);
+    switch (L) {
         case 1: wx_run_L<T, 1>(a, hmode, nchunk, s); break;
         case 2: wx_run_L<T, 2>(a, hmode, nchunk, s); break;
         case 3: wx_run_L<T, 3>(a, hmode, nchunk, s); break;
@@ -123,17 +124,17 @@ switch (L) {
         case 6: wx_run_L<T, 6>(a, hmode, nchunk, s); break;
         default: return -1;
     }
-
+    if (ev) hipEventRecord(ev[1], s);
     hipLaunchKernelGGL(wx_finish_kernel<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, a.part, nchunk,
                        a.ldp, a.n, L, a.nrhs, x, tq, y, epilogue);
     return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
 int wx_launch_mfma(const WxMfmaArgs& a, int L, int width, int hmode, int nchunk, const cx<float>* x,
-                   const cx<float>* tq, cx<float>* y, int epilogue, hipStream_t s) {
+                   const cx<float>* tq, cx<float>* y, int epilogue, hipStream_t s, const hipEvent_t* ev) {
     const int half = L * (L + 2);
     const int64_t tot = (int64_t)a.n * half * a.nrhs;
-    const int rc = wx_mfma_launch(a, L, width, hmode, nchunk, s);
+    const int rc = wx_mfma_launch(a, L, width, hmode, nchunk, s, ev);
     if (rc != 0) return rc;
     hipLaunchKernelGGL(wx_finish_kernel<float>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, a.part, nchunk,
                        a.ldp, a.n, L, a.nrhs, x, tq, y, epilogue);
@@ -141,8 +142,8 @@ int wx_launch_mfma(const WxMfmaArgs& a, int L, int width, int hmode, int nchunk,
 }
 
 template int wx_launch<double>(const WxArgs<double>&, int, int, int, const cx<double>*, const cx<double>*,
-                               cx<double>*, int, hipStream_t);
+                               cx<double>*, int, hipStream_t, const hipEvent_t*);
 template int wx_launch<float>(const WxArgs<float>&, int, int, int, const cx<float>*, const cx<float>*,
-                              cx<float>*, int, hipStream_t);
+                              cx<float>*, int, hipStream_t, const hipEvent_t*);
 
 }  // namespace celes

@@ -58,9 +58,10 @@ constexpr int WX_TILE_SIZE = 16;    // sources per LDS tile
 
 // y = W x (epilogue = 0) or y = x - T (W x) (epilogue = 1) for a.nrhs
 // right-hand sides; x, y: [nrhs][N][nmax]; tq: [N][2][L] Mie coefficients.
-// Returns 0 on success.
+// ev[0], ev[1] (if ev is given) are recorded on s right before and after the
+// coupling kernel.  Returns 0 on success.
 template <typename T>
 int wx_launch(const WxArgs<T>& a, int L, int hmode, int nchunk, const cx<T>* x, const cx<T>* tq,
-              cx<T>* y, int epilogue, hipStream_t s);
+              cx<T>* y, int epilogue, hipStream_t s, const hipEvent_t* ev = nullptr);
 
 }  // namespace celes

@@ -419,23 +419,25 @@ __global__ void wx_mfma_prep_kernel(const cx<float>* __restrict__ x0, const int*
 }
 
 template <int L, int NT>
-void launch_nt(const WxMfmaArgs& a, int hmode, int nchunk, hipStream_t s) {
+void launch_nt(const WxMfmaArgs& a, int hmode, int nchunk, hipStream_t s, const hipEvent_t* ev) {
     using S = MShape<L>;
     const int64_t total = (int64_t)a.nrhs * a.n * 2 * S::KS * 64 / 16;
     hipLaunchKernelGGL((wx_mfma_prep_kernel<L, NT>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, a.x,
                        a.kstep, a.kin, a.slot_stride, a.xb, a.n, a.nrhs);
     dim3 grid((unsigned)((a.n + 3) / 4), (unsigned)nchunk, (unsigned)(a.nrhs / (16 * NT)));
+    if (ev) hipEventRecord(ev[0], s);
     if (hmode == 0)
         hipLaunchKernelGGL((wx_mfma_kernel<L, NT, 0>), grid, dim3(256), 0, s, a);
     else
         hipLaunchKernelGGL((wx_mfma_kernel<L, NT, 1>), grid, dim3(256), 0, s, a);
+    if (ev) hipEventRecord(ev[1], s);
 }
 
 template <int L>
-void launch_L(const WxMfmaArgs& a, int width, int hmode, int nchunk, hipStream_t s) {
-    if (width == 64) launch_nt<L, 4>(a, hmode, nchunk, s);
-    else if (width == 32) launch_nt<L, 2>(a, hmode, nchunk, s);
-    else launch_nt<L, 1>(a, hmode, nchunk, s);
+void launch_L(const WxMfmaArgs& a, int width, int hmode, int nchunk, hipStream_t s, const hipEvent_t* ev) {
+    if (width == 64) launch_nt<L, 4>(a, hmode, nchunk, s, ev);
+    else if (width == 32) launch_nt<L, 2>(a, hmode, nchunk, s, ev);
+    else launch_nt<L, 1>(a, hmode, nchunk, s, ev);
 }
 
 }  // namespace
@@ -456,14 +458,15 @@ int wx_mfma_block(int L, int K, bool any) {
     return 0;
 }
 
-int wx_mfma_launch(const WxMfmaArgs& a, int L, int width, int hmode, int nchunk, hipStream_t s) {
+int wx_mfma_launch(const WxMfmaArgs& a, int L, int width, int hmode, int nchunk, hipStream_t s,
+                   const hipEvent_t* ev) {
     if (wx_mfma_block(L, a.nrhs, true) == 0 || (width != 16 && width != 32 && width != 64) || a.nrhs % width)
         return -1;
     switch (L) {
-        case 1: launch_L<1>(a, width, hmode, nchunk, s); break;
-        case 2: launch_L<2>(a, width, hmode, nchunk, s); break;
-        case 3: launch_L<3>(a, width, hmode, nchunk, s); break;
-        case 4: launch_L<4>(a, width, hmode, nchunk, s); break;
+        case 1: launch_L<1>(a, width, hmode, nchunk, s, ev); break;
+        case 2: launch_L<2>(a, width, hmode, nchunk, s, ev); break;
+        case 3: launch_L<3>(a, width, hmode, nchunk, s, ev); break;
+        case 4: launch_L<4>(a, width, hmode, nchunk, s, ev); break;
         default: return -1;
     }
     return hipGetLastError() == hipSuccess ? 0 : -2;

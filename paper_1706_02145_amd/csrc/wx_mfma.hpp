@@ -50,12 +50,14 @@ size_t wx_mfma_xb_floats(int L, int64_t N, int K);
 int wx_mfma_block(int L, int K, bool any = false);
 
 // Prep (x -> operand-ordered xb) and the kernel on grid (ceil(N / 4),
-// nchunk, nrhs / width); returns 0, -1 (not applicable) or -2 (launch error)
-int wx_mfma_launch(const WxMfmaArgs& a, int L, int width, int hmode, int nchunk, hipStream_t s);
+// nchunk, nrhs / width), with ev[0], ev[1] (if given) recorded around the
+// kernel; returns 0, -1 (not applicable) or -2 (launch error)
+int wx_mfma_launch(const WxMfmaArgs& a, int L, int width, int hmode, int nchunk, hipStream_t s,
+                   const hipEvent_t* ev = nullptr);
 
 // wx_mfma_launch, then the chunk reduction with the optional
 // y = x - T (W x) epilogue; x, y: [nrhs][N][nmax] complex64
 int wx_launch_mfma(const WxMfmaArgs& a, int L, int width, int hmode, int nchunk, const cx<float>* x,
-                   const cx<float>* tq, cx<float>* y, int epilogue, hipStream_t s);
+                   const cx<float>* tq, cx<float>* y, int epilogue, hipStream_t s, const hipEvent_t* ev = nullptr);
 
 }  // namespace celes
