@@ -78,3 +78,66 @@ def scattered_field(k, pos, b, L, points):
             if b[i, c] != 0:
                 E += b[i, c] * svwf(3, tau, l, m, pts - pos[i], k)
     return E
+
+
+def gaussian_spectrum(k, waist, focus, alpha_G, E0, beta, alpha):
+    """Plane-wave pattern (g_alpha, g_beta) of the Gaussian beam of Appendix C
+    in direction (beta, alpha), beta < pi/2: the amplitude
+    E0 k^2 w^2/(4 pi) cos(beta) exp(-(w k sin(beta))^2 / 4), polarisation
+    cos(alpha - alpha_G) e_alpha + sin(alpha - alpha_G) e_beta, and the phase
+    exp(-i k.r_G) of the focus (the same spectrum as gaussian_beam_field)."""
+    sb, cb = np.sin(beta), np.cos(beta)
+    g = E0 * k * k * waist * waist / (4 * np.pi) * cb * np.exp(-(waist * k * sb) ** 2 / 4)
+    kr = k * (sb * np.cos(alpha) * focus[0] + sb * np.sin(alpha) * focus[1] + cb * focus[2])
+    ph = np.exp(-1j * kr)
+    return g * np.cos(alpha - alpha_G) * ph, g * np.sin(alpha - alpha_G) * ph
+
+
+def power_flux(k, pos, b, L, tvec, waist, focus, alpha_G, E0=1.0, n_beam=64, n_beta=None, n_alpha=None):
+    """Reflected, transmitted and absorbed fractions of a Gaussian beam's power
+    (Appendix D).  A field sum_j int dalpha int dbeta sin(beta) g_j Phi_j
+    carries the power P = 2 pi^2/(omega k mu0) sum_j oint |g_j|^2 dOmega.  At
+    large r a plane-wave superposition tends to -2 pi i e^{ikr}/(kr) g(rhat)
+    (stationary phase), so the scattered field E -> e^{ikr}/(kr) F has the
+    pattern g_sca = (i / 2 pi) F.  Upper hemisphere: g_in + g_sca (transmitted),
+    lower hemisphere: g_sca (reflected).  Absorbed power from the Mie
+    coefficients as in `absorption`.  Returns (P_inc / I_0 with I_0 the
+    intensity of a unit plane wave, R, T, A)."""
+    pos = np.asarray(pos, dtype=np.float64)
+    D = 2.0 * float(np.max(np.linalg.norm(pos, axis=1)))
+    band = int(L + k * D) + 10
+    nb = n_beta or band + 1
+    na = n_alpha or 2 * band + 2
+    b1 = min(np.pi / 2, float(np.arcsin(min(1.0, 8.0 / (k * waist)))))
+
+    def gl(a, c, n):
+        x, w = np.polynomial.legendre.leggauss(n)
+        return 0.5 * (c - a) * (x + 1) + a, 0.5 * (c - a) * w
+
+    parts = [gl(0.0, b1, n_beam)]
+    if b1 < np.pi / 2:
+        parts.append(gl(b1, np.pi / 2, nb))
+    bf = np.concatenate([p[0] for p in parts])
+    wf = np.concatenate([p[1] for p in parts])
+    bb, wb = gl(np.pi / 2, np.pi, nb)
+    alpha = 2 * np.pi * np.arange(na) / na
+    wa = 2 * np.pi / na
+
+    def pattern(beta):
+        BB, AA = np.meshgrid(beta, alpha, indexing="ij")
+        F = far_field(k, pos, b, L, BB.reshape(-1), AA.reshape(-1)).reshape(BB.shape + (3,))
+        ea = np.stack([-np.sin(AA), np.cos(AA), np.zeros_like(AA)], -1)
+        eb = np.stack([np.cos(BB) * np.cos(AA), np.cos(BB) * np.sin(AA), -np.sin(BB)], -1)
+        return BB, AA, 1j / (2 * np.pi) * np.sum(F * ea, -1), 1j / (2 * np.pi) * np.sum(F * eb, -1)
+
+    BB, AA, sa, sb_ = pattern(bf)
+    ga, gb = gaussian_spectrum(k, waist, focus, alpha_G, E0, BB, AA)
+    wf2 = (wf * np.sin(bf))[:, None] * wa
+    P0 = float(np.sum(wf2 * (np.abs(ga) ** 2 + np.abs(gb) ** 2)))
+    T = float(np.sum(wf2 * (np.abs(ga + sa) ** 2 + np.abs(gb + sb_) ** 2))) / P0
+    _, _, ra, rb = pattern(bb)
+    R = float(np.sum((wb * np.sin(bb))[:, None] * wa * (np.abs(ra) ** 2 + np.abs(rb) ** 2))) / P0
+    with np.errstate(divide="ignore", invalid="ignore"):
+        f = np.where(tvec != 0, np.real(1.0 / tvec) + 1.0, 0.0)
+    A = -float(np.sum(np.abs(b) ** 2 * f)) / (4 * np.pi) / P0
+    return 4 * np.pi ** 2 / k ** 2 * P0, R, T, A
