@@ -79,15 +79,20 @@ def flops_per_pair(L, hankel_lut=True):
 
 
 def kernel_source_digest():
-    """sha256 of the coupling-kernel sources and of the host code that sizes
-    its launch (counters are only valid for them)."""
+    """sha256 of what fixes the coupling kernel and its launch: the kernel
+    sources and the host mat-vec driver that sizes the launch (counters are
+    only valid for them)."""
     import hashlib
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_1706_02145_amd", "csrc")
-    for f in ("wx_kernels.hip", "wx_plan.hpp", "wx_launch.hpp", "device_common.hpp", "wx_dispatch.hip",
-              "celes_lib.cpp"):
+    for f in ("wx_kernels.hip", "wx_plan.hpp", "wx_launch.hpp", "device_common.hpp", "wx_dispatch.hip"):
         with open(os.path.join(d, f), "rb") as fh:
             h.update(fh.read())
+    with open(os.path.join(d, "celes_lib.cpp"), encoding="utf-8") as fh:
+        src = fh.read()
+    a = src.index("// right-hand-side block width: largest compiled width")
+    b = src.index("// GMRES (right-preconditioned", a)
+    h.update(src[a:b].encode())
     return h.hexdigest()
 
 

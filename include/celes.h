@@ -192,6 +192,18 @@ int celes_near_field(celes_handle* h, int64_t npt, const double* pts, int add_in
  * (Q_{1l}, Q_{2l}) complex.  Errors: CELES_E_ARG. */
 int celes_mie_coefficients(int lmax, double kR, double m_re, double m_im, double* Q_out);
 
+/* Power balance of the last solution under a Gaussian beam (Appendix D),
+ * per right-hand side: out[4k + 0] = incident power divided by the
+ * intensity of a unit plane wave (area units), out[4k + 1] = reflected
+ * fraction R (scattered flux through the lower hemisphere at infinity),
+ * out[4k + 2] = transmitted fraction T (flux of incident + scattered field
+ * through the upper hemisphere), out[4k + 3] = absorbed fraction A; energy
+ * conservation gives R + T + A = 1.  n_beta, n_alpha: polar nodes per
+ * hemisphere and azimuthal nodes (<= 0: from the band limit lmax + k D,
+ * D = 2 max |r_i|).  Errors: CELES_E_STATE (no solution, or the incident
+ * field is not a Gaussian beam), CELES_E_ARG. */
+int celes_power_flux(celes_handle* h, int n_beta, int n_alpha, double* out);
+
 /* Kernel timing for measurement: enable = 1 starts recording HIP events on
  * the launch stream right before and after every coupling kernel that
  * celes_apply_W / celes_apply_M / celes_solve launch on this handle (the

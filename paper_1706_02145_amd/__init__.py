@@ -174,6 +174,13 @@ class Problem:
         _check(lib().celes_cross_sections(self._h, _dptr(ce), _dptr(cs), _dptr(ca)), self._h)
         return ce, cs, ca
 
+    def power_flux(self, n_beta=0, n_alpha=0):
+        """Per right-hand side (P_inc / I_0, R, T, A) of the last solution under
+        a Gaussian beam; R + T + A = 1."""
+        out = np.zeros((self.num_rhs, 4))
+        _check(lib().celes_power_flux(self._h, int(n_beta), int(n_alpha), _dptr(out)), self._h)
+        return out
+
     def far_field(self, theta, phi):
         th = np.ascontiguousarray(np.atleast_1d(theta), dtype=np.float64)
         ph = np.ascontiguousarray(np.atleast_1d(phi), dtype=np.float64)

@@ -55,6 +55,7 @@ SIGNATURES = {
     "celes_mie_coefficients": (C.c_int, [C.c_int, C.c_double, C.c_double, C.c_double, _dp]),
     "celes_lut_info": (C.c_int, [_h, _dp, _dp, C.POINTER(C.c_int64)]),
     "celes_kernel_timing": (C.c_int, [_h, C.c_int, _dp, C.POINTER(C.c_int)]),
+    "celes_power_flux": (C.c_int, [_h, C.c_int, C.c_int, _dp]),
     "celes_dims": (C.c_int, [_h, C.POINTER(C.c_int64), _ip, _ip]),
     "celes_translation_tables": (C.c_int, [C.c_int, _dp, _dp]),
     "celes_get_solution": (C.c_int, [_h, _dp]),

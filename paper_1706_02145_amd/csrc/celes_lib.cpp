@@ -1167,6 +1167,95 @@ int celes_cross_sections(celes_handle* h, double* C_ext, double* C_sca, double* 
 }
 
 
+// Power flux of a Gaussian beam (Appendix D): the transmitted power is the
+// flux of g_in + g_sca through the upper hemisphere at infinity, the reflected
+// power that of g_sca through the lower one, with g_sca = (i / 2 pi) F the
+// stationary-phase pattern of E_sca -> e^{ikr}/(kr) F; absorbed power from
+// the Mie coefficients.  Quadrature: Gauss-Legendre in the polar angle (a
+// dense set inside the beam's cone sin(beta) < 8/(k w), band-limited sets
+// elsewhere), uniform in the azimuth.
+static int celes_power_flux_impl(celes_handle* h, int n_beta, int n_alpha, double* out) {
+    if (!h || !out) return CELES_E_ARG;
+    if (!h->have_solution) return fail(h, CELES_E_STATE, "no solution");
+    if (!h->gaussian) return fail(h, CELES_E_STATE, "power flux needs a Gaussian beam (finite incident power)");
+    const int64_t N = h->N;
+    const int nm = h->nmax, L = h->L;
+    const double k = h->k, w = h->g_waist;
+    double D = 0;
+    for (int64_t i = 0; i < N; ++i) {
+        const double* r = &h->pos[3 * i];
+        D = std::max(D, 2.0 * std::sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]));
+    }
+    const int band = (int)(L + k * D) + 10;
+    const int nb = n_beta > 0 ? n_beta : band + 1;
+    const int na = n_alpha > 0 ? n_alpha : 2 * band + 2;
+    const int nbeam = 64;
+    const double b1 = std::min(M_PI / 2, std::asin(std::min(1.0, 8.0 / (k * w))));
+    // polar nodes and weights (sin(beta) included): forward, backward
+    std::vector<double> fb, fw, bb, bw;
+    auto gl = [&](double a, double c, int n, std::vector<double>* xs, std::vector<double>* ws) {
+        std::vector<double> x(n), wt(n);
+        celes::gauss_legendre(n, x.data(), wt.data());
+        for (int q = 0; q < n; ++q) {
+            const double t = 0.5 * (c - a) * (x[q] + 1.0) + a;
+            xs->push_back(t);
+            ws->push_back(0.5 * (c - a) * wt[q] * std::sin(t));
+        }
+    };
+    gl(0.0, b1, nbeam, &fb, &fw);
+    if (b1 < M_PI / 2) gl(b1, M_PI / 2, nb, &fb, &fw);
+    gl(M_PI / 2, M_PI, nb, &bb, &bw);
+    const double wa = 2.0 * M_PI / na;
+    const cplx I(0, 1);
+    const cplx gs = I / (2.0 * M_PI);
+    for (int kk = 0; kk < h->K; ++kk) {
+        double P0 = 0, Tn = 0, Rn = 0;
+#pragma omp parallel for reduction(+ : P0, Tn) collapse(2) schedule(dynamic, 4)
+        for (int q = 0; q < (int)fb.size(); ++q)
+            for (int a = 0; a < na; ++a) {
+                const double be = fb[q], al = wa * a;
+                cplx F[3];
+                far_field_dir(h, kk, be, al, F);
+                const double sa = std::sin(al), ca = std::cos(al), sbt = std::sin(be), cbt = std::cos(be);
+                const cplx Fa = F[0] * -sa + F[1] * ca;
+                const cplx Fb = F[0] * (cbt * ca) + F[1] * (cbt * sa) - F[2] * sbt;
+                const double g = k * k * w * w / (4.0 * M_PI) * cbt * std::exp(-(w * k * sbt) * (w * k * sbt) / 4.0);
+                const double kr = k * (sbt * ca * h->g_focus[0] + sbt * sa * h->g_focus[1] + cbt * h->g_focus[2]);
+                const cplx ph = h->g_E0 * std::exp(cplx(0, -kr));
+                const cplx ga = g * std::cos(al - h->g_alpha) * ph, gb = g * std::sin(al - h->g_alpha) * ph;
+                P0 += fw[q] * wa * (std::norm(ga) + std::norm(gb));
+                Tn += fw[q] * wa * (std::norm(ga + gs * Fa) + std::norm(gb + gs * Fb));
+            }
+#pragma omp parallel for reduction(+ : Rn) collapse(2) schedule(dynamic, 4)
+        for (int q = 0; q < (int)bb.size(); ++q)
+            for (int a = 0; a < na; ++a) {
+                cplx F[3];
+                far_field_dir(h, kk, bb[q], wa * a, F);
+                Rn += bw[q] * wa * (std::norm(F[0]) + std::norm(F[1]) + std::norm(F[2])) / (4.0 * M_PI * M_PI);
+            }
+        double ab = 0;
+        for (int64_t i = 0; i < N; ++i)
+            for (int tau = 0; tau < 2; ++tau)
+                for (int c = 0; c < h->half; ++c) {
+                    const size_t o = ((size_t)kk * N + i) * nm + tau * h->half + c;
+                    int l = (int)std::floor(std::sqrt((double)(c + 1)));
+                    while (l * (l + 2) < c + 1) ++l;
+                    while ((l - 1) * (l + 1) >= c + 1) --l;
+                    const cplx qv = h->tq[((size_t)i * 2 + tau) * L + (l - 1)];
+                    if (std::abs(qv) > 0) ab += std::norm(h->b[o]) * (std::real(1.0 / qv) + 1.0);
+                }
+        out[4 * kk + 0] = 4.0 * M_PI * M_PI / (k * k) * P0;
+        out[4 * kk + 1] = Rn / P0;
+        out[4 * kk + 2] = Tn / P0;
+        out[4 * kk + 3] = -ab / (4.0 * M_PI) / P0;
+    }
+    return CELES_OK;
+}
+
+int celes_power_flux(celes_handle* h, int n_beta, int n_alpha, double* out) {
+    return celes_guard([&] { return celes_power_flux_impl(h, n_beta, n_alpha, out); });
+}
+
 static int celes_near_field_impl(celes_handle* h, int64_t npt, const double* pts, int add_incident, double* E_out) {
     if (!h) return CELES_E_ARG;
     if (!h->have_solution) return fail(h, CELES_E_STATE, "no solution");

@@ -109,3 +109,29 @@ def test_noconv_status_and_x0():
     bs, _ = p2.solve()
     b2, info2 = p2.solve(x0=bs)
     assert info2["iterations"] == 0 and info2["rel_residual"] <= 1e-8
+
+
+def test_power_flux_of_gaussian_beam():
+    # Gaussian-beam power balance (Appendix D) on the GPU solution, against the
+    # oracle's quadrature of the same solution; R + T + A = 1
+    from oracle.observables import power_flux
+    from tests.gpu_helpers import tvec
+    w = workload("slab200_l4")
+    print("[solve] slab200_l4 power flux", flush=True)
+    p = make_problem(w, hankel=1, tol=1e-11)
+    b, info = p.solve()
+    assert info["status"] == 0
+    out = p.power_flux()
+    Pin, R, T, A = out[0]
+    il = w.illumination
+    Po, Ro, To, Ao = power_flux(k_of(w), w.positions, b[0], w.lmax, tvec(w), il["waist"], np.array(il["focus"]),
+                                il["alpha_G"], il["E0"])
+    print(f"[solve] R {R:.6f} T {T:.6f} A {A:.2e} R+T+A-1 {R + T + A - 1:.2e}", flush=True)
+    assert abs(Pin - Po) <= 1e-10 * Po
+    assert abs(R - Ro) <= 1e-8 and abs(T - To) <= 1e-8 and abs(A - Ao) <= 1e-12
+    assert abs(R + T + A - 1.0) <= 1e-8
+    # plane-wave incidence carries no finite power
+    q = make_problem(workload("cube8_l3"), hankel=1)
+    q.solve()
+    with pytest.raises(P.CelesError):
+        q.power_flux()
