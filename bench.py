@@ -152,7 +152,7 @@ def batched_mode(a):
         probs.append(q)
     updates = sum(q.N * (q.N - 1) * q.nmax ** 2 * q.num_rhs for q in probs)
     log(f"{len(probs)} problems set up, {updates:.3e} updates per batched mat-vec")
-    bt = P.Batch(probs, precision=P.CELES_MIXED, tol=a.batch_tol, inner_tol=1e-3, restart=60,
+    bt = P.Batch(probs, precision=P.CELES_MIXED, tol=a.batch_tol, inner_tol=1e-3, restart=a.batch_restart,
                  maxiter=a.batch_maxiter, max_refinements=4, verbose=1)
     tune = bt.autotune(P.CELES_MIXED)
     log(f"autotuned: {tune}")
@@ -208,7 +208,7 @@ def batched_mode(a):
                                       "runs on the VALU and is not counted",
                      "matvec_ms": big_ms, "updates_per_s": big_pairs * big.nmax ** 2 * big.num_rhs / (big_ms * 1e-3)},
         "autotune": tune, "solve_seconds": t_solve, "solve_status": summ["status"],
-        "worst_rel_residual": summ["rel_residual"], "tol": a.batch_tol,
+        "worst_rel_residual": summ["rel_residual"], "tol": a.batch_tol, "restart": a.batch_restart,
         "iterations_max": max(its), "iterations_mean": float(np.mean(its)), "refinements": summ["refinements"],
         "geometry_seconds": t_gen}))
 
@@ -434,6 +434,7 @@ def main():
     ap.add_argument("--realisations", type=int, default=32)
     ap.add_argument("--batch-tol", type=float, default=1e-6)
     ap.add_argument("--batch-maxiter", type=int, default=600)
+    ap.add_argument("--batch-restart", type=int, default=60)
     ap.add_argument("--train-slabs", type=int, default=40)
     ap.add_argument("--train-n", type=int, default=2000)
     ap.add_argument("--eval-n", type=int, default=20000)

@@ -180,3 +180,16 @@ def test_full_size_slab10000_64rhs_matrix_cores_sampled_rows():
         e = rel(Y[k][rows], ref)
         print(f"[matvec mfma] rhs {k} rel err {e:.2e}", flush=True)
         assert e <= 1e-4
+
+
+def test_kernel_timing_counts_coupling_launches():
+    w = workload("slab64_l3")
+    p = make_problem(w, hankel=1)
+    x = random_coefficients(107, 1, w.N, w.nmax)[0]
+    p.kernel_timing(True)
+    for _ in range(3):
+        _gpu_W(p, x)
+    ms, n = p.kernel_timing(False)
+    assert n == 3 and 0 < ms < 1e3
+    ms, n = p.kernel_timing(False)       # not running: nothing recorded
+    assert n == 0 and ms == 0
