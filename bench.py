@@ -328,6 +328,48 @@ def paper_mode(a):
                          "dimensions unstated), so this is context, not a like-for-like baseline"}))
 
 
+def scaling_mode(a):
+    """Convergence and run time against system size (the analogue of the
+    paper's Figs. 4-5): the paper's setting (R = 100 nm, lambda = 532 nm,
+    lmax 3, Gaussian beam, tolerance 1e-4) in cylindrical slabs of
+    N = 2,500 ... 20,000 spheres at volume fractions 0.1 and 0.3 (RSA does not
+    reach 0.5), FP64 GMRES with and without the block-diagonal preconditioner
+    of about 200 spheres per cuboid.  One JSON line per run, then a summary."""
+    import numpy as np
+    import torch
+    import paper_1706_02145_amd as P
+    from celes_inputs import cylinder_workload
+
+    t0 = time.perf_counter()
+    rows = []
+    for vf in (0.1, 0.3):
+        edge = (200 * 4.0 / 3.0 * np.pi * 100.0 ** 3 / vf) ** (1.0 / 3.0)
+        for n in (2500, 5000, 10000, 20000):
+            w = cylinder_workload(n, vf)
+            il = w.illumination
+            for pre in (False, True):
+                p = P.Problem(w.positions, w.radii, w.n_sphere, w.n0, w.wavelength, w.lmax,
+                              hankel=P.CELES_HANKEL_LUT, tol=w.tol, restart=100, maxiter=5000, verbose=1)
+                p.set_gaussian_beam(il["waist"], il["focus"], il["alpha_G"], il["E0"])
+                t_pre = 0.0
+                if pre:
+                    t1 = time.perf_counter()
+                    p.build_preconditioner(edge)
+                    torch.cuda.synchronize()
+                    t_pre = time.perf_counter() - t1
+                t1 = time.perf_counter()
+                _, info = p.solve()
+                torch.cuda.synchronize()
+                row = {"N": n, "vf": vf, "preconditioner": pre, "iterations": info["iterations"],
+                       "seconds": time.perf_counter() - t1, "preconditioner_setup_s": t_pre,
+                       "rel_residual": info["rel_residual"], "cuboid_edge_nm": edge if pre else None}
+                rows.append(row)
+                print(f"[scaling] {json.dumps(row)} ({time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
+                p.close()
+    print(json.dumps({"metric": "GMRES iterations and solve time against N (paper setting, tolerance 1e-4)",
+                      "unit": "s", "n_gpus": 1, "dtype": "f64", "data": "synthetic", "runs": rows}))
+
+
 def warmstart_mode(a):
     """Learned initial guess: train on solver output of several slabs
     (lmax 3, N = a.train_n each), evaluate on a larger unseen slab: GMRES
@@ -429,7 +471,8 @@ def main():
     ap.add_argument("--cuboid-edge", type=float, default=1500.0)
     ap.add_argument("--hankel", choices=["lut", "direct"], default="lut")
     ap.add_argument("--profile", action="store_true", help="mat-vec launches only (for rocprofv3)")
-    ap.add_argument("--mode", choices=["solve", "batched", "warmstart", "mixed", "paper"], default="solve")
+    ap.add_argument("--mode", choices=["solve", "batched", "warmstart", "mixed", "paper", "scaling"],
+                    default="solve")
     ap.add_argument("--mixed-workload", default="slab20000_l4")
     ap.add_argument("--realisations", type=int, default=32)
     ap.add_argument("--batch-tol", type=float, default=1e-6)
@@ -452,6 +495,8 @@ def main():
         return mixed_mode(a)
     if a.mode == "paper":
         return paper_mode(a)
+    if a.mode == "scaling":
+        return scaling_mode(a)
 
     import numpy as np
     import torch

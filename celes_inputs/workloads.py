@@ -103,6 +103,13 @@ WORKLOADS = tuple(_BUILDERS)
 _CACHE = {}
 
 
+def cylinder_workload(n, vf, seed=6001, thickness=2000.0):
+    """The paper's application setting (see _cylinder) for any N and volume
+    fraction: R = 100 nm, n = 1.5, lambda = 532 nm, lmax 3, Gaussian beam
+    waist 4 um, tolerance 1e-4, cylindrical slab of the given thickness."""
+    return _cylinder(f"cyl_n{n}_vf{vf:g}", seed, n, vf, thickness)
+
+
 def workload(name, seed=None, n=None):
     """Return the named workload.  `seed`/`n` override the slab seed/size for
     families of realisations (same statistics, different geometry)."""
