@@ -502,7 +502,7 @@ def main():
     ap.add_argument("--realisations", type=int, default=32)
     ap.add_argument("--batch-tol", type=float, default=1e-6)
     ap.add_argument("--batch-maxiter", type=int, default=600)
-    ap.add_argument("--batch-restart", type=int, default=60)
+    ap.add_argument("--batch-restart", type=int, default=150)
     ap.add_argument("--train-slabs", type=int, default=40)
     ap.add_argument("--train-n", type=int, default=2000)
     ap.add_argument("--eval-n", type=int, default=20000)
