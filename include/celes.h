@@ -209,7 +209,8 @@ int celes_power_flux(celes_handle* h, int n_beta, int n_alpha, double* out);
  * celes_apply_W / celes_apply_M / celes_solve launch on this handle (the
  * prep and finish kernels are outside); enable = 0 stops and returns the
  * average kernel duration in ms and the number of launches (either output may
- * be NULL).  Errors: CELES_E_ARG, CELES_E_DEVICE. */
+ * be NULL).  At most the first 4096 launches of a window are recorded.
+ * Errors: CELES_E_ARG, CELES_E_DEVICE. */
 int celes_kernel_timing(celes_handle* h, int enable, double* avg_ms, int* count);
 
 /* Geometry of the Hankel lookup table (Section 3.2.2): nodes d_lo + q*dr,

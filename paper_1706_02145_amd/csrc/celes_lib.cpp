@@ -228,7 +228,8 @@ int pick_kb(int L, int K) {
 
 // events for the next coupling-kernel launch when kernel timing is on
 static const hipEvent_t* timing_events(celes_handle* h) {
-    if (!h->time_kernels) return nullptr;
+    constexpr size_t kMaxTimed = 4096;   // launches recorded per timing window
+    if (!h->time_kernels || h->tev_used >= 2 * kMaxTimed) return nullptr;
     if (h->tev_used + 2 > h->tev.size()) {
         for (int q = 0; q < 2; ++q) {
             hipEvent_t e;
