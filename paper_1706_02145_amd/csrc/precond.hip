@@ -326,10 +326,14 @@ int BlockPrecond::build(int64_t N, int L, const double* pos, double k, const cpl
         *msg = "rocblas_create_handle failed";
         return CELES_E_DEVICE_INTERNAL;
     }
+    // one pivot array and two info slots per block, checked once at the end,
+    // so that the blocks' factorisations queue back to back on the stream
     rocblas_int *d_ipiv = nullptr, *d_info = nullptr;
-    dev((void**)&d_ipiv, (size_t)max_dim_ * sizeof(rocblas_int));
-    dev((void**)&d_info, sizeof(rocblas_int));
-    int rc = 0;
+    const bool ok_piv = dev((void**)&d_ipiv, (size_t)max_dim_ * sizeof(rocblas_int)) &&
+                        dev((void**)&d_info, (size_t)2 * nb * sizeof(rocblas_int));
+    int rc = ok_piv ? 0 : CELES_E_OOM_INTERNAL;
+    if (!ok_piv) *msg = "cannot allocate pivots";
+    if (rc == 0) hipMemset(d_info, 0, (size_t)2 * nb * sizeof(rocblas_int));
     for (int j = 0; j < nb && rc == 0; ++j) {
         g.blk = j;
         const int64_t nj = offsets_[j + 1] - offsets_[j];
@@ -337,17 +341,20 @@ int BlockPrecond::build(int64_t N, int L, const double* pos, double k, const cpl
         hipLaunchKernelGGL(assemble_kernel, dim3((unsigned)((ntot + 255) / 256)), dim3(256), 0, 0, g, ntot);
         const int dim = (int)(nj * nmax_);
         rocblas_double_complex* A = (rocblas_double_complex*)(d_inv_ + moff[j]);
-        if (rocsolver_zgetrf(rb, dim, dim, A, dim, d_ipiv, d_info) != rocblas_status_success ||
-            rocsolver_zgetri(rb, dim, A, dim, d_ipiv, d_info) != rocblas_status_success) {
+        if (rocsolver_zgetrf(rb, dim, dim, A, dim, d_ipiv, d_info + 2 * j) != rocblas_status_success ||
+            rocsolver_zgetri(rb, dim, A, dim, d_ipiv, d_info + 2 * j + 1) != rocblas_status_success) {
             *msg = "rocsolver LU/inverse failed";
             rc = CELES_E_DEVICE_INTERNAL;
         }
-        rocblas_int info = 0;
-        hipMemcpy(&info, d_info, sizeof(info), hipMemcpyDeviceToHost);
-        if (info != 0) {
-            *msg = "singular preconditioner block " + std::to_string(j);
-            rc = CELES_E_DEVICE_INTERNAL;
-        }
+    }
+    if (rc == 0) {
+        std::vector<rocblas_int> info(2 * nb, 0);
+        hipMemcpy(info.data(), d_info, info.size() * sizeof(rocblas_int), hipMemcpyDeviceToHost);
+        for (int j = 0; j < nb && rc == 0; ++j)
+            if (info[2 * j] != 0 || info[2 * j + 1] != 0) {
+                *msg = "singular preconditioner block " + std::to_string(j);
+                rc = CELES_E_DEVICE_INTERNAL;
+            }
     }
     // complex64 copy of the inverses for the complex64 inner solves (half the
     // bytes of the HBM-bound apply); the factorisation itself is FP64
