@@ -1,6 +1,6 @@
-"""Master equation, dense direct solve, block-diagonal preconditioner and a
-reference GMRES (paper, Section 2.2 eqs. "masterequation" and "M"; Section 3.2
-and 3.2.1).
+"""Master equation, dense direct solve, block-diagonal preconditioner and
+reference GMRES and BiCGSTAB solvers (paper, Section 2.2 eqs.
+"masterequation" and "M"; Section 3.2 and 3.2.1).
 
     M^{ii'}_{nn'} = delta_{nn'} delta_{ii'} - T^i_{nn} W^{ii'}_{nn'}     (T diagonal)
     M b = T a_in
@@ -128,3 +128,76 @@ def gmres(matvec, rhs, tol=1e-10, restart=100, maxiter=10000, precond=None, x0=N
         y = np.linalg.solve(np.triu(H[:m, :m]), g[:m])
         u = sum(y[i] * V[i] for i in range(m))
         x = x + P(u)
+
+
+def bicgstab(matvec, rhs, tol=1e-10, maxiter=10000, precond=None, x0=None, trace=None):
+    """Right-preconditioned BiCGSTAB, the alternative iterative solver of
+    Section 3.2 (the method as given in the iterative-templates reference the
+    paper cites, Barrett et al. 1994).  Notation: rho, alpha, omega, beta;
+    p_hat = P^{-1} p, s_hat = P^{-1} s; the shadow residual r_tilde is the
+    residual at the start of a run.
+
+    One iteration costs two products with the master matrix.  A run ends when
+    the updated residual ||s|| or ||r|| drops to tol * ||rhs|| or on a
+    breakdown (rho = 0, r_tilde^H v = 0, omega = 0); the true residual
+    rhs - M x is then evaluated and, if it is still above the tolerance, a new
+    run starts from the current x (a stalled run that makes no iteration ends
+    the solve).  Returns (x, iterations, history of true residuals at run
+    starts and at the end).  `trace`, if a list, receives per iteration a
+    dict with the vectors s, t, r (updated), x after the iteration and the
+    shadow residual r_tilde."""
+    P = precond if precond is not None else (lambda v: v)
+    x = np.zeros_like(rhs) if x0 is None else np.array(x0, dtype=np.complex128)
+    nb = np.linalg.norm(rhs)
+    if nb == 0:
+        return np.zeros_like(rhs), 0, [0.0]
+    its = 0
+    hist = []
+    while True:
+        r = rhs - matvec(x)
+        res = np.linalg.norm(r) / nb
+        hist.append(res)
+        if res <= tol or its >= maxiter:
+            return x, its, hist
+        r_tilde = r.copy()
+        rho_old = alpha = omega = 1.0
+        p = np.zeros_like(r)
+        v = np.zeros_like(r)
+        run_its = 0
+        while its < maxiter:
+            rho = np.vdot(r_tilde, r)
+            if rho == 0:
+                break
+            if run_its == 0:
+                p = r.copy()
+            else:
+                beta = (rho / rho_old) * (alpha / omega)
+                p = r + beta * (p - omega * v)
+            p_hat = P(p)
+            v = matvec(p_hat)
+            rv = np.vdot(r_tilde, v)
+            if rv == 0:
+                break
+            alpha = rho / rv
+            s = r - alpha * v
+            its += 1
+            run_its += 1
+            if np.linalg.norm(s) / nb <= tol:
+                x = x + alpha * p_hat
+                if trace is not None:
+                    trace.append({"s": s, "t": None, "r": s, "x": x.copy(), "r_tilde": r_tilde})
+                break
+            s_hat = P(s)
+            t = matvec(s_hat)
+            tt = np.vdot(t, t).real
+            omega = np.vdot(t, s) / tt if tt > 0 else 0.0
+            x = x + alpha * p_hat + omega * s_hat
+            r = s - omega * t
+            rho_old = rho
+            if trace is not None:
+                trace.append({"s": s, "t": t, "r": r, "x": x.copy(), "r_tilde": r_tilde})
+            if np.linalg.norm(r) / nb <= tol or omega == 0:
+                break
+        if run_its == 0:
+            hist.append(np.linalg.norm(rhs - matvec(x)) / nb)
+            return x, its, hist
