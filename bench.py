@@ -298,9 +298,11 @@ def mixed_mode(a):
 def paper_mode(a):
     """The paper's run-time comparison setting (Section 4, Table 1 row N = 2e4,
     vf 10 %): 20,000 spheres of R = 100 nm, n = 1.5, in a cylindrical slab,
-    lambda = 532 nm, lmax 3, Gaussian beam (waist 4 um), GMRES to 1e-4, with
+    lambda = 532 nm, lmax 3, Gaussian beam (waist 4 um), solved to 1e-4 with
     and without a block-diagonal preconditioner of about 200 spheres per
-    cuboid; FP64 and mixed precision."""
+    cuboid; FP64 and mixed precision; GMRES and (--paper-solvers) BiCGSTAB,
+    the two solvers of Section 3.2.  One BiCGSTAB iteration costs two
+    mat-vecs."""
     import numpy as np
     import torch
     import paper_1706_02145_amd as P
@@ -316,32 +318,35 @@ def paper_mode(a):
     log(f"{w.name} generated (N={w.N}, cylinder radius {w.extra['cylinder_radius']:.0f} nm)")
     edge = (200 * 4.0 / 3.0 * np.pi * 100.0 ** 3 / 0.10) ** (1.0 / 3.0)   # ~200 spheres per cuboid
     res = {}
-    for name, prec in (("fp64", P.CELES_FP64), ("mixed", P.CELES_MIXED)):
-        for pre in (False, True):
-            p = P.Problem(w.positions, w.radii, w.n_sphere, w.n0, w.wavelength, w.lmax, hankel=P.CELES_HANKEL_LUT,
-                          lut_dr=w.lut_dr, precision=prec, tol=w.tol, restart=100, maxiter=3000,
-                          inner_tol=1e-3, verbose=1)
-            p.set_gaussian_beam(il["waist"], il["focus"], il["alpha_G"], il["E0"])
-            t_pre = 0.0
-            if pre:
-                t1 = time.perf_counter()
-                p.build_preconditioner(edge)
-                torch.cuda.synchronize()
-                t_pre = time.perf_counter() - t1
-            p.solve()                                   # warm-up (allocations)
-            torch.cuda.synchronize()
+    solvers = {"gmres": P.CELES_SOLVER_GMRES, "bicgstab": P.CELES_SOLVER_BICGSTAB}
+    runs = [(sv, name, prec, pre) for sv in a.paper_solvers.split(",")
+            for name, prec in (("fp64", P.CELES_FP64), ("mixed", P.CELES_MIXED)) for pre in (False, True)]
+    for sv, name, prec, pre in runs:
+        p = P.Problem(w.positions, w.radii, w.n_sphere, w.n0, w.wavelength, w.lmax, hankel=P.CELES_HANKEL_LUT,
+                      lut_dr=w.lut_dr, precision=prec, tol=w.tol, restart=100, maxiter=3000,
+                      inner_tol=1e-3, verbose=1, solver=solvers[sv])
+        p.set_gaussian_beam(il["waist"], il["focus"], il["alpha_G"], il["E0"])
+        t_pre = 0.0
+        if pre:
             t1 = time.perf_counter()
-            _, info = p.solve()
+            p.build_preconditioner(edge)
             torch.cuda.synchronize()
-            dt = time.perf_counter() - t1
-            key = name + ("_preconditioned" if pre else "")
-            res[key] = {"seconds": dt, "iterations": info["iterations"], "matvecs": info["matvecs"],
-                        "rel_residual": info["rel_residual"], "preconditioner_setup_s": t_pre}
-            log(f"{key}: {dt:.2f} s, {info['iterations']} iterations")
-            p.close()
-    best = min(v["seconds"] + v["preconditioner_setup_s"] for v in res.values())
+            t_pre = time.perf_counter() - t1
+        p.solve(check=False)                        # warm-up (allocations)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, info = p.solve(check=False)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        key = ("" if sv == "gmres" else sv + "_") + name + ("_preconditioned" if pre else "")
+        res[key] = {"seconds": dt, "iterations": info["iterations"], "matvecs": info["matvecs"],
+                    "rel_residual": info["rel_residual"], "status": info["status"], "preconditioner_setup_s": t_pre}
+        log(f"{key}: {dt:.2f} s, {info['iterations']} iterations, {info['matvecs']} mat-vecs, "
+            f"residual {info['rel_residual']:.2e}")
+        p.close()
+    best = min(v["seconds"] + v["preconditioner_setup_s"] for v in res.values() if v["status"] == 0)
     print(json.dumps({
-        "metric": "solve time to GMRES tolerance 1e-4 (the paper's Table 1 setting)", "value": best, "unit": "s",
+        "metric": "solve time to relative residual 1e-4 (the paper's Table 1 setting)", "value": best, "unit": "s",
         "higher_is_better": False, "n_gpus": 1, "dtype": "f64 / f32", "data": "synthetic",
         "config": {"workload": f"{w.name}: N={w.N}, R=100 nm, n=1.5, vf 0.10, cylindrical slab t=2 um "
                                f"(radius {w.extra['cylinder_radius']:.0f} nm, RSA), lambda=532 nm, lmax 3, "
@@ -466,7 +471,7 @@ def warmstart_mode(a):
             t1 = time.perf_counter()
             _, info = p.solve(x0=x0)
             dt = time.perf_counter() - t1
-            key = name + ("_preconditioned" if pre else "")
+            key = ("" if sv == "gmres" else sv + "_") + name + ("_preconditioned" if pre else "")
             res[key] = {"iterations": info["iterations"], "seconds": dt, "x0_used": info["x0_used"],
                         "rel_residual": info["rel_residual"], "initial_rel_residual": initial_residual(x0)}
             log(f"x0 = {key}: {info['iterations']} iterations, {dt:.2f} s, "
@@ -499,6 +504,7 @@ def main():
     ap.add_argument("--mode", choices=["solve", "batched", "warmstart", "mixed", "paper", "scaling"],
                     default="solve")
     ap.add_argument("--mixed-workload", default="slab20000_l4")
+    ap.add_argument("--paper-solvers", default="gmres,bicgstab", help="paper mode: comma-separated gmres,bicgstab")
     ap.add_argument("--realisations", type=int, default=32)
     ap.add_argument("--batch-tol", type=float, default=1e-6)
     ap.add_argument("--batch-maxiter", type=int, default=600)

@@ -56,6 +56,10 @@ extern "C" {
                                  * 3.2.2), higher orders by the upward three-term recurrence   */
 #define CELES_HANKEL_DIRECT 1   /* h_0, h_1 from sin/cos per pair, then the same recurrence    */
 
+/* iterative solver of the master equation (Section 3.2 offers both) */
+#define CELES_SOLVER_GMRES 0    /* restarted GMRES (default)                                  */
+#define CELES_SOLVER_BICGSTAB 1 /* BiCGSTAB: two mat-vecs per iteration, seven work vectors  */
+
 #define CELES_MAX_LMAX 6
 
 typedef struct celes_handle celes_handle;
@@ -72,11 +76,14 @@ typedef struct celes_options {
     double cuboid_edge;     /* preconditioner cuboid edge; <= 0 disables the preconditioner   */
     int device;             /* HIP device ordinal                                             */
     int verbose;            /* 0 silent, 1 per-restart residuals on stderr                    */
+    int solver;             /* CELES_SOLVER_GMRES or CELES_SOLVER_BICGSTAB (single problems;
+                             * batches run GMRES only)                                        */
 } celes_options;
 
 typedef struct celes_solve_info {
     int status;             /* CELES_OK, CELES_E_NOCONV or CELES_E_BREAKDOWN                   */
-    int iterations;         /* inner GMRES iterations (all restarts, all refinements)          */
+    int iterations;         /* inner GMRES iterations or BiCGSTAB iterations (two mat-vecs
+                             * each), over all restarts and refinements                        */
     int refinements;        /* outer FP64 refinement steps (mixed) or restarts (FP64)          */
     int matvecs;            /* coupling mat-vecs performed (any precision)                     */
     double rel_residual;    /* final true relative residual, evaluated in FP64                 */
@@ -86,7 +93,8 @@ typedef struct celes_solve_info {
 } celes_solve_info;
 
 /* Fill *opt with defaults: FP64, LUT, lut_dr = 1, tol = 1e-8, inner_tol = 1e-4,
- * restart = 100, maxiter = 2000, max_refinements = 30, cuboid_edge = 0, device 0. */
+ * restart = 100, maxiter = 2000, max_refinements = 30, cuboid_edge = 0, device 0,
+ * solver GMRES. */
 void celes_default_options(celes_options* opt);
 
 /* Library version (CELES_VERSION). */
@@ -144,7 +152,12 @@ int celes_build_preconditioner(celes_handle* h, double cuboid_edge);
 
 /* Solve the master equation M b = T a_in (Section 2.2, eqs. masterequation
  * and M) for every right-hand side by right-preconditioned restarted GMRES
- * (Section 3.2), W applied on the fly on the device.  x0 [K][N][nmax]
+ * or, with opt.solver = CELES_SOLVER_BICGSTAB, right-preconditioned BiCGSTAB
+ * (Section 3.2), W applied on the fly on the device.  BiCGSTAB runs until
+ * its updated residual reaches tol (or breaks down), then checks the true
+ * residual and starts a new run from the current iterate if needed; its
+ * maxiter counts BiCGSTAB iterations.  With CELES_MIXED the complex64
+ * correction solves use the chosen solver.  x0 [K][N][nmax]
  * complex128 is the initial guess (NULL: zero; the custom initial condition
  * of Section 4.2): it is kept only if its relative residual is below 1,
  * otherwise the solve starts from zero (info->x0_used tells which).  b_out [K][N][nmax]

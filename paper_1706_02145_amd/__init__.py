@@ -9,11 +9,12 @@ import ctypes as C
 
 import numpy as np
 
-from ._capi import (CELES_FP64, CELES_HANKEL_DIRECT, CELES_HANKEL_LUT, CELES_MIXED, ERRORS, Options,
-                    SolveInfo, lib, LIB_PATH)
+from ._capi import (CELES_FP64, CELES_HANKEL_DIRECT, CELES_HANKEL_LUT, CELES_MIXED, CELES_SOLVER_BICGSTAB,
+                    CELES_SOLVER_GMRES, ERRORS, Options, SolveInfo, lib, LIB_PATH)
 
 __all__ = ["Problem", "Batch", "Network", "CelesError", "default_options", "mie_coefficients", "translation_tables", "version",
-           "CELES_FP64", "CELES_MIXED", "CELES_HANKEL_LUT", "CELES_HANKEL_DIRECT", "LIB_PATH"]
+           "CELES_FP64", "CELES_MIXED", "CELES_HANKEL_LUT", "CELES_HANKEL_DIRECT", "CELES_SOLVER_GMRES",
+           "CELES_SOLVER_BICGSTAB", "LIB_PATH"]
 
 
 class CelesError(RuntimeError):

@@ -14,13 +14,14 @@ ERRORS = {
 }
 CELES_FP64, CELES_MIXED = 0, 1
 CELES_HANKEL_LUT, CELES_HANKEL_DIRECT = 0, 1
+CELES_SOLVER_GMRES, CELES_SOLVER_BICGSTAB = 0, 1
 
 
 class Options(C.Structure):
     _fields_ = [("precision", C.c_int), ("hankel", C.c_int), ("lut_dr", C.c_double), ("tol", C.c_double),
                 ("inner_tol", C.c_double), ("restart", C.c_int), ("maxiter", C.c_int),
                 ("max_refinements", C.c_int), ("cuboid_edge", C.c_double), ("device", C.c_int),
-                ("verbose", C.c_int)]
+                ("verbose", C.c_int), ("solver", C.c_int)]
 
 
 class SolveInfo(C.Structure):

@@ -485,6 +485,138 @@ int gmres_device(celes_handle* h, const cx<T>* rhs, cx<T>* x, double tol, int ma
     return rc;
 }
 
+// ---------------------------------------------------------------------------
+// BiCGSTAB (right-preconditioned, the alternative solver of Section 3.2) on
+// device vectors of precision T, inner products in FP64.  Solves M x = rhs
+// from the initial x.  A run starts from the true residual r = rhs - M x
+// with shadow residual r~ = r and ends when the updated residual reaches
+// tol * ||rhs|| or on a breakdown (rho = 0, r~^H v = 0, omega = 0); the true
+// residual then decides whether a new run starts.  A run that makes no
+// iteration ends the solve.  work: 7 vectors of N nmax.
+// ---------------------------------------------------------------------------
+template <typename T>
+int bicgstab_device(celes_handle* h, const cx<T>* rhs, cx<T>* x, double tol, int maxiter, double rhs_norm,
+                    GmresResult* out, hipStream_t s, cx<T>* work) {
+    const int64_t n = h->N * h->nmax;
+    // r (later s) and t are adjacent and r~ sits two vectors after r, so one
+    // dots launch over {r, t} or {r, r~} yields two inner products
+    cx<T>* r = work;
+    cx<T>* t = work + n;
+    cx<T>* rt = work + 2 * n;
+    cx<T>* p = work + 3 * n;
+    cx<T>* v = work + 4 * n;
+    cx<T>* ph = work + 5 * n;
+    cx<T>* sh = work + 6 * n;
+    cx<double>* dh = h->d_h.as<cx<double>>();
+    cx<double>* dpart = h->d_partial.as<cx<double>>();
+    const bool use_pre = (bool)h->pre;
+    cx<double> hv[2];
+    // out[c] = V[c]^H w for c < m, V[c] = V0 + c * ldv; copied to hv
+    auto dots = [&](const cx<T>* V0, int64_t ldv, int m, const cx<T>* w) {
+        celes::vec_dots<T>(V0, ldv, m, w, n, dpart, dh, s);
+        hipMemcpyAsync(hv, dh, m * sizeof(cx<double>), hipMemcpyDeviceToHost, s);
+        hipStreamSynchronize(s);
+    };
+    auto cplx_of = [](cx<double> a) { return cplx(a.re, a.im); };
+    auto cxd = [](cplx a) { return cx<double>{a.real(), a.imag()}; };
+    const cx<double> one = {1.0, 0.0}, zero = {0.0, 0.0};
+    hipEvent_t e0, e1;
+    hipEventCreate(&e0);
+    hipEventCreate(&e1);
+    auto timed_matvec = [&](const cx<T>* in, cx<T>* outv) -> int {
+        hipEventRecord(e0, s);
+        int rc = matvec<T>(h, in, outv, 1, 1, s);
+        hipEventRecord(e1, s);
+        hipEventSynchronize(e1);
+        float ms = 0;
+        hipEventElapsedTime(&ms, e0, e1);
+        out->matvec_seconds += ms * 1e-3;
+        out->matvecs++;
+        return rc;
+    };
+    // returns the vector holding P^{-1} in (in itself without a preconditioner)
+    auto precond = [&](const cx<T>* in, cx<T>* buf, int* rc) -> const cx<T>* {
+        if (!use_pre) return in;
+        *rc = h->pre->apply<T>(in, buf, s);
+        return buf;
+    };
+    int rc = CELES_OK;
+    while (true) {
+        if ((rc = timed_matvec(x, t)) != CELES_OK) break;
+        celes::vec_sub<T>(rhs, t, r, n, s);
+        dots(r, 0, 1, r);
+        double res = std::sqrt(std::max(0.0, hv[0].re)) / rhs_norm;
+        out->est = res;
+        if (!std::isfinite(res)) {
+            out->breakdown = true;
+            break;
+        }
+        if (res <= tol || out->iterations >= maxiter) break;
+        celes::vec_scale<T>(r, 1.0, rt, n, s);
+        cplx rho = hv[0].re, rho_old = 1.0, alpha = 1.0, omega = 1.0;
+        int run_its = 0;
+        while (out->iterations < maxiter) {
+            if (rho == cplx(0, 0)) break;
+            if (run_its == 0) {
+                celes::vec_scale<T>(r, 1.0, p, n, s);
+            } else {
+                const cplx beta = (rho / rho_old) * (alpha / omega);
+                celes::vec_comb3<T>(r, one, p, cxd(beta), v, cxd(-beta * omega), p, n, s);
+            }
+            const cx<T>* phat = precond(p, ph, &rc);
+            if (rc != CELES_OK) break;
+            if ((rc = timed_matvec(phat, v)) != CELES_OK) break;
+            dots(rt, 0, 1, v);
+            const cplx rv = cplx_of(hv[0]);
+            if (rv == cplx(0, 0)) break;
+            alpha = rho / rv;
+            // s = r - alpha v, kept in r
+            celes::vec_comb3<T>(r, one, v, cxd(-alpha), nullptr, zero, r, n, s);
+            out->iterations++;
+            run_its++;
+            dots(r, 0, 1, r);
+            const double snorm = std::sqrt(std::max(0.0, hv[0].re)) / rhs_norm;
+            out->est = snorm;
+            if (!std::isfinite(snorm)) {
+                out->breakdown = true;
+                break;
+            }
+            if (snorm <= tol) {
+                celes::vec_comb3<T>(x, one, phat, cxd(alpha), nullptr, zero, x, n, s);
+                break;
+            }
+            const cx<T>* shat = precond(r, sh, &rc);
+            if (rc != CELES_OK) break;
+            if ((rc = timed_matvec(shat, t)) != CELES_OK) break;
+            dots(r, n, 2, t);  // {s^H t, t^H t}
+            const double tt = hv[1].re;
+            omega = tt > 0 ? std::conj(cplx_of(hv[0])) / tt : cplx(0, 0);
+            celes::vec_comb3<T>(x, one, phat, cxd(alpha), shat, cxd(omega), x, n, s);
+            celes::vec_comb3<T>(r, one, t, cxd(-omega), nullptr, zero, r, n, s);
+            rho_old = rho;
+            dots(r, 2 * n, 2, r);  // {r^H r, r~^H r}
+            const double rnorm = std::sqrt(std::max(0.0, hv[0].re)) / rhs_norm;
+            rho = cplx_of(hv[1]);
+            out->est = rnorm;
+            if (!std::isfinite(rnorm)) {
+                out->breakdown = true;
+                break;
+            }
+            if (rnorm <= tol || omega == cplx(0, 0)) break;
+        }
+        if (rc != CELES_OK || out->breakdown) break;
+        out->restarts++;
+        if (h->opt.verbose)
+            std::fprintf(stderr, "bicgstab (%s) run %d: %d iterations, updated residual %.3e\n",
+                         sizeof(T) == 8 ? "fp64" : "fp32", out->restarts, out->iterations, out->est);
+        if (run_its == 0) break;
+    }
+    hipStreamSynchronize(s);
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    return rc;
+}
+
 int ensure_solver_buffers(celes_handle* h, bool mixed) {
     const int64_t n = h->N * h->nmax;
     const int m = std::max(1, h->opt.restart);
@@ -493,12 +625,14 @@ int ensure_solver_buffers(celes_handle* h, bool mixed) {
               h->d_w.ensure(n * sizeof(cx<double>)) && h->d_z.ensure(n * sizeof(cx<double>)) &&
               h->d_r.ensure(n * sizeof(cx<double>)) && h->d_x.ensure(n * sizeof(cx<double>)) &&
               h->d_rhs.ensure(n * sizeof(cx<double>));
+    // Krylov basis (GMRES) or the seven work vectors (BiCGSTAB)
+    const size_t nv = h->opt.solver == CELES_SOLVER_BICGSTAB ? 7 : (size_t)(m + 1);
     if (mixed)
-        ok = ok && h->d_V32.ensure((size_t)(m + 1) * n * sizeof(cx<float>)) &&
+        ok = ok && h->d_V32.ensure(nv * n * sizeof(cx<float>)) &&
              h->d_w32.ensure(n * sizeof(cx<float>)) && h->d_z32.ensure(n * sizeof(cx<float>)) &&
              h->d_r32.ensure(n * sizeof(cx<float>)) && h->d_x32.ensure(n * sizeof(cx<float>));
     else
-        ok = ok && h->d_V.ensure((size_t)(m + 1) * n * sizeof(cx<double>));
+        ok = ok && h->d_V.ensure(nv * n * sizeof(cx<double>));
     return ok ? CELES_OK : fail(h, CELES_E_OOM, "cannot allocate solver buffers");
 }
 
@@ -586,6 +720,8 @@ static int celes_create_impl(celes_handle** out, int64_t N, const double* pos, c
     else celes_default_options(&h->opt);
     if (!(h->opt.lut_dr > 0)) return fail(nullptr, CELES_E_ARG, "lut_dr must be positive");
     if (h->opt.restart < 1) h->opt.restart = 1;
+    if (h->opt.solver != CELES_SOLVER_GMRES && h->opt.solver != CELES_SOLVER_BICGSTAB)
+        return fail(nullptr, CELES_E_ARG, "unknown solver");
     if (hipSetDevice(h->opt.device) != hipSuccess) return fail(nullptr, CELES_E_DEVICE, "hipSetDevice failed");
     h->N = N;
     h->L = lmax;
@@ -875,6 +1011,7 @@ static int celes_solve_impl(celes_handle* h, const double* x0, double* b_out, ce
     if (!h) return CELES_E_ARG;
     if (h->K < 1) return fail(h, CELES_E_STATE, "no incident field set");
     const bool mixed = h->opt.precision == CELES_MIXED;
+    const bool bicg = h->opt.solver == CELES_SOLVER_BICGSTAB;
     int rc = ensure_solver_buffers(h, mixed);
     if (rc != CELES_OK) return rc;
     hipStream_t s = nullptr;
@@ -930,8 +1067,12 @@ static int celes_solve_impl(celes_handle* h, const double* x0, double* b_out, ce
             HIPCHK(h, hipMemset(dx, 0, n * sizeof(cx<double>)));
         } else if (!mixed) {
             GmresResult gr;
-            rc = gmres_device<double>(h, drhs, dx, h->opt.tol, h->opt.maxiter, rn, &gr, s, h->d_V.as<cx<double>>(),
-                                      h->d_w.as<cx<double>>(), h->d_z.as<cx<double>>());
+            if (bicg)
+                rc = bicgstab_device<double>(h, drhs, dx, h->opt.tol, h->opt.maxiter, rn, &gr, s,
+                                             h->d_V.as<cx<double>>());
+            else
+                rc = gmres_device<double>(h, drhs, dx, h->opt.tol, h->opt.maxiter, rn, &gr, s,
+                                          h->d_V.as<cx<double>>(), h->d_w.as<cx<double>>(), h->d_z.as<cx<double>>());
             if (rc != CELES_OK) return rc;
             inf.iterations += gr.iterations;
             inf.refinements += gr.restarts;
@@ -957,9 +1098,13 @@ static int celes_solve_impl(celes_handle* h, const double* x0, double* b_out, ce
                 GmresResult gr;
                 double rnorm = r * rn;
                 double inner = std::max(h->opt.inner_tol, 0.5 * h->opt.tol / r);
-                rc = gmres_device<float>(h, h->d_r32.as<cx<float>>(), h->d_x32.as<cx<float>>(), inner, inner_left,
-                                         rnorm, &gr, s, h->d_V32.as<cx<float>>(), h->d_w32.as<cx<float>>(),
-                                         h->d_z32.as<cx<float>>());
+                if (bicg)
+                    rc = bicgstab_device<float>(h, h->d_r32.as<cx<float>>(), h->d_x32.as<cx<float>>(), inner,
+                                                inner_left, rnorm, &gr, s, h->d_V32.as<cx<float>>());
+                else
+                    rc = gmres_device<float>(h, h->d_r32.as<cx<float>>(), h->d_x32.as<cx<float>>(), inner,
+                                             inner_left, rnorm, &gr, s, h->d_V32.as<cx<float>>(),
+                                             h->d_w32.as<cx<float>>(), h->d_z32.as<cx<float>>());
                 if (rc != CELES_OK) return rc;
                 inf.iterations += gr.iterations;
                 inf.matvecs += gr.matvecs;
@@ -989,8 +1134,9 @@ static int celes_solve_impl(celes_handle* h, const double* x0, double* b_out, ce
     h->have_solution = true;
     if (b_out) std::memcpy(b_out, h->b.data(), h->b.size() * sizeof(cplx));
     if (info) *info = inf;
-    if (status == CELES_E_NOCONV) h->err = "GMRES did not reach the tolerance";
-    if (status == CELES_E_BREAKDOWN) h->err = "GMRES breakdown (non-finite iterate)";
+    const char* name = bicg ? "BiCGSTAB" : "GMRES";
+    if (status == CELES_E_NOCONV) h->err = std::string(name) + " did not reach the tolerance";
+    if (status == CELES_E_BREAKDOWN) h->err = std::string(name) + " breakdown (non-finite iterate)";
     return status;
 }
 int celes_solve(celes_handle* h, const double* x0, double* b_out, celes_solve_info* info) {
@@ -1650,6 +1796,7 @@ static int celes_batch_create_impl(celes_batch** out, int nprob, celes_handle* c
     b->probs.assign(probs, probs + nprob);
     b->L = probs[0]->L;
     if (b->L > 4) return bfail(nullptr, CELES_E_UNSUPPORTED, "batches are compiled for lmax <= 4");
+    if (b->opt.solver != CELES_SOLVER_GMRES) return bfail(nullptr, CELES_E_UNSUPPORTED, "batches run GMRES only");
     b->nmax = probs[0]->nmax;
     b->half = probs[0]->half;
     b->m = std::max(1, b->opt.restart);

@@ -115,6 +115,19 @@ __global__ void zsub(const cx<T>* __restrict__ x, const cx<T>* __restrict__ y, c
     z[i] = {x[i].re - y[i].re, x[i].im - y[i].im};
 }
 
+// out = a x + b y + c z (complex scalars; y and z may be null when b, c are
+// unused).  Element-wise, so out may alias any input.
+template <typename T>
+__global__ void zcomb3(const cx<T>* x, cx<T> a, const cx<T>* y, cx<T> b, const cx<T>* z, cx<T> c, cx<T>* out,
+                       int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * VB + threadIdx.x;
+    if (i >= n) return;
+    cx<T> acc = cmul(a, x[i]);
+    if (y) cfma(acc, b, y[i]);
+    if (z) cfma(acc, c, z[i]);
+    out[i] = acc;
+}
+
 // precision conversion
 template <typename A, typename B>
 __global__ void zconvert(const cx<A>* __restrict__ x, cx<B>* __restrict__ y, int64_t n) {
@@ -158,6 +171,12 @@ template <typename T>
 void vec_sub(const cx<T>* x, const cx<T>* y, cx<T>* z, int64_t n, hipStream_t s) {
     hipLaunchKernelGGL(zsub<T>, grid1(n), dim3(VB), 0, s, x, y, z, n);
 }
+template <typename T>
+void vec_comb3(const cx<T>* x, cx<double> a, const cx<T>* y, cx<double> b, const cx<T>* z, cx<double> c, cx<T>* out,
+               int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(zcomb3<T>, grid1(n), dim3(VB), 0, s, x, cx<T>{(T)a.re, (T)a.im}, y, cx<T>{(T)b.re, (T)b.im}, z,
+                       cx<T>{(T)c.re, (T)c.im}, out, n);
+}
 void vec_to32(const cx<double>* x, cx<float>* y, int64_t n, hipStream_t s) {
     hipLaunchKernelGGL((zconvert<double, float>), grid1(n), dim3(VB), 0, s, x, y, n);
 }
@@ -176,7 +195,9 @@ void vec_acc32(const cx<float>* d, cx<double>* x, int64_t n, hipStream_t s) {
     template void vec_gemv_add<T>(const cx<T>*, int64_t, int, const cx<double>*, cx<T>*, int64_t,          \
                                   hipStream_t);                                                            \
     template void vec_scale<T>(const cx<T>*, double, cx<T>*, int64_t, hipStream_t);                        \
-    template void vec_sub<T>(const cx<T>*, const cx<T>*, cx<T>*, int64_t, hipStream_t);
+    template void vec_sub<T>(const cx<T>*, const cx<T>*, cx<T>*, int64_t, hipStream_t);                    \
+    template void vec_comb3<T>(const cx<T>*, cx<double>, const cx<T>*, cx<double>, const cx<T>*, cx<double>, \
+                               cx<T>*, int64_t, hipStream_t);
 CELES_VEC_INST(double)
 CELES_VEC_INST(float)
 

@@ -75,11 +75,15 @@ def test_create_rejects_bad_input_before_device_use():
     with pytest.raises(P.CelesError) as e:
         P.Problem(np.zeros((1, 3)), [-1.0], 1.5, 1.0, 550.0, 3)
     assert e.value.name == "CELES_E_NONFINITE"
+    with pytest.raises(P.CelesError) as e:
+        P.Problem(np.zeros((1, 3)), [100.0], 1.5, 1.0, 550.0, 3, solver=7)
+    assert e.value.name == "CELES_E_ARG"
 
 
 def test_default_options():
     o = P.default_options()
     assert o.precision == P.CELES_FP64 and o.hankel == P.CELES_HANKEL_LUT
     assert o.lut_dr == 1.0 and o.restart == 100
+    assert o.solver == P.CELES_SOLVER_GMRES
     with pytest.raises(KeyError):
         P.default_options(nonsense=1)
