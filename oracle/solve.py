@@ -201,3 +201,21 @@ def bicgstab(matvec, rhs, tol=1e-10, maxiter=10000, precond=None, x0=None, trace
         if run_its == 0:
             hist.append(np.linalg.norm(rhs - matvec(x)) / nb)
             return x, its, hist
+
+
+def subsystem_initial_guess(pos, radii, n_sphere, n0, wavelength, L, a_in, idx, hankel=None):
+    """Custom initial condition of Section 4.2: the solution of the master
+    equation of a sub-ensemble (the spheres idx, under the same incident
+    field) placed at those spheres, zero at all others.  a_in: [N][nmax]
+    incident coefficients of the whole ensemble (a sphere's coefficients
+    depend only on its own position, so the sub-ensemble's are the rows idx);
+    hankel: None or a Hankel table built for the sub-ensemble.  Returns the
+    initial guess [N][nmax]."""
+    idx = np.asarray(idx, dtype=np.int64)
+    pos = np.asarray(pos, dtype=float)
+    M, W, t = master_matrix(pos[idx], np.asarray(radii)[idx], np.asarray(n_sphere)[idx], n0, wavelength, L, hankel)
+    rhs = t * np.asarray(a_in)[idx].reshape(-1)
+    b = solve_dense(M, rhs).reshape(len(idx), -1)
+    x0 = np.zeros_like(np.asarray(a_in, dtype=np.complex128))
+    x0[idx] = b
+    return x0
