@@ -73,6 +73,26 @@ def bohren_huffman_ab(nmax, x, m):
     return a, b
 
 
+def bohren_huffman_S1_S2(nmax, x, m, theta):
+    """Textbook scattering amplitudes S1(theta), S2(theta) of a sphere
+    (Bohren & Huffman): S1 = sum (2n+1)/(n(n+1)) (a_n pi_n + b_n tau_n),
+    S2 = sum (2n+1)/(n(n+1)) (a_n tau_n + b_n pi_n), with the angular
+    functions pi_n, tau_n of cos(theta) from their upward recurrences (not
+    the normalized Legendre functions the rest of the oracle uses)."""
+    a, b = bohren_huffman_ab(nmax, x, m)
+    mu = np.cos(np.atleast_1d(theta))
+    S1 = np.zeros(mu.shape, dtype=np.complex128)
+    S2 = np.zeros(mu.shape, dtype=np.complex128)
+    pi_prev, pi_cur = np.zeros_like(mu), np.ones_like(mu)        # pi_0, pi_1
+    for n in range(1, nmax + 1):
+        tau = n * mu * pi_cur - (n + 1) * pi_prev
+        f = (2.0 * n + 1.0) / (n * (n + 1.0))
+        S1 += f * (a[n - 1] * pi_cur + b[n - 1] * tau)
+        S2 += f * (a[n - 1] * tau + b[n - 1] * pi_cur)
+        pi_prev, pi_cur = pi_cur, ((2.0 * n + 1.0) / n) * mu * pi_cur - ((n + 1.0) / n) * pi_prev
+    return S1, S2
+
+
 def T_vector(L, k, radii, n_sphere, n0=1.0):
     """Diagonal of the block T-matrix as [N, nmax] (Q_{tau l} repeated over m)."""
     radii = np.atleast_1d(radii)

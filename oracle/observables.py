@@ -52,6 +52,24 @@ def far_field(k, pos, b, L, theta, phi):
     return F
 
 
+def phase_function_s11(k, pos, b_runs, L, theta, n_phi=64):
+    """(1,1) element of the phase matrix as the paper obtains it (Section 4,
+    validation): the far-field intensity |F(theta, phi)|^2 averaged over
+    runs with different incident polarisations (b_runs: list of [N, nmax]
+    coefficient arrays, e.g. TE and TM) and over n_phi equally spaced
+    azimuths phi_j = 2 pi j / n_phi.  Not normalised: k^2 times the
+    polarisation-averaged differential scattering cross section; divide by
+    the value at theta = 0 for the S11(0) = 1 convention."""
+    theta = np.atleast_1d(np.asarray(theta, dtype=float))
+    out = np.zeros(theta.size)
+    phis = 2.0 * np.pi * np.arange(n_phi) / n_phi
+    for b in b_runs:
+        for ph in phis:
+            F = far_field(k, pos, b, L, theta, np.full(theta.size, ph))
+            out += np.sum(np.abs(F) ** 2, axis=1)
+    return out / (len(b_runs) * n_phi)
+
+
 def scattering_cross_section(k, pos, b, L, n_theta=None, n_phi=None):
     """C_sca by Gauss-Legendre quadrature in cos(theta) and the trapezoid rule
     in phi, sized from the band limit L + k D (D = cluster diameter)."""
