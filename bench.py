@@ -295,14 +295,89 @@ def mixed_mode(a):
         "solution_rel_diff_mixed_vs_fp64_at_1e-8": diff, "results": results}))
 
 
+def _cyl_workload(args):
+    n, vf = args
+    from celes_inputs import cylinder_workload
+    return cylinder_workload(n, vf)
+
+
 def paper_mode(a):
-    """The paper's run-time comparison setting (Section 4, Table 1 row N = 2e4,
-    vf 10 %): 20,000 spheres of R = 100 nm, n = 1.5, in a cylindrical slab,
-    lambda = 532 nm, lmax 3, Gaussian beam (waist 4 um), solved to 1e-4 with
-    and without a block-diagonal preconditioner of about 200 spheres per
-    cuboid; FP64 and mixed precision; GMRES and (--paper-solvers) BiCGSTAB,
-    the two solvers of Section 3.2.  One BiCGSTAB iteration costs two
-    mat-vecs."""
+    """The paper's run-time comparison setting (Section 4, Table 1: N = 1e4
+    and 2e4 at vf 10 % and 50 %): spheres of R = 100 nm, n = 1.5, in a
+    cylindrical slab, lambda = 532 nm, lmax 3, Gaussian beam (waist 4 um),
+    solved to 1e-4 with and without a block-diagonal preconditioner of about
+    200 spheres per cuboid; FP64 and mixed precision; GMRES and
+    (--paper-solvers) BiCGSTAB, the two solvers of Section 3.2.  One BiCGSTAB
+    iteration costs two mat-vecs."""
+    import numpy as np
+    import torch
+    import paper_1706_02145_amd as P
+    from concurrent.futures import ProcessPoolExecutor
+
+    t0 = time.perf_counter()
+
+    def log(msg):
+        print(f"[paper] {msg} ({time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
+
+    rows = [(int(r.split(":")[0]), float(r.split(":")[1])) for r in a.paper_rows.split(",")]
+    with ProcessPoolExecutor(min(16, len(rows), os.cpu_count() or 1)) as ex:
+        wls = list(ex.map(_cyl_workload, rows))
+    log(f"{len(wls)} geometries generated")
+    solvers = {"gmres": P.CELES_SOLVER_GMRES, "bicgstab": P.CELES_SOLVER_BICGSTAB}
+    results, summary = {}, {}
+    for (n, vf), w in zip(rows, wls):
+        il = w.illumination
+        edge = (200 * 4.0 / 3.0 * np.pi * 100.0 ** 3 / vf) ** (1.0 / 3.0)   # ~200 spheres per cuboid
+        row = f"N={n} vf={vf:g}"
+        res = {}
+        runs = [(sv, name, prec, pre) for sv in a.paper_solvers.split(",")
+                for name, prec in (("fp64", P.CELES_FP64), ("mixed", P.CELES_MIXED)) for pre in (False, True)]
+        for sv, name, prec, pre in runs:
+            p = P.Problem(w.positions, w.radii, w.n_sphere, w.n0, w.wavelength, w.lmax,
+                          hankel=P.CELES_HANKEL_LUT, lut_dr=w.lut_dr, precision=prec, tol=w.tol, restart=100,
+                          maxiter=5000, inner_tol=1e-3, verbose=1, solver=solvers[sv])
+            p.set_gaussian_beam(il["waist"], il["focus"], il["alpha_G"], il["E0"])
+            t_pre = 0.0
+            if pre:
+                t1 = time.perf_counter()
+                p.build_preconditioner(edge)
+                torch.cuda.synchronize()
+                t_pre = time.perf_counter() - t1
+            t1 = time.perf_counter()
+            _, info = p.solve(check=False)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t1
+            key = ("" if sv == "gmres" else sv + "_") + name + ("_preconditioned" if pre else "")
+            res[key] = {"seconds": dt, "iterations": info["iterations"], "matvecs": info["matvecs"],
+                        "rel_residual": info["rel_residual"], "status": info["status"],
+                        "preconditioner_setup_s": t_pre}
+            log(f"{row} {key}: {dt:.2f} s (+{t_pre:.2f} s set-up), {info['iterations']} iterations, "
+                f"{info['matvecs']} mat-vecs, residual {info['rel_residual']:.2e}")
+            p.close()
+        results[row] = {"cylinder_radius_nm": w.extra["cylinder_radius"], "cuboid_edge_nm": edge, "runs": res}
+        summary[row] = min(v["seconds"] + v["preconditioner_setup_s"] for v in res.values() if v["status"] == 0)
+    head = "N=20000 vf=0.1" if "N=20000 vf=0.1" in summary else next(iter(summary))
+    print(json.dumps({
+        "metric": "solve time to relative residual 1e-4 (the paper's Table 1 setting)", "value": summary[head],
+        "unit": "s", "higher_is_better": False, "n_gpus": 1, "dtype": "f64 / f32", "data": "synthetic",
+        "config": {"workload": f"paper Table 1 rows {list(summary)}: R=100 nm, n=1.5, cylindrical slab t=2 um "
+                               f"(radius from N and vf; RSA at vf 0.1, overlap-relaxation packing at vf 0.5), "
+                               f"lambda=532 nm, lmax 3, Gaussian beam waist 4 um focused on the entry face, "
+                               f"LUT 1 nm, restart 100; value = best time incl. preconditioner set-up for {head}"},
+        "best_seconds_per_row": summary, "results": results,
+        "paper_context": "CELES (paper, Table 1, GTX Titan X, single precision): N=1e4 vf 10 % 1096 s, vf 50 % "
+                         "3463 s; N=2e4 vf 10 % 5663 s, vf 50 % 15951 s; packing (Lubachevsky-Stillinger) and "
+                         "slab size differ, so this is context, not a like-for-like baseline"}))
+
+
+def validation_mode(a):
+    """The paper's validation target (Section 4): 2,500 spheres (R = 100 nm,
+    n = 1.5) at volume fraction 10 % in a ball centred on the origin, Gaussian
+    beam (waist 4 um, lambda = 532 nm) focused on the centre, lmax 3, LUT
+    1 nm, solved to 1e-6 (block-diagonal preconditioner) once with TE and once
+    with TM polarisation.  Reports the reflected and transmitted power
+    fractions with the energy balance R + T + A - 1, and S11(theta) (far-field
+    intensity averaged over both runs and the azimuth, S11(0) = 1)."""
     import numpy as np
     import torch
     import paper_1706_02145_amd as P
@@ -311,71 +386,69 @@ def paper_mode(a):
     t0 = time.perf_counter()
 
     def log(msg):
-        print(f"[paper] {msg} ({time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
+        print(f"[validation] {msg} ({time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
 
-    w = workload("paper_cyl20000_vf10")
+    w = workload("paper_ball2500_vf10")
     il = w.illumination
-    log(f"{w.name} generated (N={w.N}, cylinder radius {w.extra['cylinder_radius']:.0f} nm)")
-    edge = (200 * 4.0 / 3.0 * np.pi * 100.0 ** 3 / 0.10) ** (1.0 / 3.0)   # ~200 spheres per cuboid
-    res = {}
-    solvers = {"gmres": P.CELES_SOLVER_GMRES, "bicgstab": P.CELES_SOLVER_BICGSTAB}
-    runs = [(sv, name, prec, pre) for sv in a.paper_solvers.split(",")
-            for name, prec in (("fp64", P.CELES_FP64), ("mixed", P.CELES_MIXED)) for pre in (False, True)]
-    for sv, name, prec, pre in runs:
+    log(f"{w.name} generated (N={w.N}, ball radius {w.extra['ball_radius']:.0f} nm)")
+    runs, res = [], {}
+    for name, alpha_G in (("TE", 0.0), ("TM", np.pi / 2)):
         p = P.Problem(w.positions, w.radii, w.n_sphere, w.n0, w.wavelength, w.lmax, hankel=P.CELES_HANKEL_LUT,
-                      lut_dr=w.lut_dr, precision=prec, tol=w.tol, restart=100, maxiter=3000,
-                      inner_tol=1e-3, verbose=1, solver=solvers[sv])
-        p.set_gaussian_beam(il["waist"], il["focus"], il["alpha_G"], il["E0"])
-        t_pre = 0.0
-        if pre:
-            t1 = time.perf_counter()
-            p.build_preconditioner(edge)
-            torch.cuda.synchronize()
-            t_pre = time.perf_counter() - t1
-        p.solve(check=False)                        # warm-up (allocations)
+                      lut_dr=w.lut_dr, tol=w.tol, restart=100, maxiter=3000)
+        p.set_gaussian_beam(il["waist"], il["focus"], alpha_G, il["E0"])
+        p.build_preconditioner(a.cuboid_edge)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        _, info = p.solve(check=False)
-        torch.cuda.synchronize()
+        _, info = p.solve()
         dt = time.perf_counter() - t1
-        key = ("" if sv == "gmres" else sv + "_") + name + ("_preconditioned" if pre else "")
-        res[key] = {"seconds": dt, "iterations": info["iterations"], "matvecs": info["matvecs"],
-                    "rel_residual": info["rel_residual"], "status": info["status"], "preconditioner_setup_s": t_pre}
-        log(f"{key}: {dt:.2f} s, {info['iterations']} iterations, {info['matvecs']} mat-vecs, "
-            f"residual {info['rel_residual']:.2e}")
-        p.close()
-    best = min(v["seconds"] + v["preconditioner_setup_s"] for v in res.values() if v["status"] == 0)
+        Pin, R, T, A = p.power_flux()[0]
+        res[name] = {"seconds": dt, "iterations": info["iterations"], "rel_residual": info["rel_residual"],
+                     "R": R, "T": T, "A": A, "energy_balance": R + T + A - 1.0}
+        log(f"{name}: {info['iterations']} iterations, {dt:.2f} s; R {R:.4%} T {T:.4%} A {A:.2e} "
+            f"R+T+A-1 {R + T + A - 1:.2e}")
+        runs.append(p)
+    theta_deg = np.arange(0, 181, 5)
+    t1 = time.perf_counter()
+    s11 = P.s11(runs, np.radians(theta_deg), n_phi=64)
+    log(f"S11 at {theta_deg.size} angles x 64 azimuths x 2 runs in {time.perf_counter() - t1:.2f} s")
     print(json.dumps({
-        "metric": "solve time to relative residual 1e-4 (the paper's Table 1 setting)", "value": best, "unit": "s",
-        "higher_is_better": False, "n_gpus": 1, "dtype": "f64 / f32", "data": "synthetic",
-        "config": {"workload": f"{w.name}: N={w.N}, R=100 nm, n=1.5, vf 0.10, cylindrical slab t=2 um "
-                               f"(radius {w.extra['cylinder_radius']:.0f} nm, RSA), lambda=532 nm, lmax 3, "
-                               f"Gaussian beam waist 4 um focused on the entry face, LUT 1 nm, restart 100; "
-                               f"preconditioner cuboid edge {edge:.0f} nm"},
+        "metric": "energy balance R + T + A - 1 of the validation target (TE and TM)",
+        "value": max(abs(v["energy_balance"]) for v in res.values()), "unit": "relative",
+        "higher_is_better": False, "n_gpus": 1, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{w.name}: N={w.N}, R=100 nm, n=1.5, vf 0.10 in a ball of radius "
+                               f"{w.extra['ball_radius']:.0f} nm (RSA), lambda=532 nm, lmax 3, Gaussian beam waist "
+                               f"4 um focused on the centre, LUT 1 nm, tolerance {w.tol:g}, preconditioner cuboid "
+                               f"edge {a.cuboid_edge:g} nm"},
         "results": res,
-        "paper_context": "CELES (paper, Table 1): 5663 s for N = 2e4, vf 10 %, GTX Titan X, single precision, "
-                         "best of preconditioned / unpreconditioned; packing and slab size differ (LS packing, "
-                         "dimensions unstated), so this is context, not a like-for-like baseline"}))
+        "s11_theta_deg": theta_deg.tolist(), "s11_normalised": (s11 / s11[0]).tolist(),
+        "paper_context": "paper (Section 4 validation, Lubachevsky-Stillinger packing, its own geometry): "
+                         "R 16.25 %, T 83.73 %, R + T = 1 within 1e-3"}))
 
 
 def scaling_mode(a):
     """Convergence and run time against system size (the analogue of the
     paper's Figs. 4-5): the paper's setting (R = 100 nm, lambda = 532 nm,
     lmax 3, Gaussian beam, tolerance 1e-4) in cylindrical slabs of
-    N = 2,500 ... 20,000 spheres at volume fractions 0.1 and 0.3 (RSA does not
-    reach 0.5), FP64 GMRES with and without the block-diagonal preconditioner
-    of about 200 spheres per cuboid.  One JSON line per run, then a summary."""
+    N = 2,500 ... 20,000 spheres at volume fractions 0.1, 0.3 and 0.5
+    (--scaling-vfs; 0.5 packed by overlap relaxation), FP64 GMRES with and
+    without the block-diagonal preconditioner of about 200 spheres per
+    cuboid.  One JSON line per run, then a summary."""
     import numpy as np
     import torch
     import paper_1706_02145_amd as P
-    from celes_inputs import cylinder_workload
+    from concurrent.futures import ProcessPoolExecutor
 
     t0 = time.perf_counter()
     rows = []
-    for vf in (0.1, 0.3):
+    vfs = [float(v) for v in a.scaling_vfs.split(",")]
+    cases = [(n, vf) for vf in vfs for n in (2500, 5000, 10000, 20000)]
+    with ProcessPoolExecutor(min(16, len(cases), os.cpu_count() or 1)) as ex:
+        wls = dict(zip(cases, ex.map(_cyl_workload, cases)))
+    print(f"[scaling] {len(wls)} geometries generated ({time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
+    for vf in vfs:
         edge = (200 * 4.0 / 3.0 * np.pi * 100.0 ** 3 / vf) ** (1.0 / 3.0)
         for n in (2500, 5000, 10000, 20000):
-            w = cylinder_workload(n, vf)
+            w = wls[(n, vf)]
             il = w.illumination
             for pre in (False, True):
                 p = P.Problem(w.positions, w.radii, w.n_sphere, w.n0, w.wavelength, w.lmax,
@@ -403,8 +476,9 @@ def scaling_mode(a):
 def warmstart_mode(a):
     """Learned initial guess: train on solver output of several slabs
     (lmax 3, N = a.train_n each), evaluate on a larger unseen slab: GMRES
-    iterations and time to residual 1e-6 from x0 = 0, x0 = T a_in and the
-    network's prediction."""
+    iterations and time to residual 1e-6 from x0 = 0, x0 = T a_in, the
+    network's prediction and the solution of a central sub-ensemble (the
+    paper's custom initial condition, Section 4.2)."""
     import numpy as np
     import torch
     import paper_1706_02145_amd as P
@@ -449,7 +523,14 @@ def warmstart_mode(a):
     t1 = time.perf_counter()
     x_net = net.predict(p)
     t_pred = time.perf_counter() - t1
-    guesses = {"zero": None, "T_a_in": rhs[None], "network": x_net[None]}
+    # sub-ensemble guess (Section 4.2): the spheres within a.sub_radius of
+    # the slab's axis solved alone (block-diagonal preconditioner)
+    sub = np.nonzero(np.hypot(pos[:, 0], pos[:, 1]) < a.sub_radius)[0]
+    t1 = time.perf_counter()
+    x_sub, sub_info = p.subsystem_guess(sub, cuboid_edge=a.cuboid_edge)
+    t_sub = time.perf_counter() - t1
+    log(f"sub-ensemble guess: {sub.size} spheres, {sub_info['iterations']} iterations, {t_sub:.2f} s")
+    guesses = {"zero": None, "T_a_in": rhs[None], "network": x_net[None], "subsystem": x_sub}
 
     def initial_residual(x0):
         # || T a_in - M x0 || / || T a_in ||, M x0 by the FP64 mat-vec
@@ -471,14 +552,16 @@ def warmstart_mode(a):
             t1 = time.perf_counter()
             _, info = p.solve(x0=x0)
             dt = time.perf_counter() - t1
-            key = ("" if sv == "gmres" else sv + "_") + name + ("_preconditioned" if pre else "")
+            key = name + ("_preconditioned" if pre else "")
             res[key] = {"iterations": info["iterations"], "seconds": dt, "x0_used": info["x0_used"],
                         "rel_residual": info["rel_residual"], "initial_rel_residual": initial_residual(x0)}
             log(f"x0 = {key}: {info['iterations']} iterations, {dt:.2f} s, "
                 f"initial residual {res[key]['initial_rel_residual']:.3f}")
     res["network"]["predict_seconds"] = t_pred
+    res["subsystem"].update({"guess_seconds": t_sub, "spheres": int(sub.size), "guess_iterations": sub_info["iterations"]})
     print(json.dumps({
         "metric": "GMRES iterations and time to residual 1e-6 with a learned initial guess",
+        "guess_comparators": "zero, T a_in (single scattering), sub-ensemble solution",
         "value": res["network"]["seconds"], "unit": "s", "higher_is_better": False, "n_gpus": 1,
         "dtype": "f64 solve, bf16/f32 network", "data": "synthetic",
         "config": {"workload": f"train {a.train_slabs} slabs N={a.train_n}, evaluate N={a.eval_n}, lmax 3, "
@@ -501,10 +584,12 @@ def main():
     ap.add_argument("--cuboid-edge", type=float, default=1500.0)
     ap.add_argument("--hankel", choices=["lut", "direct"], default="lut")
     ap.add_argument("--profile", action="store_true", help="mat-vec launches only (for rocprofv3)")
-    ap.add_argument("--mode", choices=["solve", "batched", "warmstart", "mixed", "paper", "scaling"],
+    ap.add_argument("--mode", choices=["solve", "batched", "warmstart", "mixed", "paper", "scaling", "validation"],
                     default="solve")
     ap.add_argument("--mixed-workload", default="slab20000_l4")
-    ap.add_argument("--paper-solvers", default="gmres,bicgstab", help="paper mode: comma-separated gmres,bicgstab")
+    ap.add_argument("--paper-solvers", default="gmres", help="paper mode: comma-separated gmres,bicgstab")
+    ap.add_argument("--paper-rows", default="10000:0.1,10000:0.5,20000:0.1,20000:0.5",
+                    help="paper mode: comma-separated N:vf rows of Table 1")
     ap.add_argument("--realisations", type=int, default=32)
     ap.add_argument("--batch-tol", type=float, default=1e-6)
     ap.add_argument("--batch-maxiter", type=int, default=600)
@@ -513,6 +598,8 @@ def main():
     ap.add_argument("--train-n", type=int, default=2000)
     ap.add_argument("--eval-n", type=int, default=20000)
     ap.add_argument("--epochs", type=int, default=40)
+    ap.add_argument("--scaling-vfs", default="0.1,0.3,0.5", help="scaling mode: volume fractions")
+    ap.add_argument("--sub-radius", type=float, default=5000.0, help="warmstart: sub-ensemble radius (nm)")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
@@ -528,6 +615,8 @@ def main():
         return paper_mode(a)
     if a.mode == "scaling":
         return scaling_mode(a)
+    if a.mode == "validation":
+        return validation_mode(a)
 
     import numpy as np
     import torch

@@ -8,7 +8,7 @@ and the slab thickness, and derive the lateral side from them.
 from dataclasses import dataclass, field
 import numpy as np
 
-from .packing import rsa_box, rsa_cylinder, uniform_box, lognormal_radii, slab_side_for_fraction
+from .packing import relax_pack_cylinder, rsa_ball, rsa_box, rsa_cylinder, uniform_box, lognormal_radii, slab_side_for_fraction
 
 
 @dataclass
@@ -53,13 +53,32 @@ def _cylinder(name, seed, n, vf, thickness=2000.0, radius=100.0):
     (R = 100 nm, n = 1.5) at a given volume fraction in a cylindrical slab,
     lambda = 532 nm, lmax 3, Gaussian beam (waist 4 um) focused on the centre
     of the entry face, GMRES tolerance 1e-4.  The slab's thickness is not
-    stated there; 2 um is used and the cylinder radius follows from N and vf."""
+    stated there; 2 um is used and the cylinder radius follows from N and vf.
+    Packing: random sequential addition up to vf 0.35, overlap relaxation
+    with growth (relax_pack_cylinder) above."""
     rcyl = float(np.sqrt(n * 4.0 / 3.0 * np.pi * radius ** 3 / (vf * np.pi * thickness)))
     radii = np.full(n, radius)
-    pos = rsa_cylinder(seed, radii, rcyl, thickness)
+    if vf <= 0.35:
+        pos = rsa_cylinder(seed, radii, rcyl, thickness)
+    else:     # beyond random sequential addition (the paper packs with Lubachevsky-Stillinger)
+        pos = relax_pack_cylinder(seed, n, radius, rcyl, thickness)
     ill = {"kind": "gaussian", "waist": 4000.0, "focus": (0.0, 0.0, 0.0), "alpha_G": -np.pi / 2, "E0": 1.0}
     return Workload(name, pos, radii, np.full(n, 1.5 + 0j), 1.0, 532.0, 3, ill, 1e-4, 1.0,
                     (2 * rcyl, 2 * rcyl, thickness), {"cylinder_radius": rcyl})
+
+
+def _ball(name, seed, n, vf, radius=100.0):
+    """The validation target of the paper's Section 4: N spheres (R = 100 nm,
+    n = 1.5) at volume fraction vf inside a spherical region centred on the
+    origin, lambda = 532 nm, lmax 3, Gaussian beam (waist 4 um) focused on the
+    centre.  The paper packs with Lubachevsky-Stillinger; at vf 0.1 random
+    sequential addition reaches the same density."""
+    rball = float(radius * (n / vf) ** (1.0 / 3.0))
+    radii = np.full(n, radius)
+    pos = rsa_ball(seed, radii, rball)
+    ill = {"kind": "gaussian", "waist": 4000.0, "focus": (0.0, 0.0, 0.0), "alpha_G": 0.0, "E0": 1.0}
+    return Workload(name, pos, radii, np.full(n, 1.5 + 0j), 1.0, 532.0, 3, ill, 1e-6, 1.0,
+                    (2 * rball, 2 * rball, 2 * rball), {"ball_radius": rball})
 
 
 def _small_cube():
@@ -83,6 +102,7 @@ def _plane_normal():
 _BUILDERS = {
     # the paper's run-time comparison setting (N = 2e4, vf 10 %, cylindrical slab)
     "paper_cyl20000_vf10": lambda: _cylinder("paper_cyl20000_vf10", 6001, 20000, 0.10),
+    "paper_ball2500_vf10": lambda: _ball("paper_ball2500_vf10", 7001, 2500, 0.10),
     # 8 spheres, R = 100 nm, n = 1.5+0.01i, lmax 3, x-polarised plane wave along +z
     "cube8_l3": _small_cube,
     # 2,000-sphere slab, t = 2 um, lmax 4, Gaussian beam w = 2 um, FP64 GMRES 1e-8

@@ -167,6 +167,22 @@ int celes_build_preconditioner(celes_handle* h, double cuboid_edge);
  * CELES_E_BREAKDOWN, CELES_E_STATE, CELES_E_DEVICE. */
 int celes_solve(celes_handle* h, const double* x0, double* b_out, celes_solve_info* info);
 
+/* Initial guess from a sub-ensemble (Section 4.2: the solver accepts a custom
+ * initial condition, typically the solution of a smaller system made of a
+ * subset of the spheres).  Solves the master equation of the n_sub spheres
+ * idx [n_sub] (distinct indices into this problem) alone, under this
+ * problem's incident field (their rows of a_in) and options (precision,
+ * solver, tolerance, Hankel mode), with a block-diagonal preconditioner of
+ * cuboid edge `cuboid_edge` (<= 0: none), and writes x0_out [K][N][nmax]
+ * complex128 (host): the sub-ensemble's coefficients at its spheres, zero at
+ * all others, ready for celes_solve.  info (may be NULL) receives the
+ * sub-solve's statistics.  Device memory of the sub-problem is released on
+ * return.  Errors: CELES_E_ARG (range, repeats, null), CELES_E_STATE (no
+ * incident field), CELES_E_NOCONV (x0_out holds the sub-solve's best
+ * iterate), those of celes_create and celes_solve. */
+int celes_subsystem_guess(celes_handle* h, int64_t n_sub, const int64_t* idx, double cuboid_edge, double* x0_out,
+                          celes_solve_info* info);
+
 /* Hot path, device pointers: y = W x for K right-hand sides (Section 2.2,
  * eq. a: (W x)^i_n = sum_{i' != i} sum_{n'} A_{n'n}(r_i - r_{i'}) x^{i'}_{n'}),
  * W evaluated on the fly per sphere pair (Section 3.2.2).  precision
@@ -193,6 +209,18 @@ int celes_cross_sections(celes_handle* h, double* C_ext, double* C_sca, double* 
  * cartesian complex.  Errors: CELES_E_STATE, CELES_E_ARG. */
 int celes_far_field(celes_handle* h, int64_t ndir, const double* theta, const double* phi,
                     double* F_out);
+
+/* (1,1) element of the phase matrix as the paper's validation obtains it
+ * (Section 4): the far-field intensity |F(theta, phi)|^2 averaged over every
+ * solved right-hand side of the nh problems hs (e.g. one TE and one TM run,
+ * or one problem with both plane waves) and over n_phi azimuths
+ * phi_j = 2 pi j / n_phi, at n_theta polar angles theta.  out [n_theta]:
+ * k^2 times the polarisation-averaged differential scattering cross section
+ * (unnormalised; divide by the value at theta = 0 for S11(0) = 1).  Host
+ * computation from the last solutions.  Errors: CELES_E_ARG (null, sizes,
+ * problems of different wavenumbers), CELES_E_STATE (a problem without a
+ * solution; its last error says so). */
+int celes_s11(celes_handle* const* hs, int nh, int64_t n_theta, const double* theta, int n_phi, double* out);
 
 /* Electric near field at npt points outside all spheres (Section 2.1, eq.
  * Escat summed over spheres), plus the incident field when add_incident != 0;

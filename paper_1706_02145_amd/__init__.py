@@ -13,6 +13,7 @@ from ._capi import (CELES_FP64, CELES_HANKEL_DIRECT, CELES_HANKEL_LUT, CELES_MIX
                     CELES_SOLVER_GMRES, ERRORS, Options, SolveInfo, lib, LIB_PATH)
 
 __all__ = ["Problem", "Batch", "Network", "CelesError", "default_options", "mie_coefficients", "translation_tables", "version",
+           "s11",
            "CELES_FP64", "CELES_MIXED", "CELES_HANKEL_LUT", "CELES_HANKEL_DIRECT", "CELES_SOLVER_GMRES",
            "CELES_SOLVER_BICGSTAB", "LIB_PATH"]
 
@@ -69,6 +70,20 @@ def _stream_ptr(stream):
     if stream is None:
         return None
     return C.c_void_p(int(getattr(stream, "cuda_stream", stream)))
+
+
+def s11(problems, theta, n_phi=64):
+    """Phase-function element S11(theta): |F|^2 averaged over the solved
+    right-hand sides of `problems` and over n_phi azimuths (celes_s11),
+    unnormalised."""
+    probs = list(problems)
+    th = np.ascontiguousarray(np.atleast_1d(theta), dtype=np.float64)
+    out = np.zeros(th.size)
+    arr = (C.c_void_p * len(probs))(*[p._h.value for p in probs])
+    rc = lib().celes_s11(arr, len(probs), th.size, _dptr(th), int(n_phi), _dptr(out))
+    if rc != 0:
+        raise CelesError(rc, "a problem has no solution" if rc == -10 else "invalid arguments to celes_s11")
+    return out
 
 
 class Problem:
@@ -154,6 +169,18 @@ class Problem:
         if check and rc not in (0,):
             _check(rc, self._h)
         return b, {f: getattr(info, f) for f, _ in SolveInfo._fields_}
+
+    def subsystem_guess(self, idx, cuboid_edge=0.0, check=True):
+        """Initial guess [K][N][nmax] from solving the sub-ensemble idx alone
+        (celes_subsystem_guess); returns (x0, info of the sub-solve)."""
+        ix = np.ascontiguousarray(np.atleast_1d(idx), dtype=np.int64)
+        x0 = np.zeros((self.num_rhs, self.N, self.nmax), dtype=np.complex128)
+        info = SolveInfo()
+        rc = lib().celes_subsystem_guess(self._h, ix.size, ix.ctypes.data_as(C.POINTER(C.c_int64)),
+                                         float(cuboid_edge), _dptr(x0.view(np.float64)), C.byref(info))
+        if check and rc != 0:
+            _check(rc, self._h)
+        return x0, {f: getattr(info, f) for f, _ in SolveInfo._fields_}
 
     def apply_W(self, x, y, precision=CELES_FP64, stream=None, K=1):
         """y = W x on device buffers (torch tensors or raw pointers)."""

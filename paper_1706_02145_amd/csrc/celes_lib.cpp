@@ -1143,6 +1143,60 @@ int celes_solve(celes_handle* h, const double* x0, double* b_out, celes_solve_in
     return celes_guard([&] { return celes_solve_impl(h, x0, b_out, info); });
 }
 
+// Sub-ensemble initial guess (Section 4.2): a problem of the spheres idx
+// alone, with their rows of the incident coefficients, solved with this
+// problem's options; its solution is scattered into x0 (zero elsewhere).
+static int celes_subsystem_guess_impl(celes_handle* h, int64_t n_sub, const int64_t* idx, double cuboid_edge,
+                                      double* x0_out, celes_solve_info* info) {
+    if (!h) return CELES_E_ARG;
+    if (n_sub < 1 || n_sub > h->N || !idx || !x0_out) return fail(h, CELES_E_ARG, "n_sub out of range or null array");
+    if (h->K < 1) return fail(h, CELES_E_STATE, "no incident field set");
+    std::vector<char> seen(h->N, 0);
+    for (int64_t j = 0; j < n_sub; ++j) {
+        if (idx[j] < 0 || idx[j] >= h->N) return fail(h, CELES_E_ARG, "sphere index out of range");
+        if (seen[idx[j]]) return fail(h, CELES_E_ARG, "repeated sphere index");
+        seen[idx[j]] = 1;
+    }
+    const int nm = h->nmax;
+    std::vector<double> pos(3 * n_sub), rad(n_sub), ns(2 * n_sub);
+    for (int64_t j = 0; j < n_sub; ++j) {
+        const int64_t i = idx[j];
+        for (int c = 0; c < 3; ++c) pos[3 * j + c] = h->pos[3 * i + c];
+        rad[j] = h->radius[i];
+        ns[2 * j] = h->nsph[i].real();
+        ns[2 * j + 1] = h->nsph[i].imag();
+    }
+    celes_options o = h->opt;
+    o.cuboid_edge = 0.0;
+    celes_handle* raw = nullptr;
+    int rc = celes_create_impl(&raw, n_sub, pos.data(), rad.data(), ns.data(), h->n0, h->wavelength, h->L, &o);
+    if (rc != CELES_OK) return fail(h, rc, "sub-ensemble: " + g_create_error);
+    std::unique_ptr<celes_handle> sub(raw);
+    // a sphere's incident coefficients depend on its own position only
+    sub->K = h->K;
+    sub->a_in.assign((size_t)h->K * n_sub * nm, cplx(0, 0));
+    for (int kk = 0; kk < h->K; ++kk)
+        for (int64_t j = 0; j < n_sub; ++j)
+            std::copy_n(&h->a_in[((size_t)kk * h->N + idx[j]) * nm], nm, &sub->a_in[((size_t)kk * n_sub + j) * nm]);
+    if (cuboid_edge > 0 && (rc = celes_build_preconditioner_impl(sub.get(), cuboid_edge)) != CELES_OK)
+        return fail(h, rc, "sub-ensemble preconditioner: " + sub->err);
+    std::vector<double> bs((size_t)h->K * n_sub * nm * 2);
+    celes_solve_info si{};
+    rc = celes_solve_impl(sub.get(), nullptr, bs.data(), &si);
+    if (info) *info = si;
+    if (rc != CELES_OK && rc != CELES_E_NOCONV) return fail(h, rc, "sub-ensemble solve: " + sub->err);
+    std::fill(x0_out, x0_out + (size_t)h->K * h->N * nm * 2, 0.0);
+    for (int kk = 0; kk < h->K; ++kk)
+        for (int64_t j = 0; j < n_sub; ++j)
+            std::copy_n(&bs[((size_t)kk * n_sub + j) * nm * 2], 2 * nm, &x0_out[((size_t)kk * h->N + idx[j]) * nm * 2]);
+    if (rc == CELES_E_NOCONV) h->err = "sub-ensemble solve: " + sub->err;
+    return rc;
+}
+int celes_subsystem_guess(celes_handle* h, int64_t n_sub, const int64_t* idx, double cuboid_edge, double* x0_out,
+                          celes_solve_info* info) {
+    return celes_guard([&] { return celes_subsystem_guess_impl(h, n_sub, idx, cuboid_edge, x0_out, info); });
+}
+
 
 static int celes_mie_coefficients_impl(int lmax, double kR, double m_re, double m_im, double* Q_out) {
     if (lmax < 1 || !(kR > 0) || !Q_out) return CELES_E_ARG;
@@ -1257,6 +1311,38 @@ static int celes_far_field_impl(celes_handle* h, int64_t ndir, const double* the
 }
 int celes_far_field(celes_handle* h, int64_t ndir, const double* theta, const double* phi, double* F_out) {
     return celes_guard([&] { return celes_far_field_impl(h, ndir, theta, phi, F_out); });
+}
+
+// S11 as the paper's validation obtains it: |F|^2 averaged over the solved
+// right-hand sides of several problems (e.g. TE and TM runs) and over n_phi
+// equally spaced azimuths
+static int celes_s11_impl(celes_handle* const* hs, int nh, int64_t n_theta, const double* theta, int n_phi,
+                          double* out) {
+    if (nh < 1 || !hs || n_theta < 0 || n_phi < 1 || (n_theta > 0 && (!theta || !out))) return CELES_E_ARG;
+    int runs = 0;
+    for (int j = 0; j < nh; ++j) {
+        celes_handle* h = hs[j];
+        if (!h) return CELES_E_ARG;
+        if (!h->have_solution) return fail(h, CELES_E_STATE, "no solution");
+        if (h->k != hs[0]->k) return fail(h, CELES_E_ARG, "problems of different wavenumbers");
+        runs += h->K;
+    }
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t t = 0; t < n_theta; ++t) {
+        double acc = 0;
+        for (int j = 0; j < nh; ++j)
+            for (int kk = 0; kk < hs[j]->K; ++kk)
+                for (int q = 0; q < n_phi; ++q) {
+                    cplx F[3];
+                    far_field_dir(hs[j], kk, theta[t], 2.0 * M_PI * q / n_phi, F);
+                    acc += std::norm(F[0]) + std::norm(F[1]) + std::norm(F[2]);
+                }
+        out[t] = acc / ((double)runs * n_phi);
+    }
+    return CELES_OK;
+}
+int celes_s11(celes_handle* const* hs, int nh, int64_t n_theta, const double* theta, int n_phi, double* out) {
+    return celes_guard([&] { return celes_s11_impl(hs, nh, n_theta, theta, n_phi, out); });
 }
 
 
