@@ -150,6 +150,16 @@ int celes_num_rhs(const celes_handle* h);
  * Errors: CELES_E_OOM, CELES_E_DEVICE. */
 int celes_build_preconditioner(celes_handle* h, double cuboid_edge);
 
+/* y = P^{-1} x for the block-diagonal preconditioner of the last
+ * celes_build_preconditioner (Section 3.2.1): every cuboid's block of x is
+ * multiplied by the inverse of M_j = I - T W_jj.  precision CELES_FP64:
+ * x_dev, y_dev complex128 [N][nmax] (one right-hand side), FP64 inverses;
+ * CELES_MIXED: complex64 vectors and the complex64 copy of the inverses.
+ * Enqueued on `stream` (NULL = default stream).  x_dev and y_dev must not
+ * alias.  Errors: CELES_E_ARG, CELES_E_STATE (no preconditioner),
+ * CELES_E_DEVICE. */
+int celes_apply_preconditioner(celes_handle* h, int precision, const void* x_dev, void* y_dev, void* stream);
+
 /* Solve the master equation M b = T a_in (Section 2.2, eqs. masterequation
  * and M) for every right-hand side by right-preconditioned restarted GMRES
  * or, with opt.solver = CELES_SOLVER_BICGSTAB, right-preconditioned BiCGSTAB

@@ -48,6 +48,7 @@ SIGNATURES = {
     "celes_num_rhs": (C.c_int, [_h]),
     "celes_build_preconditioner": (C.c_int, [_h, C.c_double]),
     "celes_solve": (C.c_int, [_h, _dp, _dp, C.POINTER(SolveInfo)]),
+    "celes_apply_preconditioner": (C.c_int, [_h, C.c_int, _vp, _vp, _vp]),
     "celes_s11": (C.c_int, [C.c_void_p, C.c_int, C.c_int64, _dp, C.c_int, _dp]),
     "celes_subsystem_guess": (C.c_int, [_h, C.c_int64, C.POINTER(C.c_int64), C.c_double, _dp, C.POINTER(SolveInfo)]),
     "celes_apply_W": (C.c_int, [_h, C.c_int, C.c_int, _vp, _vp, _vp]),

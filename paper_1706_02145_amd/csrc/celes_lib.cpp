@@ -989,6 +989,22 @@ int celes_apply_M(celes_handle* h, int precision, int K, const void* x_dev, void
 }
 
 
+static int celes_apply_preconditioner_impl(celes_handle* h, int precision, const void* x_dev, void* y_dev,
+                                           void* stream) {
+    if (!h) return CELES_E_ARG;
+    if (!x_dev || !y_dev || x_dev == y_dev) return fail(h, CELES_E_ARG, "null or aliasing device pointer");
+    if (!h->pre) return fail(h, CELES_E_STATE, "no preconditioner built");
+    hipStream_t s = (hipStream_t)stream;
+    int rc;
+    if (precision == CELES_FP64) rc = h->pre->apply<double>((const cx<double>*)x_dev, (cx<double>*)y_dev, s);
+    else if (precision == CELES_MIXED) rc = h->pre->apply<float>((const cx<float>*)x_dev, (cx<float>*)y_dev, s);
+    else return fail(h, CELES_E_ARG, "unknown precision");
+    return rc == CELES_OK ? CELES_OK : fail(h, rc, "preconditioner apply failed");
+}
+int celes_apply_preconditioner(celes_handle* h, int precision, const void* x_dev, void* y_dev, void* stream) {
+    return celes_guard([&] { return celes_apply_preconditioner_impl(h, precision, x_dev, y_dev, stream); });
+}
+
 static int celes_build_preconditioner_impl(celes_handle* h, double cuboid_edge) {
     if (!h) return CELES_E_ARG;
     h->pre.reset();

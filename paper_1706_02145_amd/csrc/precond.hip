@@ -4,10 +4,16 @@
 #include <rocsolver/rocsolver.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <numeric>
+#include <thread>
 
 namespace celes {
+
+// concurrent block factorisations during set-up (one host thread, stream and
+// rocBLAS handle each)
+constexpr int PRE_STREAMS = 4;
 
 void partition_cuboids(int64_t N, const double* pos, double edge, std::vector<int64_t>* perm,
                        std::vector<int64_t>* offsets) {
@@ -321,30 +327,66 @@ int BlockPrecond::build(int64_t N, int L, const double* pos, double k, const cpl
     g.L = L;
     g.hmode = hmode;
     g.mat = d_inv_;
-    rocblas_handle rb;
-    if (rocblas_create_handle(&rb) != rocblas_status_success) {
-        *msg = "rocblas_create_handle failed";
-        return CELES_E_DEVICE_INTERNAL;
-    }
-    // one pivot array and two info slots per block, checked once at the end,
-    // so that the blocks' factorisations queue back to back on the stream
-    rocblas_int *d_ipiv = nullptr, *d_info = nullptr;
-    const bool ok_piv = dev((void**)&d_ipiv, (size_t)max_dim_ * sizeof(rocblas_int)) &&
-                        dev((void**)&d_info, (size_t)2 * nb * sizeof(rocblas_int));
-    int rc = ok_piv ? 0 : CELES_E_OOM_INTERNAL;
-    if (!ok_piv) *msg = "cannot allocate pivots";
+    // The blocks are independent: PRE_STREAMS host threads, each with its own
+    // stream, rocBLAS handle and pivot array, take blocks largest first from
+    // a shared counter, so that one block's latency-bound panel kernels
+    // overlap another block's GEMMs.  Each block's arithmetic does not depend
+    // on the schedule.  Two info slots per block are checked once at the end.
+    rocblas_int* d_info = nullptr;
+    int rc = dev((void**)&d_info, (size_t)2 * nb * sizeof(rocblas_int)) ? 0 : CELES_E_OOM_INTERNAL;
+    if (rc != 0) *msg = "cannot allocate factorisation info";
     if (rc == 0) hipMemset(d_info, 0, (size_t)2 * nb * sizeof(rocblas_int));
-    for (int j = 0; j < nb && rc == 0; ++j) {
-        g.blk = j;
-        const int64_t nj = offsets_[j + 1] - offsets_[j];
-        const int64_t ntot = nj * nj * (nmax_ / 2);
-        hipLaunchKernelGGL(assemble_kernel, dim3((unsigned)((ntot + 255) / 256)), dim3(256), 0, 0, g, ntot);
-        const int dim = (int)(nj * nmax_);
-        rocblas_double_complex* A = (rocblas_double_complex*)(d_inv_ + moff[j]);
-        if (rocsolver_zgetrf(rb, dim, dim, A, dim, d_ipiv, d_info + 2 * j) != rocblas_status_success ||
-            rocsolver_zgetri(rb, dim, A, dim, d_ipiv, d_info + 2 * j + 1) != rocblas_status_success) {
-            *msg = "rocsolver LU/inverse failed";
-            rc = CELES_E_DEVICE_INTERNAL;
+    std::vector<int> order(nb);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        return offsets_[x + 1] - offsets_[x] > offsets_[y + 1] - offsets_[y];
+    });
+    const int nstreams = std::max(1, std::min(PRE_STREAMS, nb));
+    std::atomic<int> next{0};
+    std::atomic<int> failed{0};
+    hipDeviceSynchronize();  // tables and index arrays are on the device before any worker starts
+    int device = 0;
+    hipGetDevice(&device);
+    auto worker = [&]() {
+        hipSetDevice(device);
+        hipStream_t st = nullptr;
+        rocblas_handle rb = nullptr;
+        rocblas_int* d_ipiv = nullptr;
+        if (hipStreamCreate(&st) != hipSuccess) {
+            failed = CELES_E_DEVICE_INTERNAL;
+            return;
+        }
+        if (rocblas_create_handle(&rb) != rocblas_status_success || rocblas_set_stream(rb, st) != rocblas_status_success)
+            failed = CELES_E_DEVICE_INTERNAL;
+        else if (hipMalloc((void**)&d_ipiv, (size_t)max_dim_ * sizeof(rocblas_int)) != hipSuccess)
+            failed = CELES_E_OOM_INTERNAL;
+        while (!failed) {
+            const int q = next.fetch_add(1);
+            if (q >= nb) break;
+            const int j = order[q];
+            AsmArgs gj = g;
+            gj.blk = j;
+            const int64_t nj = offsets_[j + 1] - offsets_[j];
+            const int64_t ntot = nj * nj * (nmax_ / 2);
+            hipLaunchKernelGGL(assemble_kernel, dim3((unsigned)((ntot + 255) / 256)), dim3(256), 0, st, gj, ntot);
+            const int dim = (int)(nj * nmax_);
+            rocblas_double_complex* A = (rocblas_double_complex*)(d_inv_ + moff[j]);
+            if (rocsolver_zgetrf(rb, dim, dim, A, dim, d_ipiv, d_info + 2 * j) != rocblas_status_success ||
+                rocsolver_zgetri(rb, dim, A, dim, d_ipiv, d_info + 2 * j + 1) != rocblas_status_success)
+                failed = CELES_E_DEVICE_INTERNAL;
+        }
+        if (hipStreamSynchronize(st) != hipSuccess || hipGetLastError() != hipSuccess) failed = CELES_E_DEVICE_INTERNAL;
+        if (rb) rocblas_destroy_handle(rb);
+        if (d_ipiv) hipFree(d_ipiv);
+        hipStreamDestroy(st);
+    };
+    if (rc == 0) {
+        std::vector<std::thread> pool;
+        for (int t = 0; t < nstreams; ++t) pool.emplace_back(worker);
+        for (auto& th : pool) th.join();
+        if (failed) {
+            rc = failed;
+            *msg = rc == CELES_E_OOM_INTERNAL ? "cannot allocate pivots" : "rocsolver LU/inverse failed";
         }
     }
     if (rc == 0) {
@@ -368,8 +410,6 @@ int BlockPrecond::build(int64_t N, int L, const double* pos, double k, const cpl
         }
     }
     hipDeviceSynchronize();
-    rocblas_destroy_handle(rb);
-    hipFree(d_ipiv);
     hipFree(d_info);
     hipFree(d_a5);
     hipFree(d_b5);
