@@ -103,6 +103,7 @@ _BUILDERS = {
     # the paper's run-time comparison setting (N = 2e4, vf 10 %, cylindrical slab)
     "paper_cyl20000_vf10": lambda: _cylinder("paper_cyl20000_vf10", 6001, 20000, 0.10),
     "paper_ball2500_vf10": lambda: _ball("paper_ball2500_vf10", 7001, 2500, 0.10),
+    "paper_ball100000_vf10": lambda: _ball("paper_ball100000_vf10", 7002, 100000, 0.10),
     # 8 spheres, R = 100 nm, n = 1.5+0.01i, lmax 3, x-polarised plane wave along +z
     "cube8_l3": _small_cube,
     # 2,000-sphere slab, t = 2 um, lmax 4, Gaussian beam w = 2 um, FP64 GMRES 1e-8

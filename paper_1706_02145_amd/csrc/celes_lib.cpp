@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -17,6 +18,7 @@
 #include "../../include/celes.h"
 #include "device_common.hpp"
 #include "host_math.hpp"
+#include "farfield.hpp"
 #include "internal.hpp"
 #include "precond.hpp"
 #include "vec_kernels.hpp"
@@ -1254,20 +1256,14 @@ int celes_translation_tables(int lmax, double* a5_out, double* b5im_out) {
 // ---------------------------------------------------------------------------
 // observables (Appendix D and the SVWF definitions of Appendix A.1)
 // ---------------------------------------------------------------------------
-static void far_field_dir(const celes_handle* h, int kk, double th, double ph, cplx F[3]) {
-    const int L = h->L, nm = h->nmax;
+// F(theta, phi) from the sphere sums c_n = sum_i e^{-ik rhat.r_i} b^i_n
+// (Appendix D): f_{1lm} = (-i)^{l+1} e (i m pi e_theta - tau e_phi),
+// f_{2lm} = (-i)^l e (tau e_theta + i m pi e_phi), e = e^{i m phi}/sqrt(2l(l+1))
+static void far_field_from_sums(const celes_handle* h, double th, double ph, const cx<double>* c, cplx F[3]) {
+    const int L = h->L;
     const double st = std::sin(th), ct = std::cos(th), sp = std::sin(ph), cp = std::cos(ph);
-    const double rh[3] = {st * cp, st * sp, ct};
     const double et[3] = {ct * cp, ct * sp, -st};
     const double ep[3] = {-sp, cp, 0.0};
-    // coefficient sums over spheres: c_n = sum_i e^{-ik rhat.r_i} b_n^i
-    std::vector<cplx> c(nm, cplx(0, 0));
-    for (int64_t i = 0; i < h->N; ++i) {
-        const double* r = &h->pos[3 * i];
-        const cplx e = std::exp(cplx(0, -h->k * (rh[0] * r[0] + rh[1] * r[1] + rh[2] * r[2])));
-        const cplx* b = &h->b[((size_t)kk * h->N + i) * nm];
-        for (int n = 0; n < nm; ++n) c[n] += e * b[n];
-    }
     F[0] = F[1] = F[2] = 0;
     const cplx I(0, 1);
     for (int l = 1; l <= L; ++l) {
@@ -1277,13 +1273,50 @@ static void far_field_dir(const celes_handle* h, int kk, double th, double ph, c
             celes::pi_tau(l, std::abs(m), th, &pi, &tau);
             const cplx e = std::exp(cplx(0, m * ph)) / std::sqrt(2.0 * l * (l + 1));
             const int c1 = celes::lm_index(l, m), c2 = h->half + c1;
-            // f_{1lm} = (-i)^{l+1} e (i m pi e_theta - tau e_phi); f_{2lm} = (-i)^l e (tau e_theta + i m pi e_phi)
-            const cplx a1 = c[c1] * mi_l * cplx(0, -1) * e, a2 = c[c2] * mi_l * e;
+            const cplx a1 = cplx(c[c1].re, c[c1].im) * mi_l * cplx(0, -1) * e, a2 = cplx(c[c2].re, c[c2].im) * mi_l * e;
             const cplx ut = a1 * (I * (double)m * pi) + a2 * tau;
             const cplx up = -a1 * tau + a2 * (I * (double)m * pi);
             for (int q = 0; q < 3; ++q) F[q] += ut * et[q] + up * ep[q];
         }
     }
+}
+
+// Far field of right-hand side kk at nd directions (theta, phi): the sphere
+// sums on the device (ff_sums_launch) in chunks of directions, the angular
+// functions on the host.  F: [nd][3].
+static int far_field_batch(celes_handle* h, int kk, int64_t nd, const double* theta, const double* phi,
+                           std::vector<std::array<cplx, 3>>* F) {
+    const int64_t N = h->N;
+    const int nm = h->nmax;
+    F->assign(nd, {cplx(0, 0), cplx(0, 0), cplx(0, 0)});
+    if (nd == 0) return CELES_OK;
+    const int64_t chunk = std::min<int64_t>(nd, 1 << 17);
+    if (!h->d_ffb.ensure((size_t)N * nm * sizeof(cx<double>)) || !h->d_ffdir.ensure((size_t)chunk * 3 * sizeof(double)) ||
+        !h->d_ffc.ensure((size_t)chunk * nm * sizeof(cx<double>)))
+        return fail(h, CELES_E_OOM, "cannot allocate far-field buffers");
+    HIPCHK(h, hipMemcpy(h->d_ffb.p, &h->b[(size_t)kk * N * nm], (size_t)N * nm * sizeof(cx<double>),
+                        hipMemcpyHostToDevice));
+    std::vector<double> dirs((size_t)chunk * 3);
+    std::vector<cx<double>> c((size_t)chunk * nm);
+    for (int64_t d0 = 0; d0 < nd; d0 += chunk) {
+        const int64_t nc = std::min(chunk, nd - d0);
+        for (int64_t d = 0; d < nc; ++d) {
+            const double st = std::sin(theta[d0 + d]), ct = std::cos(theta[d0 + d]);
+            dirs[3 * d] = st * std::cos(phi[d0 + d]);
+            dirs[3 * d + 1] = st * std::sin(phi[d0 + d]);
+            dirs[3 * d + 2] = ct;
+        }
+        HIPCHK(h, hipMemcpy(h->d_ffdir.p, dirs.data(), (size_t)nc * 3 * sizeof(double), hipMemcpyHostToDevice));
+        if (celes::ff_sums_launch(h->d_px.as<double>(), h->d_py.as<double>(), h->d_pz.as<double>(),
+                                  h->d_ffb.as<cx<double>>(), N, nm, h->d_ffdir.as<double>(), nc, h->k,
+                                  h->d_ffc.as<cx<double>>(), nullptr) != 0)
+            return fail(h, CELES_E_DEVICE, "far-field launch failed");
+        HIPCHK(h, hipMemcpy(c.data(), h->d_ffc.p, (size_t)nc * nm * sizeof(cx<double>), hipMemcpyDeviceToHost));
+#pragma omp parallel for schedule(static)
+        for (int64_t d = 0; d < nc; ++d)
+            far_field_from_sums(h, theta[d0 + d], phi[d0 + d], &c[(size_t)d * nm], (*F)[d0 + d].data());
+    }
+    return CELES_OK;
 }
 
 static void svwf3(int L, double k, const double* r, int tau, int l, int m, cplx E[3]) {
@@ -1312,16 +1345,15 @@ static int celes_far_field_impl(celes_handle* h, int64_t ndir, const double* the
     if (!h) return CELES_E_ARG;
     if (!h->have_solution) return fail(h, CELES_E_STATE, "no solution");
     if (ndir < 0 || (ndir > 0 && (!theta || !phi || !F_out))) return fail(h, CELES_E_ARG, "bad direction arrays");
+    std::vector<std::array<cplx, 3>> F;
     for (int kk = 0; kk < h->K; ++kk) {
-#pragma omp parallel for schedule(dynamic, 4)
-        for (int64_t d = 0; d < ndir; ++d) {
-            cplx F[3];
-            far_field_dir(h, kk, theta[d], phi[d], F);
+        int rc = far_field_batch(h, kk, ndir, theta, phi, &F);
+        if (rc != CELES_OK) return rc;
+        for (int64_t d = 0; d < ndir; ++d)
             for (int q = 0; q < 3; ++q) {
-                F_out[(((size_t)kk * ndir + d) * 3 + q) * 2] = F[q].real();
-                F_out[(((size_t)kk * ndir + d) * 3 + q) * 2 + 1] = F[q].imag();
+                F_out[(((size_t)kk * ndir + d) * 3 + q) * 2] = F[d][q].real();
+                F_out[(((size_t)kk * ndir + d) * 3 + q) * 2 + 1] = F[d][q].imag();
             }
-        }
     }
     return CELES_OK;
 }
@@ -1343,18 +1375,22 @@ static int celes_s11_impl(celes_handle* const* hs, int nh, int64_t n_theta, cons
         if (h->k != hs[0]->k) return fail(h, CELES_E_ARG, "problems of different wavenumbers");
         runs += h->K;
     }
-#pragma omp parallel for schedule(dynamic, 1)
-    for (int64_t t = 0; t < n_theta; ++t) {
-        double acc = 0;
-        for (int j = 0; j < nh; ++j)
-            for (int kk = 0; kk < hs[j]->K; ++kk)
-                for (int q = 0; q < n_phi; ++q) {
-                    cplx F[3];
-                    far_field_dir(hs[j], kk, theta[t], 2.0 * M_PI * q / n_phi, F);
-                    acc += std::norm(F[0]) + std::norm(F[1]) + std::norm(F[2]);
-                }
-        out[t] = acc / ((double)runs * n_phi);
-    }
+    const int64_t nd = n_theta * n_phi;
+    std::vector<double> th(nd), ph(nd);
+    for (int64_t t = 0; t < n_theta; ++t)
+        for (int q = 0; q < n_phi; ++q) {
+            th[t * n_phi + q] = theta[t];
+            ph[t * n_phi + q] = 2.0 * M_PI * q / n_phi;
+        }
+    std::vector<double> acc(n_theta, 0.0);
+    std::vector<std::array<cplx, 3>> F;
+    for (int j = 0; j < nh; ++j)
+        for (int kk = 0; kk < hs[j]->K; ++kk) {
+            int rc = far_field_batch(hs[j], kk, nd, th.data(), ph.data(), &F);
+            if (rc != CELES_OK) return rc;
+            for (int64_t d = 0; d < nd; ++d) acc[d / n_phi] += std::norm(F[d][0]) + std::norm(F[d][1]) + std::norm(F[d][2]);
+        }
+    for (int64_t t = 0; t < n_theta; ++t) out[t] = acc[t] / ((double)runs * n_phi);
     return CELES_OK;
 }
 int celes_s11(celes_handle* const* hs, int nh, int64_t n_theta, const double* theta, int n_phi, double* out) {
@@ -1398,14 +1434,19 @@ static int celes_cross_sections_impl(celes_handle* h, double* C_ext, double* C_s
         if (C_ext) C_ext[kk] = -M_PI / (k * k) * ext;
         if (C_abs) C_abs[kk] = -M_PI / (k * k) * ab;
         if (C_sca) {
-            double sum = 0;
-#pragma omp parallel for reduction(+ : sum) collapse(2) schedule(dynamic, 8)
+            const int64_t nd = (int64_t)nt * nph;
+            std::vector<double> th(nd), ph(nd);
             for (int a = 0; a < nt; ++a)
                 for (int bq = 0; bq < nph; ++bq) {
-                    cplx F[3];
-                    far_field_dir(h, kk, std::acos(xg[a]), 2.0 * M_PI * bq / nph, F);
-                    sum += wg[a] * (2.0 * M_PI / nph) * (std::norm(F[0]) + std::norm(F[1]) + std::norm(F[2]));
+                    th[(int64_t)a * nph + bq] = std::acos(xg[a]);
+                    ph[(int64_t)a * nph + bq] = 2.0 * M_PI * bq / nph;
                 }
+            std::vector<std::array<cplx, 3>> F;
+            int rc = far_field_batch(h, kk, nd, th.data(), ph.data(), &F);
+            if (rc != CELES_OK) return rc;
+            double sum = 0;
+            for (int64_t d = 0; d < nd; ++d)
+                sum += wg[d / nph] * (2.0 * M_PI / nph) * (std::norm(F[d][0]) + std::norm(F[d][1]) + std::norm(F[d][2]));
             C_sca[kk] = sum / (k * k);
         }
     }
@@ -1459,12 +1500,28 @@ static int celes_power_flux_impl(celes_handle* h, int n_beta, int n_alpha, doubl
     const cplx gs = I / (2.0 * M_PI);
     for (int kk = 0; kk < h->K; ++kk) {
         double P0 = 0, Tn = 0, Rn = 0;
-#pragma omp parallel for reduction(+ : P0, Tn) collapse(2) schedule(dynamic, 4)
+        std::vector<std::array<cplx, 3>> FF, FB;
+        {
+            const int64_t nf = (int64_t)fb.size() * na, nbk = (int64_t)bb.size() * na;
+            std::vector<double> th(std::max(nf, nbk)), ph(std::max(nf, nbk));
+            for (int64_t d = 0; d < nf; ++d) {
+                th[d] = fb[d / na];
+                ph[d] = wa * (d % na);
+            }
+            int rc = far_field_batch(h, kk, nf, th.data(), ph.data(), &FF);
+            if (rc != CELES_OK) return rc;
+            for (int64_t d = 0; d < nbk; ++d) {
+                th[d] = bb[d / na];
+                ph[d] = wa * (d % na);
+            }
+            rc = far_field_batch(h, kk, nbk, th.data(), ph.data(), &FB);
+            if (rc != CELES_OK) return rc;
+        }
+#pragma omp parallel for reduction(+ : P0, Tn) collapse(2) schedule(static)
         for (int q = 0; q < (int)fb.size(); ++q)
             for (int a = 0; a < na; ++a) {
                 const double be = fb[q], al = wa * a;
-                cplx F[3];
-                far_field_dir(h, kk, be, al, F);
+                const cplx* F = FF[(size_t)q * na + a].data();
                 const double sa = std::sin(al), ca = std::cos(al), sbt = std::sin(be), cbt = std::cos(be);
                 const cplx Fa = F[0] * -sa + F[1] * ca;
                 const cplx Fb = F[0] * (cbt * ca) + F[1] * (cbt * sa) - F[2] * sbt;
@@ -1475,11 +1532,10 @@ static int celes_power_flux_impl(celes_handle* h, int n_beta, int n_alpha, doubl
                 P0 += fw[q] * wa * (std::norm(ga) + std::norm(gb));
                 Tn += fw[q] * wa * (std::norm(ga + gs * Fa) + std::norm(gb + gs * Fb));
             }
-#pragma omp parallel for reduction(+ : Rn) collapse(2) schedule(dynamic, 4)
+#pragma omp parallel for reduction(+ : Rn) collapse(2) schedule(static)
         for (int q = 0; q < (int)bb.size(); ++q)
             for (int a = 0; a < na; ++a) {
-                cplx F[3];
-                far_field_dir(h, kk, bb[q], wa * a, F);
+                const cplx* F = FB[(size_t)q * na + a].data();
                 Rn += bw[q] * wa * (std::norm(F[0]) + std::norm(F[1]) + std::norm(F[2])) / (4.0 * M_PI * M_PI);
             }
         double ab = 0;

@@ -76,6 +76,7 @@ struct celes_handle {
     DevBuf d_px, d_py, d_pz, d_tq64, d_tq32, d_lut64, d_lut32;
     DevBuf d_mrec;               // block-entry records of the matrix-core mat-vec (lmax <= 4)
     DevBuf d_xsd, d_part;        // mat-vec scratch
+    DevBuf d_ffb, d_ffdir, d_ffc;  // far-field sums: coefficients, directions, sums
     // incident field / solution (host, canonical layout [K][N][nmax])
     int K = 0;
     std::vector<cplx> a_in;

@@ -62,3 +62,20 @@ def test_cluster_s11_matches_oracle_and_run_split():
     with pytest.raises(P.CelesError) as e:
         P.s11([both, fresh], theta)
     assert e.value.name == "CELES_E_STATE"
+
+
+def test_far_field_sums_many_spheres_sampled_directions():
+    # the device sphere sums against the oracle's far field on the same
+    # coefficients (the library's own solution), 2,000 spheres, lmax 4
+    from oracle.observables import far_field
+    from tests.gpu_helpers import make_problem
+    w = workload("slab2000_l4")
+    print("[s11] slab2000_l4 far field, sampled directions", flush=True)
+    p = make_problem(w, tol=1e-4)
+    b, _ = p.solve()
+    rng = np.random.default_rng(5)
+    theta = np.concatenate([[0.0, math.pi, math.pi / 2], np.arccos(rng.uniform(-1, 1, 21))])
+    phi = rng.uniform(0, 2 * math.pi, theta.size)
+    F = p.far_field(theta, phi)[0]
+    ref = far_field(k_of(w), w.positions, b[0], w.lmax, theta, phi)
+    assert np.max(np.abs(F - ref)) <= 1e-11 * np.max(np.abs(ref))
