@@ -216,7 +216,10 @@ int celes_cross_sections(celes_handle* h, double* C_ext, double* C_sca, double* 
 
 /* Far-field amplitude F(theta, phi) of the scattered field, E_sca ->
  * e^{ikr}/(kr) F (Appendix D), at ndir directions; F_out [K][ndir][3][2]
- * cartesian complex.  Errors: CELES_E_STATE, CELES_E_ARG. */
+ * cartesian complex.  The sphere sums c_n = sum_i e^{-ik rhat.r_i} b^i_n run
+ * on the device (FP64), the angular functions on the host; the same path
+ * serves C_sca, S11 and the power flux.  Errors: CELES_E_STATE, CELES_E_ARG,
+ * CELES_E_OOM, CELES_E_DEVICE. */
 int celes_far_field(celes_handle* h, int64_t ndir, const double* theta, const double* phi,
                     double* F_out);
 
@@ -226,8 +229,9 @@ int celes_far_field(celes_handle* h, int64_t ndir, const double* theta, const do
  * or one problem with both plane waves) and over n_phi azimuths
  * phi_j = 2 pi j / n_phi, at n_theta polar angles theta.  out [n_theta]:
  * k^2 times the polarisation-averaged differential scattering cross section
- * (unnormalised; divide by the value at theta = 0 for S11(0) = 1).  Host
- * computation from the last solutions.  Errors: CELES_E_ARG (null, sizes,
+ * (unnormalised; divide by the value at theta = 0 for S11(0) = 1).  The
+ * sphere sums of the far field run on the device of each problem.  Errors:
+ * CELES_E_ARG (null, sizes,
  * problems of different wavenumbers), CELES_E_STATE (a problem without a
  * solution; its last error says so). */
 int celes_s11(celes_handle* const* hs, int nh, int64_t n_theta, const double* theta, int n_phi, double* out);

@@ -180,6 +180,15 @@ constexpr int PA_ROWS = 256, PA_COLS = 256;
 
 // T: vector precision; TM: matrix precision (FP64 inverse, or its FP32 copy
 // for complex64 vectors); accumulation in TM
+// streaming load of one complex matrix entry that bypasses cache retention
+// (the inverses are read once per apply)
+template <typename TM>
+__device__ __forceinline__ cx<TM> stream_load(const cx<TM>* p) {
+    typedef TM v2 __attribute__((ext_vector_type(2)));
+    const v2 v = __builtin_nontemporal_load(reinterpret_cast<const v2*>(p));
+    return {v.x, v.y};
+}
+
 template <typename T, typename TM>
 __global__ void __launch_bounds__(PA_ROWS) apply_tiles(const cx<TM>* __restrict__ inv,
                                                        const int64_t* __restrict__ perm,
@@ -214,7 +223,7 @@ __global__ void __launch_bounds__(PA_ROWS) apply_tiles(const cx<TM>* __restrict_
     for (; c + 8 <= ncol; c += 8) {
         cx<TM> a[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) a[u] = M[(int64_t)(c + u) * dim];
+        for (int u = 0; u < 8; ++u) a[u] = stream_load(M + (int64_t)(c + u) * dim);
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const cx<TM> x = xs[c + u];
@@ -223,7 +232,7 @@ __global__ void __launch_bounds__(PA_ROWS) apply_tiles(const cx<TM>* __restrict_
         }
     }
     for (; c < ncol; ++c) {
-        const cx<TM> a0 = M[(int64_t)c * dim], x0 = xs[c];
+        const cx<TM> a0 = stream_load(M + (int64_t)c * dim), x0 = xs[c];
         re[0] = fma(a0.re, x0.re, fma(-a0.im, x0.im, re[0]));
         im[0] = fma(a0.re, x0.im, fma(a0.im, x0.re, im[0]));
     }
