@@ -411,6 +411,21 @@ def validation_mode(a):
     t1 = time.perf_counter()
     s11 = P.s11(runs, np.radians(theta_deg), n_phi=64)
     log(f"S11 at {theta_deg.size} angles x 64 azimuths x 2 runs in {time.perf_counter() - t1:.2f} s")
+    # near-field map in the plane y = 0 (the paper's validation figure), points outside all spheres
+    g = np.linspace(-1.5 * w.extra["ball_radius"], 1.5 * w.extra["ball_radius"], 201)
+    pts = np.array([[x, 0.0, z] for z in g for x in g])
+    dmin = np.full(len(pts), np.inf)
+    for c0 in range(0, w.N, 500):
+        dmin = np.minimum(dmin, (np.linalg.norm(pts[:, None, :] - w.positions[None, c0:c0 + 500], axis=-1)
+                                 - w.radii[None, c0:c0 + 500]).min(axis=1))
+    pts = pts[dmin > 0]
+    t1 = time.perf_counter()
+    E = runs[0].near_field(pts, add_incident=True)[0]
+    t_nf = time.perf_counter() - t1
+    log(f"near field (scattered + incident Gaussian beam) at {len(pts)} points in {t_nf:.2f} s, "
+        f"max |E| {np.abs(E).max():.3f}")
+    res["TE"]["near_field_points"] = int(len(pts))
+    res["TE"]["near_field_seconds"] = t_nf
     print(json.dumps({
         "metric": "energy balance R + T + A - 1 of the validation target (TE and TM)",
         "value": max(abs(v["energy_balance"]) for v in res.values()), "unit": "relative",

@@ -237,8 +237,11 @@ int celes_far_field(celes_handle* h, int64_t ndir, const double* theta, const do
 int celes_s11(celes_handle* const* hs, int nh, int64_t n_theta, const double* theta, int n_phi, double* out);
 
 /* Electric near field at npt points outside all spheres (Section 2.1, eq.
- * Escat summed over spheres), plus the incident field when add_incident != 0;
- * E_out [K][npt][3][2] cartesian complex.  Errors: CELES_E_STATE, CELES_E_ARG. */
+ * Escat summed over spheres), plus the incident field when add_incident != 0
+ * (plane wave, or the Gaussian beam's angular spectrum of Appendix C on
+ * 256 x 256 nodes); E_out [K][npt][3][2] cartesian complex.  Evaluated on
+ * the device in FP64.  Errors: CELES_E_STATE, CELES_E_ARG, CELES_E_OOM,
+ * CELES_E_DEVICE. */
 int celes_near_field(celes_handle* h, int64_t npt, const double* pts, int add_incident,
                      double* E_out);
 

@@ -19,6 +19,7 @@
 #include "device_common.hpp"
 #include "host_math.hpp"
 #include "farfield.hpp"
+#include "nearfield.hpp"
 #include "internal.hpp"
 #include "precond.hpp"
 #include "vec_kernels.hpp"
@@ -1319,27 +1320,6 @@ static int far_field_batch(celes_handle* h, int kk, int64_t nd, const double* th
     return CELES_OK;
 }
 
-static void svwf3(int L, double k, const double* r, int tau, int l, int m, cplx E[3]) {
-    const double rr = std::sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
-    const double th = std::acos(std::max(-1.0, std::min(1.0, r[2] / rr))), ph = std::atan2(r[1], r[0]);
-    const double kr = k * rr;
-    cplx hv[16], dh[16];
-    celes::sph_hankel(l, kr, hv, dh);
-    const cplx z = hv[l], dkrz = hv[l] + kr * dh[l];
-    double pi, ta;
-    celes::pi_tau(l, std::abs(m), th, &pi, &ta);
-    std::vector<double> Pt((l + 1) * (l + 1));
-    celes::legendre_table(l, std::cos(th), std::sin(th), Pt.data());
-    const double P = Pt[l * (l + 1) + std::abs(m)];
-    const double st = std::sin(th), ct = std::cos(th), sp = std::sin(ph), cp = std::cos(ph);
-    const double er[3] = {st * cp, st * sp, ct}, et[3] = {ct * cp, ct * sp, -st}, ep[3] = {-sp, cp, 0.0};
-    const cplx e = std::exp(cplx(0, m * ph)) / std::sqrt(2.0 * l * (l + 1));
-    const cplx I(0, 1);
-    for (int q = 0; q < 3; ++q) {
-        if (tau == 1) E[q] = e * z * (I * (double)m * pi * et[q] - ta * ep[q]);
-        else E[q] = e * ((double)(l * (l + 1)) * z / kr * P * er[q] + dkrz / kr * (ta * et[q] + I * (double)m * pi * ep[q]));
-    }
-}
 
 static int celes_far_field_impl(celes_handle* h, int64_t ndir, const double* theta, const double* phi, double* F_out) {
     if (!h) return CELES_E_ARG;
@@ -1565,65 +1545,74 @@ static int celes_near_field_impl(celes_handle* h, int64_t npt, const double* pts
     if (!h) return CELES_E_ARG;
     if (!h->have_solution) return fail(h, CELES_E_STATE, "no solution");
     if (npt < 0 || (npt > 0 && (!pts || !E_out))) return fail(h, CELES_E_ARG, "bad point arrays");
+    if (npt == 0) return CELES_OK;
     const int64_t N = h->N;
-    const int nm = h->nmax, L = h->L;
+    const int nm = h->nmax;
     const double k = h->k;
+    celes::DevBuf d_pts, d_E, d_kv, d_amp;
+    if (!d_pts.ensure((size_t)npt * 3 * sizeof(double)) || !d_E.ensure((size_t)npt * 3 * sizeof(cx<double>)) ||
+        !h->d_ffb.ensure((size_t)N * nm * sizeof(cx<double>)))
+        return fail(h, CELES_E_OOM, "cannot allocate near-field buffers");
+    HIPCHK(h, hipMemcpy(d_pts.p, pts, (size_t)npt * 3 * sizeof(double), hipMemcpyHostToDevice));
+    // incident field as a plane-wave superposition: one wave, or the angular
+    // spectrum of the Gaussian beam (Appendix C, small-beta polarisation form)
+    std::vector<double> kv;
+    std::vector<cx<double>> amp;
     for (int kk = 0; kk < h->K; ++kk) {
-#pragma omp parallel for schedule(dynamic, 1)
-        for (int64_t q = 0; q < npt; ++q) {
-            cplx E[3] = {0, 0, 0};
-            for (int64_t i = 0; i < N; ++i) {
-                const double r[3] = {pts[3 * q] - h->pos[3 * i], pts[3 * q + 1] - h->pos[3 * i + 1],
-                                     pts[3 * q + 2] - h->pos[3 * i + 2]};
-                const cplx* b = &h->b[((size_t)kk * N + i) * nm];
-                for (int tau = 1; tau <= 2; ++tau)
-                    for (int l = 1; l <= L; ++l)
-                        for (int m = -l; m <= l; ++m) {
-                            const cplx c = b[(tau - 1) * h->half + celes::lm_index(l, m)];
-                            if (c == cplx(0, 0)) continue;
-                            cplx v[3];
-                            svwf3(L, k, r, tau, l, m, v);
-                            for (int a = 0; a < 3; ++a) E[a] += c * v[a];
-                        }
-            }
-            if (add_incident) {
-                const double* p = &pts[3 * q];
-                if (!h->gaussian) {
-                    const double be = h->pw_beta[kk], al = h->pw_alpha[kk];
-                    const double kv[3] = {k * std::sin(be) * std::cos(al), k * std::sin(be) * std::sin(al), k * std::cos(be)};
-                    const cplx ph = h->pw_E0[kk] * std::exp(cplx(0, kv[0] * p[0] + kv[1] * p[1] + kv[2] * p[2]));
-                    double e[3];
-                    if (h->pw_pol[kk] == 1) { e[0] = -std::sin(al); e[1] = std::cos(al); e[2] = 0; }
-                    else { e[0] = std::cos(be) * std::cos(al); e[1] = std::cos(be) * std::sin(al); e[2] = -std::sin(be); }
-                    for (int a = 0; a < 3; ++a) E[a] += ph * e[a];
-                } else {
-                    // angular-spectrum integral of Appendix C (small-beta polarisation form)
-                    const int nb = 256, na = 256;
-                    std::vector<double> xg(nb), wg(nb);
-                    celes::gauss_legendre(nb, xg.data(), wg.data());
-                    const double w = h->g_waist;
-                    const double r[3] = {p[0] - h->g_focus[0], p[1] - h->g_focus[1], p[2] - h->g_focus[2]};
-                    for (int bq = 0; bq < nb; ++bq) {
-                        const double be = 0.25 * M_PI * (xg[bq] + 1.0), wb = 0.25 * M_PI * wg[bq];
-                        const double sb = std::sin(be), cb = std::cos(be);
-                        const double gq = k * k * w * w / (4 * M_PI) * sb * cb * std::exp(-(w * k * sb) * (w * k * sb) / 4);
-                        for (int aq = 0; aq < na; ++aq) {
-                            const double al = 2 * M_PI * aq / na;
-                            const double ca = std::cos(al), sa = std::sin(al);
-                            const cplx ph = std::exp(cplx(0, k * (sb * ca * r[0] + sb * sa * r[1] + cb * r[2])));
-                            const double pa = std::cos(al - h->g_alpha), qa = std::sin(al - h->g_alpha);
-                            const double pol[3] = {pa * (-sa) + qa * cb * ca, pa * ca + qa * cb * sa, -qa * sb};
-                            const cplx f = h->g_E0 * (wb * 2 * M_PI / na * gq) * ph;
-                            for (int a = 0; a < 3; ++a) E[a] += f * pol[a];
-                        }
+        HIPCHK(h, hipMemcpy(h->d_ffb.p, &h->b[(size_t)kk * N * nm], (size_t)N * nm * sizeof(cx<double>),
+                            hipMemcpyHostToDevice));
+        if (celes::nf_scattered_launch(h->d_px.as<double>(), h->d_py.as<double>(), h->d_pz.as<double>(),
+                                       h->d_ffb.as<cx<double>>(), N, h->L, d_pts.as<double>(), npt, k,
+                                       d_E.as<cx<double>>(), nullptr) != 0)
+            return fail(h, CELES_E_DEVICE, "near-field launch failed");
+        if (add_incident) {
+            kv.clear();
+            amp.clear();
+            double origin[3] = {0, 0, 0};
+            if (!h->gaussian) {
+                const double be = h->pw_beta[kk], al = h->pw_alpha[kk];
+                kv = {k * std::sin(be) * std::cos(al), k * std::sin(be) * std::sin(al), k * std::cos(be)};
+                double e[3];
+                if (h->pw_pol[kk] == 1) { e[0] = -std::sin(al); e[1] = std::cos(al); e[2] = 0; }
+                else { e[0] = std::cos(be) * std::cos(al); e[1] = std::cos(be) * std::sin(al); e[2] = -std::sin(be); }
+                for (int c = 0; c < 3; ++c) {
+                    const cplx v = h->pw_E0[kk] * e[c];
+                    amp.push_back({v.real(), v.imag()});
+                }
+            } else {
+                const int nb = 256, na = 256;
+                std::vector<double> xg(nb), wg(nb);
+                celes::gauss_legendre(nb, xg.data(), wg.data());
+                const double w = h->g_waist;
+                for (int c = 0; c < 3; ++c) origin[c] = h->g_focus[c];
+                for (int bq = 0; bq < nb; ++bq) {
+                    const double be = 0.25 * M_PI * (xg[bq] + 1.0), wb = 0.25 * M_PI * wg[bq];
+                    const double sb = std::sin(be), cb = std::cos(be);
+                    const double gq = k * k * w * w / (4 * M_PI) * sb * cb * std::exp(-(w * k * sb) * (w * k * sb) / 4);
+                    for (int aq = 0; aq < na; ++aq) {
+                        const double al = 2 * M_PI * aq / na;
+                        const double ca = std::cos(al), sa = std::sin(al);
+                        const double pa = std::cos(al - h->g_alpha), qa = std::sin(al - h->g_alpha);
+                        const double pol[3] = {pa * (-sa) + qa * cb * ca, pa * ca + qa * cb * sa, -qa * sb};
+                        const cplx f = h->g_E0 * (wb * 2 * M_PI / na * gq);
+                        kv.push_back(k * sb * ca);
+                        kv.push_back(k * sb * sa);
+                        kv.push_back(k * cb);
+                        for (int c = 0; c < 3; ++c) amp.push_back({(f * pol[c]).real(), (f * pol[c]).imag()});
                     }
                 }
             }
-            for (int a = 0; a < 3; ++a) {
-                E_out[(((size_t)kk * npt + q) * 3 + a) * 2] = E[a].real();
-                E_out[(((size_t)kk * npt + q) * 3 + a) * 2 + 1] = E[a].imag();
-            }
+            const int64_t nn = (int64_t)kv.size() / 3;
+            if (!d_kv.ensure(kv.size() * sizeof(double)) || !d_amp.ensure(amp.size() * sizeof(cx<double>)))
+                return fail(h, CELES_E_OOM, "cannot allocate incident-field nodes");
+            HIPCHK(h, hipMemcpy(d_kv.p, kv.data(), kv.size() * sizeof(double), hipMemcpyHostToDevice));
+            HIPCHK(h, hipMemcpy(d_amp.p, amp.data(), amp.size() * sizeof(cx<double>), hipMemcpyHostToDevice));
+            if (celes::nf_planewaves_launch(d_kv.as<double>(), d_amp.as<cx<double>>(), nn, origin[0], origin[1],
+                                            origin[2], d_pts.as<double>(), npt, d_E.as<cx<double>>(), nullptr) != 0)
+                return fail(h, CELES_E_DEVICE, "incident near-field launch failed");
         }
+        HIPCHK(h, hipMemcpy(E_out + (size_t)kk * npt * 3 * 2, d_E.p, (size_t)npt * 3 * sizeof(cx<double>),
+                            hipMemcpyDeviceToHost));
     }
     return CELES_OK;
 }
