@@ -27,6 +27,7 @@ sys.path.insert(0, ROOT)
 METRIC = "pair-multipole updates/s of W·b; time-to-residual 1e-6, mixed vs FP64"
 PEAK_FP32_MFMA_TFLOPS = 157.3   # MI355X dense FP32 matrix
 PEAK_FP64_VALU_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
+PEAK_FP32_VALU_TFLOPS = 157.3  # MI355X FP32 vector peak (twice the FP64 rate)
 
 
 def flops_per_pair(L, hankel_lut=True):
@@ -780,6 +781,16 @@ def main():
     other_ms = ev0.elapsed_time(ev1) / reps
     other_fpp = flops_per_pair(L, other == "lut")
     q.close()
+    # the complex64 VALU kernel of the mixed path (one right-hand side), same problem
+    x32 = x.to(torch.complex64)
+    y32 = torch.empty_like(x32)
+    for _ in range(3):
+        p.apply_W(x32, y32, P.CELES_MIXED, stream=stream)
+    p.kernel_timing(True)
+    for _ in range(reps):
+        p.apply_W(x32, y32, P.CELES_MIXED, stream=stream)
+    torch.cuda.synchronize()
+    k32_ms, _ = p.kernel_timing(False)
     traffic = measured_traffic(N, L, a.hankel)
 
     # ---- timed solves ----
@@ -854,6 +865,10 @@ def main():
         "cpu_baseline": cpu,
         "kernel": "wx_fused_kernel<double, 4, 1, %d> (one launch = one W.b over all N(N-1) pairs)" % (0 if a.hankel == "lut" else 1),
         "kernel_ms": kernel_ms, "kernel_launches_timed": kernel_launches,
+        "fp32_kernel": {"kernel": f"wx_fused_kernel<float, {L}, 1, {0 if a.hankel == 'lut' else 1}> (complex64, "
+                                  "the inner solves of the mixed path)", "kernel_ms": k32_ms,
+                        "tflops": mv_flops / (k32_ms * 1e-3) / 1e12, "peak": PEAK_FP32_VALU_TFLOPS,
+                        "frac": mv_flops / (k32_ms * 1e-3) / 1e12 / PEAK_FP32_VALU_TFLOPS},
         "matvec_ms": mv_ms,
         "matvec_other_hankel": {"hankel": other, "matvec_ms": other_ms, "kernel_ms": other_kernel_ms,
                                 "updates_per_s": updates_per_mv / (other_ms * 1e-3),
