@@ -61,3 +61,18 @@ def test_apply_full_size_sampled_blocks():
         Mj, _, _ = master_matrix(w.positions[sph], w.radii[sph], w.n_sphere[sph], w.n0, w.wavelength, w.lmax)
         yj = solve_dense(Mj, x[sph].reshape(-1)).reshape(len(sph), -1)
         assert rel(y[sph], yj) <= 1e-11
+
+
+def test_single_cuboid_preconditioner_is_the_exact_inverse():
+    # one cuboid holds every sphere: P^{-1} = M^{-1}, so right-preconditioned
+    # GMRES converges in one iteration; also fewer blocks than set-up streams
+    w = workload("slab64_l3")
+    print("[precond] slab64_l3 single cuboid", flush=True)
+    p = make_problem(w, hankel=1, tol=1e-10)
+    p.build_preconditioner(1e6)
+    b, info = p.solve()
+    assert info["status"] == 0 and info["iterations"] == 1
+    M, W, t = master_matrix(w.positions, w.radii, w.n_sphere, w.n0, w.wavelength, w.lmax)
+    from tests.gpu_helpers import oracle_incident
+    bref = solve_dense(M, t * oracle_incident(w).reshape(-1)).reshape(w.N, -1)
+    assert rel(b[0], bref) <= 1e-10
