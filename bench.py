@@ -176,6 +176,15 @@ def batched_mode(a):
         q = P.Problem(pos, rad, 1.52, 1.0, 550.0, 3, hankel=P.CELES_HANKEL_LUT)
         q.set_plane_waves([0.0, 0.0], [0.0, 0.0], [1, 2])
         probs.append(q)
+    t_pre = 0.0
+    if a.batch_precond > 0:
+        t1 = time.perf_counter()
+        for q in probs:
+            q.build_preconditioner(a.batch_precond)
+        torch.cuda.synchronize()
+        t_pre = time.perf_counter() - t1
+        log(f"block-diagonal preconditioners ({a.batch_precond:g} nm cuboids) for {len(probs)} problems "
+            f"in {t_pre:.1f} s")
     updates = sum(q.N * (q.N - 1) * q.nmax ** 2 * q.num_rhs for q in probs)
     log(f"{len(probs)} problems set up, {updates:.3e} updates per batched mat-vec")
     bt = P.Batch(probs, precision=P.CELES_MIXED, tol=a.batch_tol, inner_tol=1e-3, restart=a.batch_restart,
@@ -236,7 +245,8 @@ def batched_mode(a):
         "autotune": tune, "solve_seconds": t_solve, "solve_status": summ["status"],
         "worst_rel_residual": summ["rel_residual"], "tol": a.batch_tol, "restart": a.batch_restart,
         "iterations_max": max(its), "iterations_mean": float(np.mean(its)), "refinements": summ["refinements"],
-        "geometry_seconds": t_gen}))
+        "preconditioner_edge_nm": a.batch_precond if a.batch_precond > 0 else None,
+        "preconditioner_setup_s": t_pre, "geometry_seconds": t_gen}))
 
 
 def mixed_mode(a):
@@ -678,6 +688,8 @@ def main():
     ap.add_argument("--batch-tol", type=float, default=1e-6)
     ap.add_argument("--batch-maxiter", type=int, default=600)
     ap.add_argument("--batch-restart", type=int, default=150)
+    ap.add_argument("--batch-precond", type=float, default=0.0,
+                    help="batched mode: block-diagonal preconditioner cuboid edge (nm) for every problem, 0 = none")
     ap.add_argument("--train-slabs", type=int, default=40)
     ap.add_argument("--train-n", type=int, default=2000)
     ap.add_argument("--eval-n", type=int, default=20000)

@@ -300,7 +300,11 @@ int celes_get_solution(const celes_handle* h, double* b_out);
  * Krylov state of every system stays on the device, and one Arnoldi step is
  * captured once in a hipGraph and replayed.  precision CELES_MIXED runs
  * complex64 inner GMRES with FP64 residuals and refinement; CELES_FP64 runs
- * FP64 throughout.  No preconditioner is applied in a batch.
+ * FP64 throughout.  A problem whose handle has a block-diagonal
+ * preconditioner (celes_build_preconditioner, Section 3.2.1) has it applied
+ * to each of its systems (right preconditioning, complex64 inverses in the
+ * inner solves of CELES_MIXED); the other problems run unpreconditioned.
+ * Rebuilding or removing a preconditioner between solves is allowed.
  * ------------------------------------------------------------------------- */
 typedef struct celes_batch celes_batch;
 

@@ -415,6 +415,22 @@ void bk_zero(cx<T>* x, int64_t n, hipStream_t s) {
     hipLaunchKernelGGL(flat_zero<T>, dim3(nblk(n)), dim3(BB), 0, s, x, n);
 }
 
+// b[slot sb] = a[slot sa] with slot = (*k if k else 0) + offset, slots of
+// `total` elements (reads the device-side Arnoldi step index at run time)
+template <typename T>
+__global__ void slot_copy(const cx<T>* __restrict__ a, const int* ka, int oa, cx<T>* __restrict__ b, const int* kb,
+                          int ob, int64_t total) {
+    const int64_t t = (int64_t)blockIdx.x * BB + threadIdx.x;
+    if (t >= total) return;
+    const int64_t sa = (int64_t)((ka ? *ka : 0) + oa) * total, sb = (int64_t)((kb ? *kb : 0) + ob) * total;
+    b[sb + t] = a[sa + t];
+}
+template <typename T>
+void bk_slot_copy(const cx<T>* a, const int* ka, int oa, cx<T>* b, const int* kb, int ob, int64_t total,
+                  hipStream_t s) {
+    hipLaunchKernelGGL(slot_copy<T>, dim3(nblk(total)), dim3(BB), 0, s, a, ka, oa, b, kb, ob, total);
+}
+
 #define CELES_BK_INST(T)                                                                                        \
     template void bk_prep<T>(const BatchGeom&, const cx<T>*, int64_t, const int*, int, cx<T>*, hipStream_t);    \
     template void bk_finish<T>(const BatchGeom&, const cx<T>*, const cx<T>*, int64_t, const int*, int, int,     \
@@ -427,7 +443,8 @@ void bk_zero(cx<T>* x, int64_t n, hipStream_t s) {
     template void bk_copy_scaled<T>(const SegInfo&, const cx<T>*, cx<T>*, const double*, hipStream_t);          \
     template void bk_sub<T>(const cx<T>*, const cx<T>*, cx<T>*, int64_t, hipStream_t);                          \
     template void bk_add<T>(const cx<T>*, const cx<T>*, cx<T>*, int64_t, hipStream_t);                          \
-    template void bk_zero<T>(cx<T>*, int64_t, hipStream_t);
+    template void bk_zero<T>(cx<T>*, int64_t, hipStream_t);                                                    \
+    template void bk_slot_copy<T>(const cx<T>*, const int*, int, cx<T>*, const int*, int, int64_t, hipStream_t);
 CELES_BK_INST(double)
 CELES_BK_INST(float)
 

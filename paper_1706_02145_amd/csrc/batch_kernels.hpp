@@ -83,5 +83,9 @@ void bk_add(const cx<T>* a, const cx<T>* b, cx<T>* c, int64_t n, hipStream_t s);
 void bk_acc32(const cx<float>* d, cx<double>* x, int64_t n, hipStream_t s);
 template <typename T>
 void bk_zero(cx<T>* x, int64_t n, hipStream_t s);
+// b[slot (*kb or 0) + ob] = a[slot (*ka or 0) + oa], slots of `total` elements
+template <typename T>
+void bk_slot_copy(const cx<T>* a, const int* ka, int oa, cx<T>* b, const int* kb, int ob, int64_t total,
+                  hipStream_t s);
 
 }  // namespace celes

@@ -1011,6 +1011,7 @@ int celes_apply_preconditioner(celes_handle* h, int precision, const void* x_dev
 static int celes_build_preconditioner_impl(celes_handle* h, double cuboid_edge) {
     if (!h) return CELES_E_ARG;
     h->pre.reset();
+    ++h->pre_gen;
     if (!(cuboid_edge > 0)) return CELES_OK;
     std::string msg;
     auto p = std::make_unique<celes::BlockPrecond>();
@@ -1655,6 +1656,9 @@ struct celes_batch {
     hipStream_t stream = nullptr;
     hipGraphExec_t graph32 = nullptr, graph64 = nullptr;
     void* graph_V = nullptr;          // basis the captured graphs point to
+    std::vector<uint64_t> graph_pre;  // preconditioner generations the captured graphs use
+    bool any_pre = false;             // some problem has a block-diagonal preconditioner
+    DevBuf d_pz, d_pw;                // preconditioned Arnoldi step: gathered and preconditioned vectors
     std::string err;
     ~celes_batch() {
         if (graph32) hipGraphExecDestroy(graph32);
@@ -1834,11 +1838,42 @@ int batch_matvec(celes_batch* b, const cx<T>* V, const int* kstep, int kin, cx<T
     return CELES_OK;
 }
 
+// out = P^{-1} in, system by system: a problem's block-diagonal
+// preconditioner on each of its right-hand sides, the identity for problems
+// without one (flat layout, in and out must not alias)
+template <typename T>
+int batch_precond_apply(celes_batch* b, const cx<T>* in, cx<T>* out, hipStream_t s) {
+    for (int p = 0; p < b->nprob; ++p) {
+        celes_handle* h = b->probs[p];
+        const int64_t n = h->N * h->nmax;
+        for (int r = 0; r < h->K; ++r) {
+            const int64_t off = b->elem_off[p] + (int64_t)r * n;
+            if (h->pre) {
+                if (h->pre->apply<T>(in + off, out + off, s) != 0)
+                    return bfail(b, CELES_E_DEVICE, "batch preconditioner apply failed");
+            } else {
+                celes::vec_scale<T>(in + off, 1.0, out + off, n, s);
+            }
+        }
+    }
+    return CELES_OK;
+}
+
 template <typename T>
 void record_arnoldi_step(celes_batch* b, cx<T>* V, double tol, hipStream_t s) {
     const int* k = b->d_k.as<int>();
     const int ld = b->m + 1;
-    batch_matvec<T>(b, V, k, 0, V, 1, 1, s);                                  // V_{k+1} = M V_k
+    if (b->any_pre) {
+        // right preconditioning: V_{k+1} = M P^{-1} V_k, through two flat
+        // buffers because the apply takes plain pointers and the step index
+        // lives on the device
+        celes::bk_slot_copy<T>(V, k, 0, b->d_pz.as<cx<T>>(), nullptr, 0, b->total, s);
+        batch_precond_apply<T>(b, b->d_pz.as<cx<T>>(), b->d_pw.as<cx<T>>(), s);
+        celes::bk_slot_copy<T>(b->d_pw.as<cx<T>>(), nullptr, 0, V, k, 1, b->total, s);
+        batch_matvec<T>(b, V, k, 1, V, 1, 1, s);                              // in place on slot k+1
+    } else {
+        batch_matvec<T>(b, V, k, 0, V, 1, 1, s);                              // V_{k+1} = M V_k
+    }
     celes::bk_dots<T>(b->si, V, b->total, V, k, 1, 1, 0, b->st.active, b->d_partial.as<cx<double>>(), ld,
                       b->st.h1, ld, s);                                       // h1 = V^H V_{k+1}
     celes::bk_gemv<T>(b->si, V, b->total, b->st.h1, ld, k, 1, nullptr, b->st.active, V, 1, -1.0, s);
@@ -1863,6 +1898,24 @@ int batch_gmres(celes_batch* b, const cx<T>* rhs, cx<T>* d, cx<T>* tmp, double t
     hipGraphExec_t& graph = sizeof(T) == 8 ? b->graph64 : b->graph32;
     const int nsys = b->nsys, m = b->m;
     *rc_out = CELES_OK;
+    // the captured step holds the preconditioners' device pointers: re-capture
+    // when any problem's preconditioner was rebuilt or removed
+    std::vector<uint64_t> gens(b->nprob);
+    bool any_pre = false;
+    for (int p = 0; p < b->nprob; ++p) {
+        gens[p] = b->probs[p]->pre ? b->probs[p]->pre_gen : 0;
+        any_pre = any_pre || b->probs[p]->pre;
+    }
+    if (gens != b->graph_pre) {
+        if (b->graph32) { hipGraphExecDestroy(b->graph32); b->graph32 = nullptr; }
+        if (b->graph64) { hipGraphExecDestroy(b->graph64); b->graph64 = nullptr; }
+        b->graph_pre = gens;
+    }
+    b->any_pre = any_pre;
+    if (any_pre && (!b->d_pz.ensure((size_t)b->total * sizeof(cx<T>)) || !b->d_pw.ensure((size_t)b->total * sizeof(cx<T>)))) {
+        *rc_out = bfail(b, CELES_E_OOM, "cannot allocate preconditioner buffers");
+        return 0;
+    }
     celes::bk_zero<T>(d, b->total, s);
     int cycle = 0;
     std::vector<int> act(nsys);
@@ -1908,9 +1961,18 @@ int batch_gmres(celes_batch* b, const cx<T>* rhs, cx<T>* d, cx<T>* tmp, double t
                 if (!any) break;
             }
         }
-        // d += V y over each system's used steps
+        // d += V y over each system's used steps (d += P^{-1} V y when preconditioned)
         celes::bk_backsolve(b->st, s);
-        celes::bk_gemv<T>(b->si, V, b->total, b->st.y, m + 1, nullptr, 0, b->st.used, nullptr, d, 0, 1.0, s);
+        if (any_pre) {
+            celes::bk_zero<T>(b->d_pz.as<cx<T>>(), b->total, s);
+            celes::bk_gemv<T>(b->si, V, b->total, b->st.y, m + 1, nullptr, 0, b->st.used, nullptr,
+                              b->d_pz.as<cx<T>>(), 0, 1.0, s);
+            if ((*rc_out = batch_precond_apply<T>(b, b->d_pz.as<cx<T>>(), b->d_pw.as<cx<T>>(), s)) != CELES_OK)
+                return cycle;
+            celes::bk_add<T>(d, b->d_pw.as<cx<T>>(), d, b->total, s);
+        } else {
+            celes::bk_gemv<T>(b->si, V, b->total, b->st.y, m + 1, nullptr, 0, b->st.used, nullptr, d, 0, 1.0, s);
+        }
         std::vector<double> est(nsys);
         std::vector<int> en(nsys);
         hipMemcpyAsync(est.data(), b->st.est, nsys * 8, hipMemcpyDeviceToHost, s);

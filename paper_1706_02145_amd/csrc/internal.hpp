@@ -93,6 +93,7 @@ struct celes_handle {
     DevBuf d_V, d_w, d_z, d_r, d_x, d_rhs, d_h, d_partial, d_V32, d_w32, d_z32, d_r32, d_x32;
     // preconditioner
     std::unique_ptr<celes::BlockPrecond> pre;
+    uint64_t pre_gen = 0;        // bumped whenever the preconditioner is rebuilt or removed
     int target_blocks = 0;       // mat-vec work split (0: default); set by the autotuner
     // celes_kernel_timing: HIP events around each coupling-kernel launch
     bool time_kernels = false;
