@@ -211,7 +211,8 @@ int celes_apply_M(celes_handle* h, int precision, int K, const void* x_dev, void
  * last solution: C_ext = -(pi/k^2) Re sum conj(a_in) b, C_abs =
  * -(pi/k^2) sum |b|^2 (Re(1/Q) + 1), C_sca = (1/k^2) oint |F|^2 dOmega by
  * quadrature of the far field (Appendix D).  Each output has K entries
- * (any may be NULL).  Errors: CELES_E_STATE (no solution). */
+ * (any may be NULL).  Errors: CELES_E_STATE (no solution), CELES_E_OOM,
+ * CELES_E_DEVICE (far-field sums on the device). */
 int celes_cross_sections(celes_handle* h, double* C_ext, double* C_sca, double* C_abs);
 
 /* Far-field amplitude F(theta, phi) of the scattered field, E_sca ->
@@ -258,8 +259,9 @@ int celes_mie_coefficients(int lmax, double kR, double m_re, double m_im, double
  * through the upper hemisphere), out[4k + 3] = absorbed fraction A; energy
  * conservation gives R + T + A = 1.  n_beta, n_alpha: polar nodes per
  * hemisphere and azimuthal nodes (<= 0: from the band limit lmax + k D,
- * D = 2 max |r_i|).  Errors: CELES_E_STATE (no solution, or the incident
- * field is not a Gaussian beam), CELES_E_ARG. */
+ * D = 2 max |r_i|); the far-field sphere sums run on the device.  Errors:
+ * CELES_E_STATE (no solution, or the incident field is not a Gaussian beam),
+ * CELES_E_ARG, CELES_E_OOM, CELES_E_DEVICE. */
 int celes_power_flux(celes_handle* h, int n_beta, int n_alpha, double* out);
 
 /* Kernel timing for measurement: enable = 1 starts recording HIP events on
