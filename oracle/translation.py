@@ -165,14 +165,18 @@ def coupling_matrix(pos, k, L, hankel=None):
 
 def apply_W_rows(pos, x, k, L, rows, hankel=None):
     """(W x)^i for the receiving spheres i in `rows`, computed on the fly
-    (W is never formed).  x: [N, nmax] complex.  Returns [len(rows), nmax]."""
+    (W is never formed).  x: [N, nmax] complex, or [K, N, nmax] for K
+    right-hand sides sharing the geometry.  Returns [len(rows), nmax], or
+    [K, len(rows), nmax]."""
     pos = np.asarray(pos, dtype=np.float64)
     x = np.asarray(x)
-    N = pos.shape[0]
-    out = np.zeros((len(rows), nmax_of(L)), dtype=np.complex128)
+    single = x.ndim == 2
+    xs = x[None] if single else x
+    K, N = xs.shape[0], pos.shape[0]
+    out = np.zeros((K, len(rows), nmax_of(L)), dtype=np.complex128)
     for a, i in enumerate(rows):
         src = np.array([j for j in range(N) if j != i], dtype=np.int64)
         blocks = translation_blocks(pos[i] - pos[src], k, L, hankel)
-        # y_n = sum_{i', n'} A_{n'n}(r_i - r_i') x_{i' n'}
-        out[a] = np.einsum("pab,pa->b", blocks, x[src])
-    return out
+        # y_n = sum_{i', n'} A_{n'n}(r_i - r_i') x_{i' n'}, for every right-hand side
+        out[:, a] = np.einsum("pab,kpa->kb", blocks, xs[:, src])
+    return out[0] if single else out

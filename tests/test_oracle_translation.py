@@ -220,3 +220,27 @@ def test_apply_W_rows_z_pair_only_equal_m():
             if m != m_src:
                 assert y[a] == 0
         assert np.abs(y).max() > 0
+
+
+@pytest.mark.parametrize("mode", ["direct", "lut"])
+def test_apply_W_rows_several_rhs_equals_dense(mode):
+    # K right-hand sides at once ([K, N, nmax] in, [K, rows, nmax] out) against
+    # the dense W applied to each column: a mixed-up right-hand-side axis or a
+    # contraction over it would fail
+    from oracle.lut import lut_for
+    from oracle.translation import apply_W_rows
+    k = 2 * math.pi / 550
+    L = 2
+    rng = np.random.default_rng(7)
+    pos = rng.uniform(-800, 800, (5, 3))
+    radii = np.full(5, 90.0)
+    nm = 2 * L * (L + 2)
+    hk = lut_for(pos, radii, k, L, 1.0) if mode == "lut" else None
+    W = coupling_matrix(pos, k, L, hankel=hk)
+    x = rng.standard_normal((3, 5, nm)) + 1j * rng.standard_normal((3, 5, nm))
+    rows = [3, 1]
+    got = apply_W_rows(pos, x, k, L, rows, hankel=hk)
+    assert got.shape == (3, 2, nm)
+    for kk in range(3):
+        ref = (W @ x[kk].reshape(-1)).reshape(5, nm)
+        assert np.abs(got[kk] - ref[rows]).max() <= 1e-14 * np.abs(ref).max()
