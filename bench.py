@@ -1,18 +1,20 @@
 """Benchmark of the hot path on one MI355X.
 
-Workload: the 2,000-sphere slab (lognormal radii, mean 150 nm, sigma 10%,
-n = 1.52, volume fraction 0.3, thickness 2 um), lmax = 4, Gaussian beam
-(waist 2 um) at 550 nm, Hankel lookup table at 1 nm, complex128.
+Workload (default): the 20,000-sphere slab (lognormal radii, mean 150 nm,
+sigma 10%, n = 1.52, volume fraction 0.3, thickness 3 um), lmax = 4,
+Gaussian beam (waist 2 um) at 550 nm, Hankel lookup table at 1 nm.
 
-A step is one FP64 solve of the master equation by block-diagonal
-preconditioned GMRES to relative residual 1e-8 from a zero initial guess
-(preconditioner set-up is done once before timing and reported separately).
-`value` is the number of pair-multipole updates of W b executed in the timed
-steps, N(N-1) nmax^2 per mat-vec, divided by the wall time of the steps.
+A step is one FP64 coupling mat-vec W.b over all N(N-1) sphere pairs
+(complex128).  `value` is the number of pair-multipole updates executed in
+the timed steps, N(N-1) nmax^2 per mat-vec, divided by their wall time.
 
-Also reported: the mat-vec kernel alone (HIP events on the launch stream, used
-for the roofline), time to residual 1e-6 in FP64 and in mixed precision, and
-the CPU oracle timed on a bounded sample of receiver rows.
+Also reported: the coupling kernel alone (HIP events on its launch stream,
+used for the roofline), the complex64 mat-vec of the mixed path, time to
+relative residual 1e-6 of block-diagonal preconditioned GMRES in FP64 and in
+mixed precision on the same seed and the same cuboid partition (one
+preconditioner, set up once and reported separately), the 2,000-sphere slab's
+preconditioned FP64 solve to 1e-8, and the CPU oracle timed on a bounded
+sample of receiver rows.
 """
 import argparse
 import json
@@ -30,11 +32,13 @@ PEAK_FP64_VALU_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4
 PEAK_FP32_VALU_TFLOPS = 157.3  # MI355X FP32 vector peak (twice the FP64 rate)
 
 
-def flops_per_pair(L, hankel_lut=True):
-    """Floating-point operations per sphere pair of the coupling kernel as it
-    runs (all passes M0 = 0..L, one right-hand side).  Counting: real add,
-    mul or FMA = 1 or 2 flops as (add/mul 1, fma 2); complex multiply 6,
-    complex multiply-accumulate 8; sqrt, divide and sincos 1 each."""
+def _pass_counts(L):
+    """Per-pair terms of the coupling kernel's arithmetic, in flops (real
+    add, mul = 1, FMA = 2; complex multiply 6, complex multiply-accumulate 8;
+    sqrt, divide and sincos 1 each): the set-up shared by every receiving
+    |m| (geometry, Hankel orders, Legendre columns and azimuthal phases for
+    mu = 0..2L) and the work of each receiving |m| = M0 (source rotations,
+    A and B sums, A +- iB, accumulations)."""
     def iabs(a):
         return -a if a < 0 else a
 
@@ -50,18 +54,22 @@ def flops_per_pair(L, hankel_lut=True):
         return max(0, (l + lp - 1 - p) // 2 + 1) if p <= l + lp - 1 else 0
 
     P = 2 * L
-    total = 0
-    for M0 in range(L + 1):
+
+    def setup(lut, mumax):
         f = 19                                             # geometry
         # Hankel: table index + Horner for h_0, h_1 (24) + 1/(kd) (1), or
         # sincos + 1/(kd) + h_0, h_1 (6); then the recurrence, 5 per order
-        f += (4 + 24 + 1 + 5 * (P - 1)) if hankel_lut else (4 + 6 + 5 * (P - 1))
-        mumax = min(2 * L, L + M0)
+        f += (4 + 24 + 1 + 5 * (P - 1)) if lut else (4 + 6 + 5 * (P - 1))
         for mu in range(mumax + 1):
             if mu > 0:
                 f += 2 + 6                                 # P_mu^mu and e^{i mu phi}
             ncol = P - mu + 1
             f += 3 * max(0, ncol - 2) + (2 if ncol >= 2 else 0) + 2 * ncol   # Legendre column + H
+        return f
+
+    def work(M0):
+        f = 0
+        for mu in range(min(2 * L, L + M0) + 1):
             for sgn in (1, -1):
                 if sgn < 0 and (mu == 0 or M0 == 0):
                     continue
@@ -75,8 +83,32 @@ def flops_per_pair(L, hankel_lut=True):
                         f += 4 * (pa(l, lp, mu) + pb(l, lp, mu))   # A and B sums
                         f += 4                               # P = A + iB, Q = A - iB
                         f += 8 * (4 if two else 2)           # accumulations
-        total += f
-    return total
+        return f
+
+    return setup, work
+
+
+def flops_per_pair(L, hankel_lut=True):
+    """Algorithmic flops per sphere pair of one W.b (one right-hand side):
+    the pair set-up once (mu = 0..2L) plus the work of every receiving |m|.
+    This is what the roofline fraction is computed from."""
+    setup, work = _pass_counts(L)
+    return setup(hankel_lut, 2 * L) + sum(work(M0) for M0 in range(L + 1))
+
+
+def flops_per_pair_executed(L, groups, hankel_lut=True):
+    """Flops per pair as the kernel executes them: the pair set-up is
+    repeated in each pass group (a group covers the mu its passes need)."""
+    setup, work = _pass_counts(L)
+    f = sum(work(M0) for M0 in range(L + 1))
+    for g in groups:
+        f += setup(hankel_lut, max(min(2 * L, L + M0) for M0 in g))
+    return f
+
+
+# pass groups of the coupling kernel per cut-off (receiving |m| per group)
+KERNEL_GROUPS = {1: [(0, 1)], 2: [(0, 2), (1,)], 3: [(1,), (0, 3), (2,)], 4: [(2, 4), (0, 3), (1,)],
+                 5: [(3, 4), (2, 5), (1,), (0,)], 6: [(3, 5), (2, 6), (0, 4), (1,)]}
 
 
 def kernel_source_digest():
@@ -97,11 +129,11 @@ def kernel_source_digest():
     return h.hexdigest()
 
 
-def measured_traffic(N, L, hankel):
+def measured_traffic(name, N, L, hankel):
     """HBM bytes per mat-vec launch from the committed rocprofv3 FETCH_SIZE /
     WRITE_SIZE summary, or None if it was taken on other kernel sources or
     another workload."""
-    f = os.path.join(ROOT, "profiles", "wx_fused_slab2000_l4_hbm_traffic.json")
+    f = os.path.join(ROOT, "profiles", f"wx_fused_{name}_hbm_traffic.json")
     if not os.path.exists(f):
         return None
     with open(f) as fh:
@@ -115,22 +147,22 @@ def measured_traffic(N, L, hankel):
 def _oracle_rows_worker(args):
     """CPU baseline worker: the oracle's W.b rows r0, r0 + stride, ... for
     `seconds` of wall time; returns (rows done, seconds)."""
-    name, r0, stride, seconds = args
+    pos, radii, k, L, dr, r0, stride, seconds = args
     from threadpoolctl import threadpool_limits
-    from celes_inputs import workload, random_coefficients
+    from celes_inputs import random_coefficients
     from oracle.lut import lut_for
     from oracle.translation import apply_W_rows
-    w = workload(name)
-    k = 2 * math.pi * w.n0 / w.wavelength
-    lut = lut_for(w.positions, w.radii, k, w.lmax, w.lut_dr)
-    xs = random_coefficients(1, 1, w.N, w.nmax)[0]
+    N = pos.shape[0]
+    nm = 2 * L * (L + 2)
+    lut = lut_for(pos, radii, k, L, dr)
+    xs = random_coefficients(1, 1, N, nm)[0]
     rows, t = 0, 0.0
     with threadpool_limits(limits=1):
-        apply_W_rows(w.positions, xs, k, w.lmax, [r0], hankel=lut)    # warm the coefficient caches
+        apply_W_rows(pos, xs, k, L, [r0], hankel=lut)    # warm the coefficient caches
         t1 = time.perf_counter()
         r = r0
-        while t < seconds and r < w.N:
-            apply_W_rows(w.positions, xs, k, w.lmax, [r], hankel=lut)
+        while t < seconds and r < N:
+            apply_W_rows(pos, xs, k, L, [r], hankel=lut)
             rows += 1
             r += stride
             t = time.perf_counter() - t1
@@ -667,14 +699,16 @@ def warmstart_mode(a):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--matvec-reps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--matvec-reps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--workload", default="slab2000_l4")
-    ap.add_argument("--cuboid-edge", type=float, default=1500.0)
+    ap.add_argument("--workload", default="slab20000_l4")
+    ap.add_argument("--small-workload", default="slab2000_l4", help="second workload ('' to skip)")
+    ap.add_argument("--cuboid-edge", type=float, default=1500.0,
+                    help="preconditioner cuboid edge in nm (-1: budgeted automatic edge, 0: none)")
     ap.add_argument("--hankel", choices=["lut", "direct"], default="lut")
     ap.add_argument("--profile", action="store_true", help="mat-vec launches only (for rocprofv3)")
     ap.add_argument("--mode", choices=["solve", "batched", "warmstart", "mixed", "paper", "scaling", "validation",
@@ -724,46 +758,51 @@ def main():
     from celes_inputs import workload, random_coefficients
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    t_start = time.perf_counter()
+
+    def log(msg):
+        print(f"[bench] {msg} ({time.perf_counter() - t_start:.1f} s)", file=sys.stderr, flush=True)
+
     w = workload(a.workload)
+    log(f"{w.name} generated (N={w.N})")
     il = w.illumination
     N, L, nm = w.N, w.lmax, w.nmax
     updates_per_mv = N * (N - 1) * nm * nm
     hk = P.CELES_HANKEL_LUT if a.hankel == "lut" else P.CELES_HANKEL_DIRECT
+    hmode = 0 if a.hankel == "lut" else 1
 
-    def problem(**kw):
-        p = P.Problem(w.positions, w.radii, w.n_sphere, w.n0, w.wavelength, L, hankel=hk, lut_dr=w.lut_dr, **kw)
-        if il["kind"] == "gaussian":
-            p.set_gaussian_beam(il["waist"], il["focus"], il["alpha_G"], il["E0"])
+    def problem(wl, **kw):
+        p = P.Problem(wl.positions, wl.radii, wl.n_sphere, wl.n0, wl.wavelength, wl.lmax, hankel=hk,
+                      lut_dr=wl.lut_dr, **kw)
+        ill = wl.illumination
+        if ill["kind"] == "gaussian":
+            p.set_gaussian_beam(ill["waist"], ill["focus"], ill["alpha_G"], ill["E0"])
         else:
-            p.set_plane_waves([il["beta"]], [il["alpha"]], [il["pol"]])
+            p.set_plane_waves([ill["beta"]], [ill["alpha"]], [ill["pol"]])
         return p
 
     t0 = time.perf_counter()
-    p = problem(tol=w.tol, restart=100, maxiter=3000)
+    p = problem(w, restart=100, maxiter=3000)
     t_setup = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    if a.cuboid_edge > 0 and not a.profile:
-        p.build_preconditioner(a.cuboid_edge)
-    torch.cuda.synchronize()
-    t_pre = time.perf_counter() - t0
-
-    # ---- mat-vec kernel alone (roofline), HIP events on the launch stream ----
     stream = torch.cuda.current_stream()
     x = torch.from_numpy(random_coefficients(1, 1, N, nm)[0]).to("cuda")
     y = torch.empty_like(x)
-    for _ in range(3):
+    steps = a.steps if not a.profile else min(a.steps, 5)
+
+    # ---- timed steps: one FP64 W.b each; the coupling kernel timed by HIP
+    # events on its launch stream over the same launches ----
+    for _ in range(a.warmup):
         p.apply_W(x, y, P.CELES_FP64, stream=stream)
     torch.cuda.synchronize()
-    reps = a.matvec_reps if not a.profile else 5
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    p.kernel_timing(True)       # HIP events around the coupling kernel itself, on the launch stream
-    ev0.record(stream)
-    for _ in range(reps):
-        p.apply_W(x, y, P.CELES_FP64, stream=stream)
-    ev1.record(stream)
+    p.kernel_timing(True)
     torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        p.apply_W(x, y, P.CELES_FP64, stream=stream)
+    torch.cuda.synchronize()
+    t_steps = time.perf_counter() - t0
     kernel_ms, kernel_launches = p.kernel_timing(False)
-    mv_ms = ev0.elapsed_time(ev1) / reps
+    log(f"{steps} FP64 mat-vecs: {1e3 * t_steps / steps:.2f} ms each, kernel {kernel_ms:.2f} ms")
     if a.profile:
         # calibration copy of known size for the HBM byte counters
         src = torch.empty(64 * 2 ** 20, dtype=torch.float32, device="cuda").fill_(1.0)
@@ -771,129 +810,155 @@ def main():
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
-        print(json.dumps({"matvec_ms": mv_ms, "N": N, "lmax": L, "copy_bytes_each_way": src.numel() * 4}))
+        print(json.dumps({"workload": w.name, "matvec_ms": 1e3 * t_steps / steps, "kernel_ms": kernel_ms, "N": N,
+                          "lmax": L, "copy_bytes_each_way": src.numel() * 4}))
         return
+    value = steps * updates_per_mv / t_steps
     fpp = flops_per_pair(L, a.hankel == "lut")
+    fpp_exec = flops_per_pair_executed(L, KERNEL_GROUPS[L], a.hankel == "lut")
     mv_flops = fpp * N * (N - 1)
     achieved = mv_flops / (kernel_ms * 1e-3) / 1e12
+
+    # the complex64 VALU kernel of the mixed path (one right-hand side), same problem
+    x32 = x.to(torch.complex64)
+    y32 = torch.empty_like(x32)
+    p.apply_W(x32, y32, P.CELES_MIXED, stream=stream)
+    torch.cuda.synchronize()
+    p.kernel_timing(True)
+    for _ in range(a.matvec_reps):
+        p.apply_W(x32, y32, P.CELES_MIXED, stream=stream)
+    torch.cuda.synchronize()
+    k32_ms, _ = p.kernel_timing(False)
+    log(f"complex64 kernel {k32_ms:.2f} ms")
 
     # ablation: the other Hankel evaluation mode on the same geometry
     other = "direct" if a.hankel == "lut" else "lut"
     q = P.Problem(w.positions, w.radii, w.n_sphere, w.n0, w.wavelength, L, lut_dr=w.lut_dr,
                   hankel=P.CELES_HANKEL_DIRECT if other == "direct" else P.CELES_HANKEL_LUT)
-    for _ in range(3):
-        q.apply_W(x, y, P.CELES_FP64, stream=stream)
+    q.apply_W(x, y, P.CELES_FP64, stream=stream)
+    torch.cuda.synchronize()
     q.kernel_timing(True)
-    ev0.record(stream)
-    for _ in range(reps):
+    for _ in range(a.matvec_reps):
         q.apply_W(x, y, P.CELES_FP64, stream=stream)
-    ev1.record(stream)
     torch.cuda.synchronize()
     other_kernel_ms, _ = q.kernel_timing(False)
-    other_ms = ev0.elapsed_time(ev1) / reps
     other_fpp = flops_per_pair(L, other == "lut")
     q.close()
-    # the complex64 VALU kernel of the mixed path (one right-hand side), same problem
-    x32 = x.to(torch.complex64)
-    y32 = torch.empty_like(x32)
-    for _ in range(3):
-        p.apply_W(x32, y32, P.CELES_MIXED, stream=stream)
-    p.kernel_timing(True)
-    for _ in range(reps):
-        p.apply_W(x32, y32, P.CELES_MIXED, stream=stream)
-    torch.cuda.synchronize()
-    k32_ms, _ = p.kernel_timing(False)
-    traffic = measured_traffic(N, L, a.hankel)
+    log(f"{other} Hankel kernel {other_kernel_ms:.2f} ms")
+    traffic = measured_traffic(w.name, N, L, a.hankel)
 
-    # ---- timed solves ----
-    for _ in range(a.warmup):
-        p.solve()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    infos = []
-    for _ in range(a.steps):
-        b, info = p.solve()
-        infos.append(info)
-    torch.cuda.synchronize()
-    t_steps = time.perf_counter() - t0
-    matvecs = sum(i["matvecs"] for i in infos)
-    value = matvecs * updates_per_mv / t_steps
-
-    # ---- time to residual 1e-6: FP64 vs mixed (same preconditioner edge) ----
+    # ---- time to residual 1e-6: FP64 vs mixed, one preconditioner for both ----
     ttr = {}
+    t_pre, pre_info = 0.0, None
     if not a.no_mixed:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if a.cuboid_edge != 0:
+            pre_info = p.build_preconditioner(a.cuboid_edge)
+        torch.cuda.synchronize()
+        t_pre = time.perf_counter() - t0
+        log(f"preconditioner {pre_info} in {t_pre:.1f} s")
         for name, prec in (("fp64", P.CELES_FP64), ("mixed", P.CELES_MIXED)):
-            q = problem(tol=1e-6, precision=prec, restart=100, maxiter=3000, inner_tol=1e-3)
-            if a.cuboid_edge > 0:
-                q.build_preconditioner(a.cuboid_edge)
-            q.solve()   # warm
+            p.set_solve_options(tol=1e-6, precision=prec, restart=100, maxiter=3000, inner_tol=1e-3)
             torch.cuda.synchronize()
             t1 = time.perf_counter()
-            _, inf = q.solve()
+            _, inf = p.solve()
             torch.cuda.synchronize()
             ttr[name] = {"seconds": time.perf_counter() - t1, "iterations": inf["iterations"],
+                         "refinements": inf["refinements"], "matvec_seconds": inf["matvec_seconds"],
                          "rel_residual": inf["rel_residual"]}
-            q.close()
+            log(f"{name} to 1e-6: {ttr[name]['seconds']:.1f} s, {inf['iterations']} iterations")
+        ttr["speedup_mixed_vs_fp64"] = ttr["fp64"]["seconds"] / ttr["mixed"]["seconds"]
+        ttr["solve_seconds_exclude"] = "preconditioner set-up (preconditioner_setup_s)"
+
+    # ---- the 2,000-sphere slab: preconditioned FP64 GMRES to 1e-8 ----
+    small = None
+    if a.small_workload:
+        ws = workload(a.small_workload)
+        ps = problem(ws, tol=ws.tol, restart=100, maxiter=3000)
+        t0 = time.perf_counter()
+        ps.build_preconditioner(1500.0)
+        torch.cuda.synchronize()
+        tps = time.perf_counter() - t0
+        ps.solve()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, inf = ps.solve()
+        torch.cuda.synchronize()
+        ts = time.perf_counter() - t0
+        xs_ = torch.from_numpy(random_coefficients(1, 1, ws.N, ws.nmax)[0]).to("cuda")
+        ys_ = torch.empty_like(xs_)
+        ps.apply_W(xs_, ys_, P.CELES_FP64, stream=stream)
+        ps.kernel_timing(True)
+        for _ in range(a.matvec_reps):
+            ps.apply_W(xs_, ys_, P.CELES_FP64, stream=stream)
+        torch.cuda.synchronize()
+        kms, _ = ps.kernel_timing(False)
+        upd = ws.N * (ws.N - 1) * ws.nmax ** 2
+        small = {"workload": f"{ws.name}: N={ws.N}, lmax {ws.lmax}, Gaussian beam, cuboid edge 1500 nm",
+                 "solve_to_1e-8_seconds": ts, "iterations": inf["iterations"], "matvecs": inf["matvecs"],
+                 "rel_residual": inf["rel_residual"], "preconditioner_setup_s": tps,
+                 "solve_updates_per_s": inf["matvecs"] * upd / ts, "kernel_ms": kms,
+                 "kernel_frac": flops_per_pair(ws.lmax, a.hankel == "lut") * ws.N * (ws.N - 1) / (kms * 1e-3) / 1e12 /
+                                PEAK_FP64_VALU_TFLOPS}
+        ps.close()
+        log(f"{ws.name} solve to 1e-8: {ts:.2f} s")
 
     # ---- CPU oracle on a bounded sample of receiver rows ----
     cpu = None
     if not a.no_cpu_baseline:
-        from oracle.translation import apply_W_rows
-        from oracle.lut import lut_for
         k = 2 * math.pi * w.n0 / w.wavelength
-        lut = lut_for(w.positions, w.radii, k, L, w.lut_dr)
-        xs = random_coefficients(1, 1, N, nm)[0]
         # one process per host core (the box's share: 16), each timing the
         # plain oracle on its own receiver rows for the same wall window
         ncore = min(16, os.cpu_count() or 1)
         from concurrent.futures import ProcessPoolExecutor
         with ProcessPoolExecutor(ncore) as ex:
-            parts = list(ex.map(_oracle_rows_worker, [(w.name, r, ncore, a.cpu_seconds) for r in range(ncore)]))
+            parts = list(ex.map(_oracle_rows_worker, [(w.positions, w.radii, k, L, w.lut_dr, r, ncore, a.cpu_seconds)
+                                                      for r in range(ncore)]))
         rows = sum(r for r, _ in parts)
         t_cpu = max(t for _, t in parts)
         cpu = {"value": rows * (N - 1) * nm * nm / t_cpu, "unit": "updates/s", "cores": ncore, "kind": "oracle",
                "sample": f"{rows} of {N} receiver rows of one W.b (same geometry, LUT mode) in {t_cpu:.1f} s "
                          f"on {ncore} processes (numpy BLAS 1 thread each)"}
+        log(f"CPU oracle: {rows} rows in {t_cpu:.1f} s")
 
     out = {
         "metric": METRIC,
         "value": value,
         "unit": "updates/s",
         "n_gpus": 1,
-        "steps": a.steps,
+        "steps": steps,
         "warmup": a.warmup,
-        "ms_per_step": 1e3 * t_steps / a.steps,
+        "ms_per_step": 1e3 * t_steps / steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"{w.name}: N={N} RSA slab, radii lognormal(150 nm, 10%), n=1.52, vf 0.3, "
-                               f"t=2 um, lmax={L}, Gaussian beam w=2 um, lambda=550 nm, LUT dr=1 nm, "
-                               f"block-diagonal preconditioned GMRES to 1e-8 (complex128)",
-                   "N": N, "lmax": L, "hankel": a.hankel, "cuboid_edge_nm": a.cuboid_edge},
+                               f"t={w.box[2] / 1000:g} um, lmax={L}, Gaussian beam w=2 um, lambda=550 nm, "
+                               f"LUT dr=1 nm; step = one FP64 W.b (complex128)",
+                   "N": N, "lmax": L, "hankel": a.hankel},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VALU_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_VALU_TFLOPS, "traffic": traffic},
         "cpu_baseline": cpu,
-        "kernel": "wx_fused_kernel<double, 4, 1, %d> (one launch = one W.b over all N(N-1) pairs)" % (0 if a.hankel == "lut" else 1),
+        "kernel": f"wx_fused_kernel<double, {L}, 1, {hmode}> (one launch = one W.b over all N(N-1) pairs)",
         "kernel_ms": kernel_ms, "kernel_launches_timed": kernel_launches,
-        "fp32_kernel": {"kernel": f"wx_fused_kernel<float, {L}, 1, {0 if a.hankel == 'lut' else 1}> (complex64, "
-                                  "the inner solves of the mixed path)", "kernel_ms": k32_ms,
+        "flops_per_pair": fpp, "flops_per_pair_executed": fpp_exec,
+        "kernel_tflops_executed": fpp_exec * N * (N - 1) / (kernel_ms * 1e-3) / 1e12,
+        "fp32_kernel": {"kernel": f"wx_fused_kernel<float, {L}, 1, {hmode}> (complex64, the inner solves of the "
+                                  "mixed path)", "kernel_ms": k32_ms,
                         "tflops": mv_flops / (k32_ms * 1e-3) / 1e12, "peak": PEAK_FP32_VALU_TFLOPS,
-                        "frac": mv_flops / (k32_ms * 1e-3) / 1e12 / PEAK_FP32_VALU_TFLOPS},
-        "matvec_ms": mv_ms,
-        "matvec_other_hankel": {"hankel": other, "matvec_ms": other_ms, "kernel_ms": other_kernel_ms,
-                                "updates_per_s": updates_per_mv / (other_ms * 1e-3),
-                                "tflops": other_fpp * N * (N - 1) / (other_kernel_ms * 1e-3) / 1e12,
+                        "frac": mv_flops / (k32_ms * 1e-3) / 1e12 / PEAK_FP32_VALU_TFLOPS,
+                        "updates_per_s": updates_per_mv / (k32_ms * 1e-3)},
+        "kernel_other_hankel": {"hankel": other, "kernel_ms": other_kernel_ms,
                                 "frac": other_fpp * N * (N - 1) / (other_kernel_ms * 1e-3) / 1e12 /
                                         PEAK_FP64_VALU_TFLOPS},
-        "matvec_updates_per_s": updates_per_mv / (mv_ms * 1e-3),
-        "flops_per_pair": fpp,
-        "solve": {"iterations": infos[-1]["iterations"], "matvecs_per_solve": infos[-1]["matvecs"],
-                  "rel_residual": infos[-1]["rel_residual"], "matvec_share": sum(i["matvec_seconds"] for i in infos) / t_steps},
         "setup_s": t_setup,
-        "preconditioner_setup_s": t_pre,
+        "preconditioner": None if pre_info is None else {"edge_nm": pre_info[0], "cuboids": pre_info[1],
+                                                         "bytes": pre_info[2], "setup_s": t_pre},
         "time_to_residual_1e-6": ttr,
+        "small_workload": small,
     }
     print(json.dumps(out))
 

@@ -73,11 +73,22 @@ typedef struct celes_options {
     int restart;            /* GMRES restart length                                           */
     int maxiter;            /* total inner iterations allowed                                 */
     int max_refinements;    /* mixed precision: outer refinement steps allowed                */
-    double cuboid_edge;     /* preconditioner cuboid edge; <= 0 disables the preconditioner   */
+    double cuboid_edge;     /* preconditioner built by celes_create: 0 none, > 0 cubes of this
+                             * edge, CELES_CUBOID_AUTO the budgeted edge (as
+                             * celes_build_preconditioner)                                    */
     int device;             /* HIP device ordinal                                             */
     int verbose;            /* 0 silent, 1 per-restart residuals on stderr                    */
     int solver;             /* CELES_SOLVER_GMRES or CELES_SOLVER_BICGSTAB (single problems;
                              * batches run GMRES only)                                        */
+    double target_Nj;       /* automatic cuboid edge (celes_build_preconditioner with
+                             * CELES_CUBOID_AUTO): largest edge whose mean number of spheres
+                             * per occupied cuboid is <= target_Nj (<= 0: 100)               */
+    double mem_cap_bytes;   /* device bytes the preconditioner may hold: FP64 inverses,
+                             * their complex64 copy and the apply's partial sums,
+                             * sum_j (N_j nmax)^2 (16 + 8) + ceil(max_j N_j nmax / 256) N nmax 16
+                             * (<= 0: 90% of the device memory free at build time)            */
+    int autotune;           /* 1: the first mat-vec of each precision on a handle times the
+                             * candidate source-chunk splits and keeps the fastest             */
 } celes_options;
 
 typedef struct celes_solve_info {
@@ -94,7 +105,8 @@ typedef struct celes_solve_info {
 
 /* Fill *opt with defaults: FP64, LUT, lut_dr = 1, tol = 1e-8, inner_tol = 1e-4,
  * restart = 100, maxiter = 2000, max_refinements = 30, cuboid_edge = 0, device 0,
- * solver GMRES. */
+ * solver GMRES, target_Nj = 100, mem_cap_bytes = 0 (free device memory),
+ * autotune = 0. */
 void celes_default_options(celes_options* opt);
 
 /* Library version (CELES_VERSION). */
@@ -115,6 +127,15 @@ int celes_create(celes_handle** h, int64_t N, const double* pos, const double* r
 
 /* Release everything the handle owns.  NULL is allowed. */
 void celes_destroy(celes_handle* h);
+
+/* Replace the solver settings of a handle for its next solves: precision,
+ * tol, inner_tol, restart, maxiter, max_refinements, verbose, solver,
+ * target_Nj, mem_cap_bytes and autotune are taken from *opt; the fields fixed
+ * at creation (hankel, lut_dr, device, cuboid_edge) are kept, and so are the
+ * geometry, incident field and preconditioner (so FP64 and mixed solves can
+ * share one preconditioner).  Errors: CELES_E_ARG (null, unknown solver or
+ * precision). */
+int celes_set_solve_options(celes_handle* h, const celes_options* opt);
 
 /* Text of the last error on this handle (or of the last failed create when
  * h is NULL).  Valid until the next call on the handle. */
@@ -143,12 +164,38 @@ int celes_get_incident(const celes_handle* h, double* a_out);
 /* Number of right-hand sides of the current incident field (0 if none). */
 int celes_num_rhs(const celes_handle* h);
 
+/* cuboid_edge value of celes_build_preconditioner that picks the edge itself */
+#define CELES_CUBOID_AUTO (-1.0)
+
 /* Block-diagonal preconditioner (Section 3.2.1): partition the spheres into
  * cubes of edge `cuboid_edge` anchored at the minimum corner of the centres'
  * bounding box, assemble M_j = I - T W_jj per cube and factorise it (LU with
- * partial pivoting, FP64).  cuboid_edge <= 0 removes the preconditioner.
+ * partial pivoting, FP64).  The LU storage grows as sum_j N_j^2 (Section
+ * 3.2.1), so the edge is budgeted: with cuboid_edge = CELES_CUBOID_AUTO (any
+ * negative value) the edge is chosen as by celes_plan_preconditioner from
+ * the handle's target_Nj and mem_cap_bytes; with cuboid_edge > 0 that edge is
+ * used as given.  Either way the build fails with CELES_E_OOM, before any
+ * device allocation or launch, when the preconditioner's bytes (see
+ * celes_options.mem_cap_bytes) exceed the cap.  cuboid_edge = 0 removes the
+ * preconditioner.  A failed build leaves the handle without a preconditioner.
  * Errors: CELES_E_OOM, CELES_E_DEVICE. */
 int celes_build_preconditioner(celes_handle* h, double cuboid_edge);
+
+/* Cuboid edge of the block-diagonal preconditioner (Section 3.2.1) for N
+ * centres pos [N][3] at cut-off lmax, planned on the host without a device:
+ * among the edges e_q = 1.02 D 0.92^q (D the largest extent of the centres'
+ * bounding box, q = 0, 1, ... while e_q >= D / 4096) the largest one whose
+ * mean number of spheres per occupied cuboid is <= target_Nj (<= 0: 100) and
+ * whose preconditioner bytes (formula at celes_options.mem_cap_bytes) are <=
+ * mem_cap_bytes (<= 0: no cap).  Outputs (any may be NULL): the edge, the
+ * number of cuboids, the bytes, the largest cuboid's sphere count.
+ * Errors: CELES_E_ARG, CELES_E_OOM (no candidate edge fits the cap). */
+int celes_plan_preconditioner(int64_t N, const double* pos, int lmax, double target_Nj, double mem_cap_bytes,
+                              double* edge_out, int64_t* nblocks_out, double* bytes_out, int64_t* max_Nj_out);
+
+/* Cuboid edge, number of cuboids and device bytes of the handle's current
+ * preconditioner (all zero when there is none).  Any output may be NULL. */
+int celes_preconditioner_info(const celes_handle* h, double* edge, int64_t* nblocks, double* bytes);
 
 /* y = P^{-1} x for the block-diagonal preconditioner of the last
  * celes_build_preconditioner (Section 3.2.1): every cuboid's block of x is

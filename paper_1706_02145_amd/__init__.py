@@ -9,10 +9,10 @@ import ctypes as C
 
 import numpy as np
 
-from ._capi import (CELES_FP64, CELES_HANKEL_DIRECT, CELES_HANKEL_LUT, CELES_MIXED, CELES_SOLVER_BICGSTAB,
+from ._capi import (CELES_CUBOID_AUTO, CELES_FP64, CELES_HANKEL_DIRECT, CELES_HANKEL_LUT, CELES_MIXED, CELES_SOLVER_BICGSTAB,
                     CELES_SOLVER_GMRES, ERRORS, Options, SolveInfo, lib, LIB_PATH)
 
-__all__ = ["Problem", "Batch", "Network", "CelesError", "default_options", "mie_coefficients", "translation_tables", "version",
+__all__ = ["Problem", "Batch", "Network", "CelesError", "default_options", "plan_preconditioner", "mie_coefficients", "translation_tables", "version",
            "s11",
            "CELES_FP64", "CELES_MIXED", "CELES_HANKEL_LUT", "CELES_HANKEL_DIRECT", "CELES_SOLVER_GMRES",
            "CELES_SOLVER_BICGSTAB", "LIB_PATH"]
@@ -47,6 +47,17 @@ def default_options(**kw):
             raise KeyError(k)
         setattr(o, k, v)
     return o
+
+
+def plan_preconditioner(positions, lmax, target_Nj=100.0, mem_cap_bytes=0.0):
+    """Budgeted cuboid edge on the host (celes_plan_preconditioner): returns
+    (edge, cuboids, bytes, largest cuboid's sphere count)."""
+    pos = np.ascontiguousarray(positions, dtype=np.float64)
+    e, nb, by, mx = C.c_double(), C.c_int64(), C.c_double(), C.c_int64()
+    _check(lib().celes_plan_preconditioner(pos.shape[0], _dptr(pos), int(lmax), float(target_Nj),
+                                           float(mem_cap_bytes), C.byref(e), C.byref(nb), C.byref(by),
+                                           C.byref(mx)))
+    return e.value, nb.value, by.value, mx.value
 
 
 def mie_coefficients(lmax, kR, m):
@@ -107,6 +118,20 @@ class Problem:
         self.k = 2 * np.pi * n0 / wavelength
         self.options = opt
 
+    def set_solve_options(self, **kw):
+        """Change solver settings (precision, tol, inner_tol, restart, maxiter,
+        max_refinements, verbose, solver, target_Nj, mem_cap_bytes, autotune)
+        for the next solves, keeping geometry, incident field and
+        preconditioner (celes_set_solve_options)."""
+        opt = Options()
+        C.memmove(C.byref(opt), C.byref(self.options), C.sizeof(Options))
+        for k, v in kw.items():
+            if not hasattr(opt, k):
+                raise KeyError(k)
+            setattr(opt, k, v)
+        _check(lib().celes_set_solve_options(self._h, C.byref(opt)), self._h)
+        self.options = opt
+
     def close(self):
         if getattr(self, "_h", None):
             lib().celes_destroy(self._h)
@@ -154,8 +179,17 @@ class Problem:
         return out
 
     # ---- solve ------------------------------------------------------------
-    def build_preconditioner(self, cuboid_edge):
+    def build_preconditioner(self, cuboid_edge=CELES_CUBOID_AUTO):
+        """Block-diagonal preconditioner with cubes of edge cuboid_edge (0:
+        remove it; CELES_CUBOID_AUTO: the budgeted edge from the options'
+        target_Nj and mem_cap_bytes).  Returns (edge, cuboids, bytes)."""
         _check(lib().celes_build_preconditioner(self._h, float(cuboid_edge)), self._h)
+        return self.preconditioner_info()
+
+    def preconditioner_info(self):
+        e, nb, by = C.c_double(), C.c_int64(), C.c_double()
+        _check(lib().celes_preconditioner_info(self._h, C.byref(e), C.byref(nb), C.byref(by)), self._h)
+        return e.value, nb.value, by.value
 
     def solve(self, x0=None, check=True):
         K = self.num_rhs

@@ -15,13 +15,15 @@ ERRORS = {
 CELES_FP64, CELES_MIXED = 0, 1
 CELES_HANKEL_LUT, CELES_HANKEL_DIRECT = 0, 1
 CELES_SOLVER_GMRES, CELES_SOLVER_BICGSTAB = 0, 1
+CELES_CUBOID_AUTO = -1.0
 
 
 class Options(C.Structure):
     _fields_ = [("precision", C.c_int), ("hankel", C.c_int), ("lut_dr", C.c_double), ("tol", C.c_double),
                 ("inner_tol", C.c_double), ("restart", C.c_int), ("maxiter", C.c_int),
                 ("max_refinements", C.c_int), ("cuboid_edge", C.c_double), ("device", C.c_int),
-                ("verbose", C.c_int), ("solver", C.c_int)]
+                ("verbose", C.c_int), ("solver", C.c_int), ("target_Nj", C.c_double),
+                ("mem_cap_bytes", C.c_double), ("autotune", C.c_int)]
 
 
 class SolveInfo(C.Structure):
@@ -42,11 +44,15 @@ SIGNATURES = {
     "celes_create": (C.c_int, [C.POINTER(_h), C.c_int64, _dp, _dp, _dp, C.c_double, C.c_double, C.c_int,
                                C.POINTER(Options)]),
     "celes_destroy": (None, [_h]),
+    "celes_set_solve_options": (C.c_int, [_h, C.POINTER(Options)]),
     "celes_set_plane_waves": (C.c_int, [_h, C.c_int, _dp, _dp, _ip, _dp]),
     "celes_set_gaussian_beam": (C.c_int, [_h, C.c_double, _dp, C.c_double, C.c_double, C.c_double, C.c_int]),
     "celes_get_incident": (C.c_int, [_h, _dp]),
     "celes_num_rhs": (C.c_int, [_h]),
     "celes_build_preconditioner": (C.c_int, [_h, C.c_double]),
+    "celes_plan_preconditioner": (C.c_int, [C.c_int64, _dp, C.c_int, C.c_double, C.c_double, _dp,
+                                            C.POINTER(C.c_int64), _dp, C.POINTER(C.c_int64)]),
+    "celes_preconditioner_info": (C.c_int, [_h, _dp, C.POINTER(C.c_int64), _dp]),
     "celes_solve": (C.c_int, [_h, _dp, _dp, C.POINTER(SolveInfo)]),
     "celes_apply_preconditioner": (C.c_int, [_h, C.c_int, _vp, _vp, _vp]),
     "celes_s11": (C.c_int, [C.c_void_p, C.c_int, C.c_int64, _dp, C.c_int, _dp]),

@@ -301,16 +301,65 @@ static int mfma_width(const celes_handle* h, int K) {
 // y = W x (epilogue 0) or x - T W x (epilogue 1) for K right-hand sides,
 // x, y: [K][N][nmax] device buffers of precision T
 template <typename T>
+static int matvec_valu(celes_handle* h, const cx<T>* x, cx<T>* y, int K, int epilogue, hipStream_t s, int target,
+                       bool timed);
+
+// source-chunk split of the VALU mat-vec: the environment (tests), the
+// handle's forced value, the autotuned value, or 4096 blocks.  With
+// opt.autotune the first call of each precision times the candidate splits
+// on the caller's x and y (each candidate writes y completely) and keeps the
+// fastest; not while the stream is being captured.
+template <typename T>
+static int matvec_target(celes_handle* h, const cx<T>* x, cx<T>* y, int K, int epilogue, hipStream_t s) {
+    const char* env = std::getenv("CELES_WX_TARGET_BLOCKS");
+    if (env) return std::max(1, std::atoi(env));
+    if (h->target_blocks > 0) return h->target_blocks;
+    int& tuned = h->tuned_blocks[sizeof(T) == 8 ? 0 : 1];
+    if (tuned > 0 || !h->opt.autotune) return tuned > 0 ? tuned : 4096;
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone) return 4096;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return 4096;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        hipEventDestroy(e0);
+        return 4096;
+    }
+    float best = 1e30f;
+    int best_t = 4096;
+    for (int t : {1024, 2048, 4096, 8192, 16384}) {
+        if (matvec_valu<T>(h, x, y, K, epilogue, s, t, false) != CELES_OK) continue;   // warm
+        hipEventRecord(e0, s);
+        const int rc = matvec_valu<T>(h, x, y, K, epilogue, s, t, false);
+        hipEventRecord(e1, s);
+        float ms = 0;
+        if (rc != CELES_OK || hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+            continue;
+        if (ms < best) {
+            best = ms;
+            best_t = t;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    tuned = best_t;
+    return tuned;
+}
+
+template <typename T>
 int matvec(celes_handle* h, const cx<T>* x, cx<T>* y, int K, int epilogue, hipStream_t s) {
     if constexpr (sizeof(T) == 4) {
         const int width = mfma_width(h, K);
         if (width > 0) return matvec_mfma(h, x, y, K, width, epilogue, s);
     }
+    return matvec_valu<T>(h, x, y, K, epilogue, s, matvec_target<T>(h, x, y, K, epilogue, s), true);
+}
+
+template <typename T>
+static int matvec_valu(celes_handle* h, const cx<T>* x, cx<T>* y, int K, int epilogue, hipStream_t s, int target,
+                       bool timed) {
     const int64_t N = h->N;
     const int kb = pick_kb<T>(h->L, K);
     int64_t nbx = (N + celes::WX_BLOCK_SIZE - 1) / celes::WX_BLOCK_SIZE * celes::wx_num_groups(h->L) * (K / kb);
-    const char* env = std::getenv("CELES_WX_TARGET_BLOCKS");
-    const int target = env ? std::max(1, std::atoi(env)) : (h->target_blocks > 0 ? h->target_blocks : 4096);
     int64_t nchunk = (target + nbx - 1) / nbx;
     nchunk = std::max<int64_t>(1, std::min<int64_t>(nchunk, (N + celes::WX_TILE_SIZE - 1) / celes::WX_TILE_SIZE));
     int64_t chunk_len = (N + nchunk - 1) / nchunk;
@@ -340,7 +389,7 @@ int matvec(celes_handle* h, const cx<T>* x, cx<T>* y, int K, int epilogue, hipSt
     a.sys0 = 0;
     const cx<T>* tq = (sizeof(T) == 8) ? (const cx<T>*)h->d_tq64.p : (const cx<T>*)h->d_tq32.p;
     int rc = celes::wx_launch<T>(a, h->L, h->opt.hankel == CELES_HANKEL_DIRECT ? 1 : 0, nchunk_eff, x, tq, y,
-                                 epilogue, s, timing_events(h));
+                                 epilogue, s, timed ? timing_events(h) : nullptr);
     if (rc == -1) return fail(h, CELES_E_UNSUPPORTED, "lmax not compiled");
     if (rc != 0) return fail(h, CELES_E_DEVICE, "mat-vec launch failed");
     return CELES_OK;
@@ -373,24 +422,31 @@ int gmres_device(celes_handle* h, const cx<T>* rhs, cx<T>* x, double tol, int ma
     auto apply_pre = [&](const cx<T>* in, cx<T>* outv) -> int {
         return h->pre->apply<T>(in, outv, s);
     };
+    // mat-vec time from events around each mat-vec, read once the stream has
+    // reached the next host synchronisation (norm2), never by waiting on them
+    hipEvent_t e0, e1;
+    hipEventCreate(&e0);
+    hipEventCreate(&e1);
+    bool pending = false;
+    auto collect = [&]() {
+        if (!pending) return;
+        float ms = 0;
+        if (hipEventElapsedTime(&ms, e0, e1) == hipSuccess) out->matvec_seconds += ms * 1e-3;
+        pending = false;
+    };
     auto norm2 = [&](const cx<T>* v) -> double {
         celes::vec_dots<T>(v, 0, 1, v, n, dpart, dh, s);
         cx<double> r;
         hipMemcpyAsync(&r, dh, sizeof(r), hipMemcpyDeviceToHost, s);
         hipStreamSynchronize(s);
+        collect();
         return std::sqrt(std::max(0.0, r.re));
     };
-    hipEvent_t e0, e1;
-    hipEventCreate(&e0);
-    hipEventCreate(&e1);
     auto timed_matvec = [&](const cx<T>* in, cx<T>* outv) -> int {
         hipEventRecord(e0, s);
         int rc = matvec<T>(h, in, outv, 1, 1, s);
         hipEventRecord(e1, s);
-        hipEventSynchronize(e1);
-        float ms = 0;
-        hipEventElapsedTime(&ms, e0, e1);
-        out->matvec_seconds += ms * 1e-3;
+        pending = true;
         out->matvecs++;
         return rc;
     };
@@ -482,6 +538,10 @@ int gmres_device(celes_handle* h, const cx<T>* rhs, cx<T>* x, double tol, int ma
         if (h->opt.verbose)
             std::fprintf(stderr, "gmres (%s) cycle %d: %d iterations, estimate %.3e\n",
                          sizeof(T) == 8 ? "fp64" : "fp32", out->restarts, out->iterations, out->est);
+    }
+    if (pending) {
+        hipEventSynchronize(e1);
+        collect();
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
@@ -689,11 +749,17 @@ void celes_default_options(celes_options* opt) {
     opt->cuboid_edge = 0.0;
     opt->device = 0;
     opt->verbose = 0;
+    opt->solver = CELES_SOLVER_GMRES;
+    opt->target_Nj = 100.0;
+    opt->mem_cap_bytes = 0.0;
+    opt->autotune = 0;
 }
 
 int celes_version(void) { return CELES_VERSION; }
 
 const char* celes_last_error(const celes_handle* h) { return h ? h->err.c_str() : g_create_error.c_str(); }
+
+static int celes_build_preconditioner_impl(celes_handle* h, double cuboid_edge);
 
 static int celes_create_impl(celes_handle** out, int64_t N, const double* pos, const double* radius, const double* n_sphere,
                  double n0, double wavelength, int lmax, const celes_options* opt) {
@@ -792,6 +858,10 @@ static int celes_create_impl(celes_handle** out, int64_t N, const double* pos, c
             hipMemcpy(hp->d_mrec.p, rec.data(), rec.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
             return fail(nullptr, CELES_E_DEVICE, "cannot upload the block-entry records");
     }
+    if (hp->opt.cuboid_edge != 0 && (rc = celes_build_preconditioner_impl(hp, hp->opt.cuboid_edge)) != CELES_OK) {
+        g_create_error = hp->err;
+        return rc;
+    }
     *out = h.release();
     return CELES_OK;
 }
@@ -802,6 +872,26 @@ int celes_create(celes_handle** out, int64_t N, const double* pos, const double*
 
 
 void celes_destroy(celes_handle* h) { delete h; }
+
+int celes_set_solve_options(celes_handle* h, const celes_options* opt) {
+    if (!h || !opt) return CELES_E_ARG;
+    if (opt->solver != CELES_SOLVER_GMRES && opt->solver != CELES_SOLVER_BICGSTAB)
+        return fail(h, CELES_E_ARG, "unknown solver");
+    if (opt->precision != CELES_FP64 && opt->precision != CELES_MIXED) return fail(h, CELES_E_ARG, "unknown precision");
+    celes_options& o = h->opt;
+    o.precision = opt->precision;
+    o.tol = opt->tol;
+    o.inner_tol = opt->inner_tol;
+    o.restart = std::max(1, opt->restart);
+    o.maxiter = opt->maxiter;
+    o.max_refinements = opt->max_refinements;
+    o.verbose = opt->verbose;
+    o.solver = opt->solver;
+    o.target_Nj = opt->target_Nj;
+    o.mem_cap_bytes = opt->mem_cap_bytes;
+    o.autotune = opt->autotune;
+    return CELES_OK;
+}
 
 int celes_dims(const celes_handle* h, int64_t* N, int* lmax, int* nmax) {
     if (!h) return CELES_E_ARG;
@@ -1012,8 +1102,28 @@ static int celes_build_preconditioner_impl(celes_handle* h, double cuboid_edge) 
     if (!h) return CELES_E_ARG;
     h->pre.reset();
     ++h->pre_gen;
-    if (!(cuboid_edge > 0)) return CELES_OK;
+    if (cuboid_edge == 0) return CELES_OK;
+    if (!std::isfinite(cuboid_edge)) return fail(h, CELES_E_ARG, "cuboid edge must be finite");
+    // memory budget (Section 3.2.1: the LU storage grows as sum_j N_j^2),
+    // checked before anything is allocated or launched
+    double cap = h->opt.mem_cap_bytes;
+    if (!(cap > 0)) {
+        size_t free_b = 0, total_b = 0;
+        if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return fail(h, CELES_E_DEVICE, "hipMemGetInfo failed");
+        cap = 0.9 * (double)free_b;
+    }
     std::string msg;
+    std::vector<int64_t> perm, offsets;
+    if (cuboid_edge < 0) {
+        if (celes::plan_cuboid_edge(h->N, h->pos.data(), h->L, h->opt.target_Nj, cap, &cuboid_edge, &offsets, &msg) != 0)
+            return fail(h, CELES_E_OOM, msg);
+    } else {
+        celes::partition_cuboids(h->N, h->pos.data(), cuboid_edge, &perm, &offsets);
+    }
+    const double need = celes::BlockPrecond::precond_bytes(h->N, h->L, offsets);
+    if (need > cap)
+        return fail(h, CELES_E_OOM, "preconditioner needs " + std::to_string((long long)(need / (1 << 20))) +
+                                        " MiB, above the cap of " + std::to_string((long long)(cap / (1 << 20))) + " MiB");
     auto p = std::make_unique<celes::BlockPrecond>();
     int rc = p->build(h->N, h->L, h->pos.data(), h->k, h->tq.data(), cuboid_edge,
                       h->opt.hankel == CELES_HANKEL_DIRECT ? 1 : 0, h->d_lut64.p, h->lut_lo, h->lut_dr,
@@ -1024,6 +1134,35 @@ static int celes_build_preconditioner_impl(celes_handle* h, double cuboid_edge) 
 }
 int celes_build_preconditioner(celes_handle* h, double cuboid_edge) {
     return celes_guard([&] { return celes_build_preconditioner_impl(h, cuboid_edge); });
+}
+
+int celes_plan_preconditioner(int64_t N, const double* pos, int lmax, double target_Nj, double mem_cap_bytes,
+                              double* edge_out, int64_t* nblocks_out, double* bytes_out, int64_t* max_Nj_out) {
+    return celes_guard([&] {
+        if (N < 1 || !pos || lmax < 1) return fail(nullptr, CELES_E_ARG, "N < 1, lmax < 1 or null positions");
+        for (int64_t i = 0; i < 3 * N; ++i)
+            if (!std::isfinite(pos[i])) return fail(nullptr, CELES_E_NONFINITE, "non-finite position");
+        double edge = 0;
+        std::vector<int64_t> offsets;
+        std::string msg;
+        if (celes::plan_cuboid_edge(N, pos, lmax, target_Nj, mem_cap_bytes, &edge, &offsets, &msg) != 0)
+            return fail(nullptr, CELES_E_OOM, msg);
+        int64_t mx = 0;
+        for (size_t j = 0; j + 1 < offsets.size(); ++j) mx = std::max<int64_t>(mx, offsets[j + 1] - offsets[j]);
+        if (edge_out) *edge_out = edge;
+        if (nblocks_out) *nblocks_out = (int64_t)offsets.size() - 1;
+        if (bytes_out) *bytes_out = celes::BlockPrecond::precond_bytes(N, lmax, offsets);
+        if (max_Nj_out) *max_Nj_out = mx;
+        return CELES_OK;
+    });
+}
+
+int celes_preconditioner_info(const celes_handle* h, double* edge, int64_t* nblocks, double* bytes) {
+    if (!h) return CELES_E_ARG;
+    if (edge) *edge = h->pre ? h->pre->edge() : 0.0;
+    if (nblocks) *nblocks = h->pre ? h->pre->num_blocks() : 0;
+    if (bytes) *bytes = h->pre ? h->pre->bytes() : 0.0;
+    return CELES_OK;
 }
 
 

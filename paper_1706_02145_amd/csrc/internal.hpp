@@ -94,7 +94,8 @@ struct celes_handle {
     // preconditioner
     std::unique_ptr<celes::BlockPrecond> pre;
     uint64_t pre_gen = 0;        // bumped whenever the preconditioner is rebuilt or removed
-    int target_blocks = 0;       // mat-vec work split (0: default); set by the autotuner
+    int target_blocks = 0;       // mat-vec work split (0: default); forced by tests through the environment
+    int tuned_blocks[2] = {0, 0};  // autotuned work split per precision (FP64, complex64); 0: not tuned
     // celes_kernel_timing: HIP events around each coupling-kernel launch
     bool time_kernels = false;
     std::vector<hipEvent_t> tev;  // pairs (begin, end), reused

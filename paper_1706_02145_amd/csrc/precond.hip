@@ -14,6 +14,8 @@ namespace celes {
 // concurrent block factorisations during set-up (one host thread, stream and
 // rocBLAS handle each)
 constexpr int PRE_STREAMS = 4;
+// tile of the inverse apply: rows per block, columns per partial sum
+constexpr int PA_ROWS = 256, PA_COLS = 256;
 
 void partition_cuboids(int64_t N, const double* pos, double edge, std::vector<int64_t>* perm,
                        std::vector<int64_t>* offsets) {
@@ -36,6 +38,47 @@ void partition_cuboids(int64_t N, const double* pos, double edge, std::vector<in
     for (int64_t t = 0; t < N; ++t)
         if (t == 0 || lin[(*perm)[t]] != lin[(*perm)[t - 1]]) offsets->push_back(t);
     offsets->push_back(N);
+}
+
+double BlockPrecond::precond_bytes(int64_t N, int L, const std::vector<int64_t>& offsets) {
+    const double nm = 2.0 * L * (L + 2);
+    double mats = 0, max_dim = 0;
+    for (size_t j = 0; j + 1 < offsets.size(); ++j) {
+        const double dim = (double)(offsets[j + 1] - offsets[j]) * nm;
+        mats += dim * dim;
+        max_dim = std::max(max_dim, dim);
+    }
+    const double nsplit = std::ceil(max_dim / PA_COLS);
+    return mats * (16.0 + 8.0) + nsplit * (double)N * nm * 16.0;
+}
+
+int plan_cuboid_edge(int64_t N, const double* pos, int L, double target, double cap, double* edge,
+                     std::vector<int64_t>* offsets, std::string* msg) {
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int64_t i = 0; i < N; ++i)
+        for (int c = 0; c < 3; ++c) {
+            lo[c] = std::min(lo[c], pos[3 * i + c]);
+            hi[c] = std::max(hi[c], pos[3 * i + c]);
+        }
+    const double D = std::max({hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2], 1e-300});
+    if (!(target > 0)) target = 100.0;
+    std::vector<int64_t> perm, off;
+    double last_bytes = 0;
+    for (double e = 1.02 * D; e >= D / 4096.0; e *= 0.92) {
+        partition_cuboids(N, pos, e, &perm, &off);
+        const double nb = (double)(off.size() - 1);
+        const double bytes = BlockPrecond::precond_bytes(N, L, off);
+        last_bytes = bytes;
+        if ((double)N / nb <= target && (!(cap > 0) || bytes <= cap)) {
+            *edge = e;
+            *offsets = off;
+            return 0;
+        }
+    }
+    *msg = "no cuboid edge fits the preconditioner budget (smallest candidate needs " +
+           std::to_string((long long)(last_bytes / (1 << 20))) + " MiB, cap " +
+           std::to_string((long long)(cap / (1 << 20))) + " MiB)";
+    return CELES_E_OOM_INTERNAL;
 }
 
 // ---------------------------------------------------------------------------
@@ -176,7 +219,6 @@ __global__ void assemble_kernel(AsmArgs g, int64_t ntot) {
 // wave reads 64 consecutive rows = contiguous memory).  Partial sums per
 // column tile go to part[s][permuted row] and a second kernel adds them in a
 // fixed order and scatters back to the caller's sphere order.
-constexpr int PA_ROWS = 256, PA_COLS = 256;
 
 // T: vector precision; TM: matrix precision (FP64 inverse, or its FP32 copy
 // for complex64 vectors); accumulation in TM
@@ -273,6 +315,7 @@ int BlockPrecond::build(int64_t N, int L, const double* pos, double k, const cpl
     N_ = N;
     L_ = L;
     nmax_ = 2 * L * (L + 2);
+    edge_ = edge;
     partition_cuboids(N, pos, edge, &perm_, &offsets_);
     const int nb = (int)offsets_.size() - 1;
     std::vector<int64_t> moff(nb);

@@ -32,9 +32,17 @@ class BlockPrecond {
     int num_blocks() const { return (int)offsets_.size() - 1; }
     const std::vector<int64_t>& perm() const { return perm_; }
     const std::vector<int64_t>& offsets() const { return offsets_; }
-    size_t bytes() const { return mat_elems_ * (16 + 8); }
+    double edge() const { return edge_; }
+    // device bytes held (the budgeted quantity of precond_bytes)
+    double bytes() const { return precond_bytes(N_, L_, offsets_); }
+
+    // bytes a preconditioner over this partition holds on the device: FP64
+    // inverses and their complex64 copy, sum_j (N_j nmax)^2 (16 + 8), plus the
+    // apply's partial sums, ceil(max_j N_j nmax / 256) N nmax 16
+    static double precond_bytes(int64_t N, int L, const std::vector<int64_t>& offsets);
 
    private:
+    double edge_ = 0;
     int L_ = 0, nmax_ = 0;
     int64_t N_ = 0;
     std::vector<int64_t> perm_, offsets_;
@@ -53,5 +61,13 @@ class BlockPrecond {
 // index with x fastest, then y, then z; original index); empty cells skipped.
 void partition_cuboids(int64_t N, const double* pos, double edge, std::vector<int64_t>* perm,
                        std::vector<int64_t>* offsets);
+
+// Budgeted cuboid edge (host only): among e_q = 1.02 D 0.92^q, D the largest
+// extent of the centres' bounding box, q = 0, 1, ... while e_q >= D / 4096,
+// the largest edge whose mean spheres per occupied cuboid is <= target and
+// whose precond_bytes is <= cap (cap <= 0: no cap).  Returns 0, or
+// CELES_E_OOM_INTERNAL when no candidate fits (msg says why).
+int plan_cuboid_edge(int64_t N, const double* pos, int L, double target, double cap, double* edge,
+                     std::vector<int64_t>* offsets, std::string* msg);
 
 }  // namespace celes

@@ -43,3 +43,27 @@ def tvec(w):
 
 def rel(a, b):
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def row_residual(w, b, rows, a_rows, hankel):
+    """True residual rows of the master equation, r_i = T_i a_in^i - (b_i -
+    T_i (W b)^i) for the receivers `rows`, computed by the oracle alone
+    (on-the-fly W rows, Mie T, given incident rows).  b: [N, nmax] or
+    [K, N, nmax]; a_rows: [len(rows), nmax] or [K, len(rows), nmax].
+    Returns (residual rows, right-hand-side rows), shaped like a_rows."""
+    from oracle.translation import apply_W_rows
+    k = k_of(w)
+    ns = np.broadcast_to(np.asarray(w.n_sphere, dtype=np.complex128), (w.N,))
+    t = T_vector(w.lmax, k, np.asarray(w.radii)[rows], ns[rows], w.n0)
+    b = np.asarray(b)
+    Wb = apply_W_rows(w.positions, b, k, w.lmax, list(rows), hankel=hankel)
+    brow = b[..., rows, :]
+    rhs = t * a_rows
+    return rhs - (brow - t * Wb), rhs
+
+
+def beam_core_rows(w, n):
+    """The n spheres closest to the beam axis (x = y = 0): rows where a
+    Gaussian beam's right-hand side is largest."""
+    rho = np.hypot(w.positions[:, 0] - w.illumination["focus"][0], w.positions[:, 1] - w.illumination["focus"][1])
+    return [int(i) for i in np.argsort(rho, kind="stable")[:n]]

@@ -87,3 +87,39 @@ def test_default_options():
     assert o.solver == P.CELES_SOLVER_GMRES
     with pytest.raises(KeyError):
         P.default_options(nonsense=1)
+
+
+def test_preconditioner_plan_respects_target_and_memory_cap():
+    # Section 3.2.1: the LU storage of the block-diagonal preconditioner grows as
+    # sum_j N_j^2, so the cuboid edge is chosen under a sphere-count target and a
+    # byte cap.  The plan is checked against the oracle's own partition at the
+    # chosen edge (block sizes, byte formula) and against the candidate just
+    # above it (which must break the target or the cap).
+    import math
+    from celes_inputs import workload
+    from oracle.solve import partition
+    w = workload("slab2000_l4")
+    N, L, nm = w.N, 4, 48
+
+    def bytes_of(sizes):
+        return float(np.sum((sizes * nm).astype(np.float64) ** 2) * 24 + math.ceil(sizes.max() * nm / 256) * N * nm * 16)
+
+    for target, cap in ((100.0, 0.0), (30.0, 0.0), (100.0, 2.0e9)):
+        e, nb, by, mx = P.plan_preconditioner(w.positions, L, target_Nj=target, mem_cap_bytes=cap)
+        _, off = partition(w.positions, e)
+        sizes = np.diff(off)
+        assert len(sizes) == nb and sizes.max() == mx
+        assert by == pytest.approx(bytes_of(sizes), rel=1e-12)
+        assert N / nb <= target and (cap <= 0 or by <= cap)
+        up = e / 0.92
+        ext = np.ptp(w.positions, axis=0).max()
+        if up <= 1.02 * ext * (1 + 1e-12):
+            _, off2 = partition(w.positions, up)
+            s2 = np.diff(off2)
+            assert N / len(s2) > target or (cap > 0 and bytes_of(s2) > cap)
+    # a cap below every candidate's bytes
+    with pytest.raises(P.CelesError) as ex:
+        P.plan_preconditioner(w.positions, L, target_Nj=100.0, mem_cap_bytes=1.0e6)
+    assert ex.value.name == "CELES_E_OOM"
+    with pytest.raises(P.CelesError):
+        P.plan_preconditioner(np.zeros((0, 3)), L)

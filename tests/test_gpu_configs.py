@@ -1,0 +1,156 @@
+"""The configured solves at their full sizes, anchored to the oracle.
+
+No dense solve exists at these sizes, so each solution is checked by the true
+residual of the master equation (Section 2.2, eq. masterequation:
+M b = T a_in, M = I - T W) on sampled receiver rows, computed by the oracle
+alone: its on-the-fly W rows (eq. a) with its own Hankel table, its Mie T
+and its incident coefficients.  Two bounds are applied to the sampled rows S:
+  * ||r_S|| <= tol ||T a_in||: any subset of rows of a residual within the
+    solver's tolerance obeys it (the full right-hand-side norm uses the
+    library's incident coefficients, checked row by row against the oracle
+    on S first);
+  * ||r_S|| <= 10 tol ||(T a_in)_S||: the sampled rows are themselves solved
+    (rows where the right-hand side is large: the beam core for a Gaussian
+    beam, any rows for a plane wave).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import paper_1706_02145_amd as P
+from celes_inputs import workload
+from oracle.incident import gaussian_beam_coefficients, plane_wave_coefficients
+from tests.gpu_helpers import beam_core_rows, k_of, make_problem, oracle_lut, rel, row_residual, tvec
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+ROW_FACTOR = 10.0
+
+
+def _gauss_rows(w, rows):
+    il = w.illumination
+    return gaussian_beam_coefficients(w.positions[rows], k_of(w), w.lmax, il["waist"], il["focus"], il["alpha_G"],
+                                      il["E0"])
+
+
+def _check_rows(w, b, a_lib, rows, a_rows, tol, lut, label):
+    """Both residual bounds of the module docstring on rows S."""
+    assert rel(a_lib[..., rows, :], a_rows) <= 1e-11, "incident rows differ from the oracle"
+    r, rhs = row_residual(w, b, rows, a_rows, lut)
+    t_all = tvec(w)
+    rhs_norm = np.linalg.norm(t_all * a_lib)
+    rs, rhss = np.linalg.norm(r), np.linalg.norm(rhs)
+    print(f"[{label}] sampled rows {len(rows)}: ||r_S|| {rs:.3e}, ||r_S||/||rhs|| {rs / rhs_norm:.2e}, "
+          f"||r_S||/||rhs_S|| {rs / rhss:.2e} (tol {tol:g})", flush=True)
+    assert rs <= tol * rhs_norm
+    assert rs <= ROW_FACTOR * tol * rhss
+
+
+def test_preconditioner_budget_and_automatic_edge():
+    # Section 3.2.1 memory: a cap below the FP64 inverses' size is refused
+    # before anything is allocated; the automatic edge respects the target and
+    # the solve with it converges to the same solution
+    w = workload("slab300_l3")
+    print("[configs] preconditioner budget slab300_l3", flush=True)
+    p = make_problem(w, hankel=1, tol=1e-10, mem_cap_bytes=1.0e6)
+    with pytest.raises(P.CelesError) as e:
+        p.build_preconditioner(700.0)
+    assert e.value.name == "CELES_E_OOM"
+    assert p.preconditioner_info() == (0.0, 0, 0.0)
+    b0, i0 = p.solve()
+    assert i0["status"] == 0
+    q = make_problem(w, hankel=1, tol=1e-10, target_Nj=20.0)
+    edge, nb, by = q.build_preconditioner()          # automatic edge
+    e_plan, nb_plan, by_plan, _ = P.plan_preconditioner(w.positions, w.lmax, 20.0, 0.0)
+    assert (edge, nb) == (e_plan, nb_plan) and by == pytest.approx(by_plan, rel=1e-12)
+    assert w.N / nb <= 20.0
+    b1, i1 = q.solve()
+    assert i1["status"] == 0 and i1["iterations"] < i0["iterations"]
+    assert rel(b1, b0) <= 1e-9
+    # built by celes_create from the options
+    r = make_problem(w, hankel=1, tol=1e-10, target_Nj=20.0, cuboid_edge=P.CELES_CUBOID_AUTO)
+    assert r.preconditioner_info()[:2] == (edge, nb)
+
+
+def test_slab2000_preconditioned_fp64_to_1e8():
+    # the 2,000-sphere slab (lmax 4, Gaussian beam, LUT 1 nm): block-diagonal
+    # preconditioned FP64 GMRES to 1e-8, as the benchmark's second workload runs it
+    w = workload("slab2000_l4")
+    print("[configs] slab2000_l4 FP64 preconditioned to 1e-8", flush=True)
+    p = make_problem(w, tol=1e-8, restart=100, maxiter=3000)
+    p.build_preconditioner(1500.0)
+    b, info = p.solve()
+    assert info["status"] == 0 and info["rel_residual"] <= 1e-8
+    rows = beam_core_rows(w, 24)
+    lut = oracle_lut(w)
+    a_rows = _gauss_rows(w, rows)
+    _check_rows(w, b[0], p.incident()[0], rows, a_rows, 1e-8, lut, "slab2000")
+    # full-size mat-vec parity on the same rows: library M b vs oracle M b
+    bd = torch.from_numpy(b[0]).to("cuda")
+    yd = torch.empty_like(bd)
+    p.apply_M(bd, yd, P.CELES_FP64)
+    torch.cuda.synchronize()
+    r, rhs = row_residual(w, b[0], rows, a_rows, lut)
+    Mb_oracle = rhs - r
+    assert rel(yd.cpu().numpy()[rows], Mb_oracle) <= 1e-9
+
+
+@pytest.mark.timeout(600)
+def test_slab20000_mixed_to_1e8():
+    # the 20,000-sphere slab (lmax 4): complex64 inner GMRES with FP64 residual
+    # refinement and FP64 block-diagonal preconditioner, to 1e-8
+    w = workload("slab20000_l4")
+    print("[configs] slab20000_l4 mixed to 1e-8 (geometry ready)", flush=True)
+    p = make_problem(w, tol=1e-8, precision=P.CELES_MIXED, inner_tol=1e-4, restart=100, maxiter=3000)
+    p.build_preconditioner(1500.0)
+    print("[configs] slab20000_l4 preconditioner built", flush=True)
+    b, info = p.solve()
+    print(f"[configs] slab20000_l4 mixed: {info['iterations']} inner iterations, {info['refinements']} "
+          f"refinements, residual {info['rel_residual']:.2e}, {info['seconds']:.1f} s", flush=True)
+    assert info["status"] == 0 and info["rel_residual"] <= 1e-8
+    rows = beam_core_rows(w, 8)
+    _check_rows(w, b[0], p.incident()[0], rows, _gauss_rows(w, rows), 1e-8, oracle_lut(w), "slab20000")
+
+
+@pytest.mark.timeout(600)
+def test_slab10000_64rhs_plus_realisations_batched_mixed_to_1e6():
+    # the batched workload: one 10,000-sphere slab (lmax 3) with 64 plane waves
+    # (32 polar angles 0-60 deg x TE/TM) plus two disorder realisations of the
+    # drawn sizes (2 right-hand sides each), one batch, complex64 inner GMRES,
+    # FP64 refinement, block-diagonal preconditioners, to 1e-6
+    w = workload("slab10000_l3")
+    rng = np.random.Generator(np.random.PCG64(40))
+    sizes = [int(v) for v in rng.integers(500, 5001, size=2)]
+    reals = [workload("slab5000_l3", seed=4001 + r, n=n) for r, n in enumerate(sizes)]
+    print(f"[configs] slab10000_l3 x 64 RHS + realisations {sizes}", flush=True)
+    big = P.Problem(w.positions, w.radii, w.n_sphere, w.n0, w.wavelength, 3)
+    betas = np.repeat(np.arange(32) * (np.pi / 3) / 31, 2)
+    pols = np.tile([1, 2], 32)
+    big.set_plane_waves(betas, np.zeros(64), pols)
+    probs = [big]
+    for q in reals:
+        pr = P.Problem(q.positions, q.radii, q.n_sphere, q.n0, q.wavelength, 3)
+        pr.set_plane_waves([0.0, 0.0], [0.0, 0.0], [1, 2])
+        probs.append(pr)
+    for pr in probs:
+        pr.build_preconditioner(1500.0)
+    bt = P.Batch(probs, precision=P.CELES_MIXED, tol=1e-6, inner_tol=1e-3, restart=150, maxiter=600,
+                 max_refinements=4)
+    per, summ = bt.solve()
+    print(f"[configs] batch: status {summ['status']}, worst residual {summ['rel_residual']:.2e}, "
+          f"{summ['seconds']:.1f} s", flush=True)
+    assert summ["status"] == 0 and all(i["rel_residual"] <= 1e-6 for i in per)
+    # sampled systems and rows, by the oracle
+    k = k_of(w)
+    rs = np.random.default_rng(5)
+    sys_big = [0, 1, 21, 40, 62, 63]
+    rows = sorted(int(v) for v in rs.choice(w.N, 8, replace=False))
+    b = big.solution()[sys_big]
+    a_rows = np.stack([plane_wave_coefficients(w.positions[rows], k, 3, betas[s], 0.0, pols[s]) for s in sys_big])
+    _check_rows(w, b, big.incident()[sys_big], rows, a_rows, 1e-6, oracle_lut(w), "batch slab10000")
+    for q, pr in zip(reals, probs[1:]):
+        rows = sorted(int(v) for v in rs.choice(q.N, 8, replace=False))
+        a_rows = np.stack([plane_wave_coefficients(q.positions[rows], k, 3, 0.0, 0.0, pol) for pol in (1, 2)])
+        _check_rows(q, pr.solution(), pr.incident(), rows, a_rows, 1e-6, oracle_lut(q), f"batch N={q.N}")

@@ -35,8 +35,8 @@ def test_gradients_match_oracle():
     Wo, bo = unpack(go, net.in_pad, net.out_pad)
     for l in range(4):
         print(f"layer {l}: dW rel {rel(Ws[l], Wo[l]):.2e} db rel {rel(bs[l], bo[l]):.2e}")
-        assert rel(Ws[l], Wo[l]) <= 2e-3
-        assert rel(bs[l], bo[l]) <= 2e-3
+        assert rel(Ws[l], Wo[l]) <= 1e-3
+        assert rel(bs[l], bo[l]) <= 1e-3
 
 
 def test_features_are_translation_invariant_and_normalised():

@@ -52,15 +52,27 @@ def test_preconditioned_solve_slab64():
     assert i1["iterations"] < i0["iterations"]
 
 
-def test_mixed_precision_matches_fp64():
+@pytest.mark.parametrize("precond", [0.0, 700.0])
+def test_mixed_precision_matches_dense_lu(precond):
+    # complex64 inner GMRES + FP64 refinement (and its FP64 block-diagonal
+    # preconditioner) against the oracle's dense LU of the same LUT-mode M;
+    # the FP64 solve of the same problem is held to the FP64 bar beside it
     w = workload("slab300_l3")
-    print("[solve] slab300_l3 mixed vs fp64", flush=True)
-    pf = make_problem(w, tol=1e-10)
-    bf, inf_f = pf.solve()
+    print(f"[solve] slab300_l3 mixed vs dense LU, preconditioner edge {precond}", flush=True)
+    M, t, a, bref = _dense(w, 0)
     pm = make_problem(w, tol=1e-10, precision=P.CELES_MIXED, inner_tol=1e-4)
+    pf = make_problem(w, tol=1e-10)
+    if precond > 0:
+        pm.build_preconditioner(precond)
+        pf.build_preconditioner(precond)
     bm, inf_m = pm.solve()
+    bf, inf_f = pf.solve()
     assert inf_m["status"] == 0 and inf_m["rel_residual"] <= 1e-10
-    assert rel(bm, bf) <= 1e-6
+    assert inf_f["status"] == 0 and inf_f["rel_residual"] <= 1e-10
+    em, ef = rel(bm[0], bref), rel(bf[0], bref)
+    print(f"[solve] mixed {em:.2e}, fp64 {ef:.2e} vs dense LU", flush=True)
+    assert em <= 1e-6
+    assert ef <= 1e-9
 
 
 def test_optical_theorem_on_gpu_solution():
