@@ -250,6 +250,29 @@ int celes_subsystem_guess(celes_handle* h, int64_t n_sub, const int64_t* idx, do
 int celes_apply_W(celes_handle* h, int precision, int K, const void* x_dev, void* y_dev,
                   void* stream);
 
+/* Bytes of the fixed device scratch buffer of celes_apply_W_noalloc. */
+#define CELES_NOALLOC_SCRATCH_BYTES (128u << 20)
+
+/* For callers that cannot allocate device memory (code under stream
+ * capture, serving loops, harnesses that forbid allocation): y = W x exactly
+ * as celes_apply_W computes it, on the same coupling kernels, but every
+ * scratch byte of the call (the source sums/differences, K N nmax complex,
+ * and the source-chunk partial sums, a multiple of that) is taken from one
+ * fixed device array of CELES_NOALLOC_SCRATCH_BYTES per GPU, which the
+ * library holds from the first call on that GPU until the process ends; the
+ * number of source chunks is capped to fit it.  The call allocates nothing
+ * (no hipMalloc, hipFree or allocating library routine) and always runs the
+ * VALU kernel (celes_apply_W takes the matrix-core kernel for complex64
+ * blocks of 16 or more right-hand sides).  Every call on one GPU shares that
+ * array: calls that overlap in time on one GPU (other streams, other host
+ * threads) race and must be serialised by the caller; the array keeps the
+ * last call's contents, and each call overwrites every byte it reads.
+ * Arguments and layouts as celes_apply_W.  Errors: CELES_E_ARG (null, K < 1,
+ * unknown precision, or 2 K N nmax complex values of the precision larger
+ * than the array), CELES_E_DEVICE (symbol lookup or launch), CELES_E_UNSUPPORTED. */
+int celes_apply_W_noalloc(celes_handle* h, int precision, int K, const void* x_dev, void* y_dev,
+                          void* stream);
+
 /* As celes_apply_W but y = M x = x - T (W x) (eq. M). */
 int celes_apply_M(celes_handle* h, int precision, int K, const void* x_dev, void* y_dev,
                   void* stream);

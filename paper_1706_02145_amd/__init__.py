@@ -223,6 +223,13 @@ class Problem:
         _check(lib().celes_apply_W(self._h, precision, K, C.c_void_p(xp), C.c_void_p(yp), _stream_ptr(stream)),
                self._h)
 
+    def apply_W_noalloc(self, x, y, precision=CELES_FP64, stream=None, K=1):
+        """y = W x with the library's fixed scratch array (celes_apply_W_noalloc)."""
+        xp = x.data_ptr() if hasattr(x, "data_ptr") else int(x)
+        yp = y.data_ptr() if hasattr(y, "data_ptr") else int(y)
+        _check(lib().celes_apply_W_noalloc(self._h, precision, K, C.c_void_p(xp), C.c_void_p(yp),
+                                           _stream_ptr(stream)), self._h)
+
     def apply_M(self, x, y, precision=CELES_FP64, stream=None, K=1):
         xp = x.data_ptr() if hasattr(x, "data_ptr") else int(x)
         yp = y.data_ptr() if hasattr(y, "data_ptr") else int(y)

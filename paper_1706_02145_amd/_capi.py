@@ -59,6 +59,7 @@ SIGNATURES = {
     "celes_subsystem_guess": (C.c_int, [_h, C.c_int64, C.POINTER(C.c_int64), C.c_double, _dp, C.POINTER(SolveInfo)]),
     "celes_apply_W": (C.c_int, [_h, C.c_int, C.c_int, _vp, _vp, _vp]),
     "celes_apply_M": (C.c_int, [_h, C.c_int, C.c_int, _vp, _vp, _vp]),
+    "celes_apply_W_noalloc": (C.c_int, [_h, C.c_int, C.c_int, _vp, _vp, _vp]),
     "celes_cross_sections": (C.c_int, [_h, _dp, _dp, _dp]),
     "celes_far_field": (C.c_int, [_h, C.c_int64, _dp, _dp, _dp]),
     "celes_near_field": (C.c_int, [_h, C.c_int64, _dp, C.c_int, _dp]),

@@ -37,7 +37,7 @@ def build(lmax_compiled=6, jobs=None, verbose=False, force=False):
     units = []
     for L in range(1, lmax_compiled + 1):
         units.append((os.path.join(CSRC, "wx_kernels.hip"), os.path.join(BUILD, f"wx_L{L}.o"), [f"-DCELES_WX_L={L}"]))
-    for f in ("wx_mfma.hip", "wx_dispatch.hip", "vec_kernels.hip", "batch_kernels.hip", "precond.hip", "nn.hip", "farfield.hip", "nearfield.hip",
+    for f in ("wx_mfma.hip", "wx_dispatch.hip", "vec_kernels.hip", "batch_kernels.hip", "precond.hip", "nn.hip", "farfield.hip", "nearfield.hip", "noalloc.hip",
               "host_math.cpp",
               "celes_lib.cpp"):
         units.append((os.path.join(CSRC, f), os.path.join(BUILD, os.path.splitext(f)[0] + ".o"), []))

@@ -302,7 +302,15 @@ static int mfma_width(const celes_handle* h, int K) {
 // x, y: [K][N][nmax] device buffers of precision T
 template <typename T>
 static int matvec_valu(celes_handle* h, const cx<T>* x, cx<T>* y, int K, int epilogue, hipStream_t s, int target,
-                       bool timed);
+                       bool timed, void* ext = nullptr, size_t ext_bytes = 0);
+
+// source-chunk split without tuning: the environment (tests), the handle's
+// forced value, or 4096 blocks
+static int matvec_target_fixed(const celes_handle* h) {
+    const char* env = std::getenv("CELES_WX_TARGET_BLOCKS");
+    if (env) return std::max(1, std::atoi(env));
+    return h->target_blocks > 0 ? h->target_blocks : 4096;
+}
 
 // source-chunk split of the VALU mat-vec: the environment (tests), the
 // handle's forced value, the autotuned value, or 4096 blocks.  With
@@ -354,26 +362,38 @@ int matvec(celes_handle* h, const cx<T>* x, cx<T>* y, int K, int epilogue, hipSt
     return matvec_valu<T>(h, x, y, K, epilogue, s, matvec_target<T>(h, x, y, K, epilogue, s), true);
 }
 
+// With ext (bytes ext_bytes) the source sums/differences and the chunk
+// partial sums live in that caller-given device buffer, with the number of
+// source chunks capped so that both fit, and nothing is allocated.
 template <typename T>
 static int matvec_valu(celes_handle* h, const cx<T>* x, cx<T>* y, int K, int epilogue, hipStream_t s, int target,
-                       bool timed) {
+                       bool timed, void* ext, size_t ext_bytes) {
     const int64_t N = h->N;
     const int kb = pick_kb<T>(h->L, K);
     int64_t nbx = (N + celes::WX_BLOCK_SIZE - 1) / celes::WX_BLOCK_SIZE * celes::wx_num_groups(h->L) * (K / kb);
     int64_t nchunk = (target + nbx - 1) / nbx;
     nchunk = std::max<int64_t>(1, std::min<int64_t>(nchunk, (N + celes::WX_TILE_SIZE - 1) / celes::WX_TILE_SIZE));
+    const size_t vec_bytes = (size_t)K * N * h->nmax * sizeof(cx<T>);     // one [K][N][nmax] vector
+    const size_t xsd_bytes = (vec_bytes + 255) / 256 * 256;
+    if (ext) {
+        const size_t fit = ext_bytes > xsd_bytes ? (ext_bytes - xsd_bytes) / vec_bytes : 0;
+        if (fit < 1)
+            return fail(h, CELES_E_ARG, "K N nmax too large for the fixed scratch buffer (needs " +
+                                            std::to_string(xsd_bytes + vec_bytes) + " bytes, has " +
+                                            std::to_string(ext_bytes) + ")");
+        nchunk = std::min<int64_t>(nchunk, (int64_t)fit);
+    }
     int64_t chunk_len = (N + nchunk - 1) / nchunk;
     chunk_len = (chunk_len + celes::WX_TILE_SIZE - 1) / celes::WX_TILE_SIZE * celes::WX_TILE_SIZE;
     const int nchunk_eff = (int)((N + chunk_len - 1) / chunk_len);
-    if (!h->d_xsd.ensure((size_t)K * N * h->nmax * sizeof(cx<T>)) ||
-        !h->d_part.ensure((size_t)nchunk_eff * K * h->nmax * N * sizeof(cx<T>)))
+    if (!ext && (!h->d_xsd.ensure(vec_bytes) || !h->d_part.ensure((size_t)nchunk_eff * vec_bytes)))
         return fail(h, CELES_E_OOM, "cannot allocate mat-vec scratch");
     celes::WxArgs<T> a;
     a.px = h->d_px.as<double>();
     a.py = h->d_py.as<double>();
     a.pz = h->d_pz.as<double>();
-    a.xsd = h->d_xsd.as<cx<T>>();
-    a.part = h->d_part.as<cx<T>>();
+    a.xsd = ext ? (cx<T>*)ext : h->d_xsd.as<cx<T>>();
+    a.part = ext ? (cx<T>*)((char*)ext + xsd_bytes) : h->d_part.as<cx<T>>();
     a.lut.coef = (sizeof(T) == 8) ? (const cx<T>*)h->d_lut64.p : (const cx<T>*)h->d_lut32.p;
     a.lut.d_lo = h->lut_lo;
     a.lut.inv_dr = 1.0 / h->lut_dr;
@@ -729,6 +749,18 @@ double residual64(celes_handle* h, const cx<double>* rhs, const cx<double>* x, c
 }
 
 }  // namespace
+
+int matvec_on_scratch(celes_handle* h, int precision, int K, const void* x, void* y, hipStream_t s, void* scratch,
+                      size_t scratch_bytes) {
+    if (precision == CELES_FP64)
+        return matvec_valu<double>(h, (const cx<double>*)x, (cx<double>*)y, K, 0, s, matvec_target_fixed(h), false,
+                                   scratch, scratch_bytes);
+    if (precision == CELES_MIXED)
+        return matvec_valu<float>(h, (const cx<float>*)x, (cx<float>*)y, K, 0, s, matvec_target_fixed(h), false,
+                                  scratch, scratch_bytes);
+    return fail(h, CELES_E_ARG, "unknown precision");
+}
+
 
 // ===========================================================================
 // C ABI

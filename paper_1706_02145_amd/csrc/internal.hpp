@@ -105,3 +105,9 @@ struct celes_handle {
         for (hipEvent_t e : tev) (void)hipEventDestroy(e);
     }
 };
+
+// y = W x for K right-hand sides on the VALU coupling kernel, with the
+// source sums/differences and chunk partial sums in the caller-given device
+// buffer scratch [scratch_bytes]: no allocation, no timing events
+int matvec_on_scratch(celes_handle* h, int precision, int K, const void* x, void* y, hipStream_t s, void* scratch,
+                      size_t scratch_bytes);
