@@ -12,6 +12,7 @@ Modules (each function cites the passage of the paper it follows):
   special      spherical Bessel/Hankel, normalized Legendre, pi/tau functions
   wigner       exact Wigner-3j symbols (Racah formula, rational arithmetic)
   translation  a5/b5 coefficients, SVWF translation operator, dense W
+  rotation     Wigner-d basis rotation, rotation-translation-rotation form of A
   svwf         spherical and plane vector wave functions (field evaluation)
   mie          sphere T-matrix (paper formula) and an independent Mie series
   incident     plane-wave and Gaussian-beam initial-field coefficients
