@@ -106,6 +106,44 @@ def flops_per_pair_executed(L, groups, hankel_lut=True):
     return f
 
 
+def _delta_pi2(l, k, m):
+    # d^l_{km}(pi/2) (Wigner's sum), to count the nonzero constants the
+    # rotation kernel multiplies by
+    F = math.factorial
+    s = 0
+    for j in range(2 * l + 1):
+        a, b, c = l + m - j, k - m + j, l - k - j
+        if a < 0 or b < 0 or c < 0:
+            continue
+        s += (-1) ** ((k - m + j) % 2) * F(2 * l) // (F(a) * F(j) * F(b) * F(c))
+    return s
+
+
+def flops_per_pair_rotate(L, hankel_lut=True, executed=False):
+    """Flops per sphere pair of the rotation-translation-rotation mat-vec
+    (one right-hand side; counting as in flops_per_pair): geometry, Hankel
+    orders and the powers of q and e^{i theta} once, the axial A_z, B_z sums
+    once (executed: once per polarisation pass), and per pass the two
+    rotations (phases and two constant d(pi/2) products each way) and the
+    axial translation."""
+    P = 2 * L
+    f = 19 + ((4 + 24 + 1 + 5 * (P - 1)) if hankel_lut else (4 + 6 + 5 * (P - 1))) + 12 * (L - 1)
+    nz = {l: sum(1 for k in range(-l, l + 1) for m in range(-l, l + 1) if _delta_pi2(l, k, m) != 0)
+          for l in range(1, L + 1)}
+    sums = 0
+    per_pass = 0
+    for l in range(1, L + 1):
+        per_pass += 12 * l + 4 * nz[l] + 12 * l + 4 * nz[l]            # rotate in
+        per_pass += 4 * nz[l] + 12 * l + 4 * nz[l] + 2 + 16 * l         # rotate out + accumulate
+        for m in range(-l, l + 1):
+            for lp in range(max(1, abs(m)), L + 1):
+                # A terms: |l-l'| <= p <= l+l', l+l'+p even; B terms: |l-l'|+1 <= p <= l+l'-1, odd
+                nt = (min(l, lp) + 1) + min(l, lp)
+                sums += 4 * nt
+                per_pass += 4 + 8                                       # A +- iB, multiply-accumulate
+    return f + 2 * per_pass + (2 * sums if executed else sums)
+
+
 # pass groups of the coupling kernel per cut-off (receiving |m| per group)
 KERNEL_GROUPS = {1: [(0, 1)], 2: [(0, 2), (1,)], 3: [(1,), (0, 3), (2,)], 4: [(2, 4), (0, 3), (1,)],
                  5: [(3, 4), (2, 5), (1,), (0,)], 6: [(3, 5), (2, 6), (0, 4), (1,)]}
@@ -696,6 +734,54 @@ def warmstart_mode(a):
         "data_generation_seconds": t_data, "training_seconds": t_train}))
 
 
+def translation_mode(a):
+    """Direct block evaluation against rotation-translation-rotation (Section
+    5, Discussion) on one geometry (the 2,000-sphere slab) at lmax 1..6, FP64
+    and complex64: kernel time per W.b (HIP events around the coupling
+    kernel), algorithmic flops of the direct scheme, and the crossover."""
+    import torch
+    import paper_1706_02145_amd as P
+    from celes_inputs import workload, random_coefficients
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    w = workload(a.workload if a.workload != "slab20000_l4" else "slab2000_l4")
+    N = w.N
+    stream = torch.cuda.current_stream()
+    rows = []
+    for L in [int(v) for v in a.translation_lmax.split(",")]:
+        nm = 2 * L * (L + 2)
+        row = {"lmax": L}
+        x64 = torch.from_numpy(random_coefficients(7, 1, N, nm)[0]).to("cuda")
+        for scheme, tr in (("direct", P.CELES_TRANSLATION_DIRECT), ("rotate", P.CELES_TRANSLATION_ROTATE)):
+            p = P.Problem(w.positions, w.radii, w.n_sphere, w.n0, w.wavelength, L, lut_dr=w.lut_dr, translation=tr)
+            for prec, xx in (("fp64", x64), ("fp32", x64.to(torch.complex64))):
+                yy = torch.empty_like(xx)
+                pr = P.CELES_FP64 if prec == "fp64" else P.CELES_MIXED
+                p.apply_W(xx, yy, pr, stream=stream)
+                torch.cuda.synchronize()
+                p.kernel_timing(True)
+                for _ in range(a.matvec_reps):
+                    p.apply_W(xx, yy, pr, stream=stream)
+                torch.cuda.synchronize()
+                ms, _ = p.kernel_timing(False)
+                row[f"{scheme}_{prec}_ms"] = ms
+            p.close()
+        row["direct_flops_per_pair"] = flops_per_pair(L)
+        row["speedup_rotate_fp64"] = row["direct_fp64_ms"] / row["rotate_fp64_ms"]
+        row["speedup_rotate_fp32"] = row["direct_fp32_ms"] / row["rotate_fp32_ms"]
+        print(f"[translation] {row}", file=sys.stderr, flush=True)
+        rows.append(row)
+
+    def crossover(prec):
+        for r in rows:
+            if r[f"speedup_rotate_{prec}"] > 1.0:
+                return r["lmax"]
+        return None
+    print(json.dumps({"metric": "coupling kernel time per W.b, direct vs rotation-translation-rotation",
+                      "unit": "ms", "config": {"workload": f"{w.name} geometry (N={N}), LUT 1 nm, one right-hand side"},
+                      "rows": rows, "crossover_lmax_fp64": crossover("fp64"),
+                      "crossover_lmax_fp32": crossover("fp32")}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -711,8 +797,9 @@ def main():
                     help="preconditioner cuboid edge in nm (-1: budgeted automatic edge, 0: none)")
     ap.add_argument("--hankel", choices=["lut", "direct"], default="lut")
     ap.add_argument("--profile", action="store_true", help="mat-vec launches only (for rocprofv3)")
+    ap.add_argument("--translation-lmax", default="1,2,3,4,5,6", help="translation mode: cut-offs")
     ap.add_argument("--mode", choices=["solve", "batched", "warmstart", "mixed", "paper", "scaling", "validation",
-                                       "large"],
+                                       "large", "translation"],
                     default="solve")
     ap.add_argument("--mixed-workload", default="slab20000_l4")
     ap.add_argument("--paper-solvers", default="gmres", help="paper mode: comma-separated gmres,bicgstab")
@@ -751,6 +838,8 @@ def main():
         return validation_mode(a)
     if a.mode == "large":
         return large_mode(a)
+    if a.mode == "translation":
+        return translation_mode(a)
 
     import numpy as np
     import torch
@@ -847,6 +936,30 @@ def main():
     log(f"{other} Hankel kernel {other_kernel_ms:.2f} ms")
     traffic = measured_traffic(w.name, N, L, a.hankel)
 
+    # the rotation-translation-rotation scheme on the same geometry and vector
+    p.set_solve_options(translation=P.CELES_TRANSLATION_ROTATE)
+    rot = {}
+    for prec, xx, yy in (("fp64", x, y), ("fp32", x32, y32)):
+        pr = P.CELES_FP64 if prec == "fp64" else P.CELES_MIXED
+        p.apply_W(xx, yy, pr, stream=stream)
+        torch.cuda.synchronize()
+        p.kernel_timing(True)
+        for _ in range(a.matvec_reps):
+            p.apply_W(xx, yy, pr, stream=stream)
+        torch.cuda.synchronize()
+        rot[prec] = p.kernel_timing(False)[0]
+    p.set_solve_options(translation=P.CELES_TRANSLATION_DIRECT)
+    fpp_rot = flops_per_pair_rotate(L, a.hankel == "lut")
+    rotate = {"kernel": f"wx_rtr_kernel<T, {L}, {hmode}> (rotation into the pair frame, translation along z, "
+                        "rotation back)",
+              "flops_per_pair": fpp_rot,
+              "flops_per_pair_executed": flops_per_pair_rotate(L, a.hankel == "lut", executed=True)}
+    for prec, peak in (("fp64", PEAK_FP64_VALU_TFLOPS), ("fp32", PEAK_FP32_VALU_TFLOPS)):
+        rotate[prec] = {"kernel_ms": rot[prec], "updates_per_s": updates_per_mv / (rot[prec] * 1e-3),
+                        "tflops": fpp_rot * N * (N - 1) / (rot[prec] * 1e-3) / 1e12,
+                        "frac": fpp_rot * N * (N - 1) / (rot[prec] * 1e-3) / 1e12 / peak}
+    log(f"rotation scheme kernels: FP64 {rot['fp64']:.2f} ms, complex64 {rot['fp32']:.2f} ms")
+
     # ---- time to residual 1e-6: FP64 vs mixed, one preconditioner for both ----
     ttr = {}
     t_pre, pre_info = 0.0, None
@@ -858,8 +971,12 @@ def main():
         torch.cuda.synchronize()
         t_pre = time.perf_counter() - t0
         log(f"preconditioner {pre_info} in {t_pre:.1f} s")
-        for name, prec in (("fp64", P.CELES_FP64), ("mixed", P.CELES_MIXED)):
-            p.set_solve_options(tol=1e-6, precision=prec, restart=100, maxiter=3000, inner_tol=1e-3)
+        for name, prec, tr in (("fp64", P.CELES_FP64, P.CELES_TRANSLATION_DIRECT),
+                               ("mixed", P.CELES_MIXED, P.CELES_TRANSLATION_DIRECT),
+                               ("fp64_rotate", P.CELES_FP64, P.CELES_TRANSLATION_ROTATE),
+                               ("mixed_rotate", P.CELES_MIXED, P.CELES_TRANSLATION_ROTATE)):
+            p.set_solve_options(tol=1e-6, precision=prec, restart=100, maxiter=3000, inner_tol=1e-3,
+                                translation=tr)
             torch.cuda.synchronize()
             t1 = time.perf_counter()
             _, inf = p.solve()
@@ -868,7 +985,9 @@ def main():
                          "refinements": inf["refinements"], "matvec_seconds": inf["matvec_seconds"],
                          "rel_residual": inf["rel_residual"]}
             log(f"{name} to 1e-6: {ttr[name]['seconds']:.1f} s, {inf['iterations']} iterations")
+        p.set_solve_options(translation=P.CELES_TRANSLATION_DIRECT)
         ttr["speedup_mixed_vs_fp64"] = ttr["fp64"]["seconds"] / ttr["mixed"]["seconds"]
+        ttr["speedup_mixed_rotate_vs_fp64"] = ttr["fp64"]["seconds"] / ttr["mixed_rotate"]["seconds"]
         ttr["solve_seconds_exclude"] = "preconditioner set-up (preconditioner_setup_s)"
 
     # ---- the 2,000-sphere slab: preconditioned FP64 GMRES to 1e-8 ----
@@ -954,6 +1073,7 @@ def main():
         "kernel_other_hankel": {"hankel": other, "kernel_ms": other_kernel_ms,
                                 "frac": other_fpp * N * (N - 1) / (other_kernel_ms * 1e-3) / 1e12 /
                                         PEAK_FP64_VALU_TFLOPS},
+        "rotate_scheme": rotate,
         "setup_s": t_setup,
         "preconditioner": None if pre_info is None else {"edge_nm": pre_info[0], "cuboids": pre_info[1],
                                                          "bytes": pre_info[2], "setup_s": t_pre},

@@ -56,6 +56,11 @@ extern "C" {
                                  * 3.2.2), higher orders by the upward three-term recurrence   */
 #define CELES_HANKEL_DIRECT 1   /* h_0, h_1 from sin/cos per pair, then the same recurrence    */
 
+/* evaluation of the translation blocks inside the single-problem mat-vec */
+#define CELES_TRANSLATION_DIRECT 0   /* each block entry from the a5/b5 sums (Appendix A.2), O(lmax^4) */
+#define CELES_TRANSLATION_ROTATE 1   /* rotate the source into the pair frame, translate along z,
+                                      * rotate back (Section 5, Discussion), O(lmax^3) per pair */
+
 /* iterative solver of the master equation (Section 3.2 offers both) */
 #define CELES_SOLVER_GMRES 0    /* restarted GMRES (default)                                  */
 #define CELES_SOLVER_BICGSTAB 1 /* BiCGSTAB: two mat-vecs per iteration, seven work vectors  */
@@ -89,6 +94,11 @@ typedef struct celes_options {
                              * (<= 0: 90% of the device memory free at build time)            */
     int autotune;           /* 1: the first mat-vec of each precision on a handle times the
                              * candidate source-chunk splits and keeps the fastest             */
+    int translation;        /* CELES_TRANSLATION_DIRECT (default) or CELES_TRANSLATION_ROTATE:
+                             * how the VALU mat-vec of single problems (celes_apply_W/M,
+                             * celes_solve, celes_apply_W_noalloc) evaluates each pair's
+                             * block; the matrix-core kernel, batches and the
+                             * preconditioner assembly always use the direct form           */
 } celes_options;
 
 typedef struct celes_solve_info {
@@ -130,11 +140,12 @@ void celes_destroy(celes_handle* h);
 
 /* Replace the solver settings of a handle for its next solves: precision,
  * tol, inner_tol, restart, maxiter, max_refinements, verbose, solver,
- * target_Nj, mem_cap_bytes and autotune are taken from *opt; the fields fixed
- * at creation (hankel, lut_dr, device, cuboid_edge) are kept, and so are the
+ * target_Nj, mem_cap_bytes, autotune and translation are taken from *opt;
+ * the fields fixed at creation (hankel, lut_dr, device, cuboid_edge) are
+ * kept, and so are the
  * geometry, incident field and preconditioner (so FP64 and mixed solves can
- * share one preconditioner).  Errors: CELES_E_ARG (null, unknown solver or
- * precision). */
+ * share one preconditioner).  Errors: CELES_E_ARG (null, unknown solver,
+ * precision or translation scheme). */
 int celes_set_solve_options(celes_handle* h, const celes_options* opt);
 
 /* Text of the last error on this handle (or of the last failed create when

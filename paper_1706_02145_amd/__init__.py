@@ -9,7 +9,7 @@ import ctypes as C
 
 import numpy as np
 
-from ._capi import (CELES_CUBOID_AUTO, CELES_FP64, CELES_HANKEL_DIRECT, CELES_HANKEL_LUT, CELES_MIXED, CELES_SOLVER_BICGSTAB,
+from ._capi import (CELES_CUBOID_AUTO, CELES_TRANSLATION_DIRECT, CELES_TRANSLATION_ROTATE, CELES_FP64, CELES_HANKEL_DIRECT, CELES_HANKEL_LUT, CELES_MIXED, CELES_SOLVER_BICGSTAB,
                     CELES_SOLVER_GMRES, ERRORS, Options, SolveInfo, lib, LIB_PATH)
 
 __all__ = ["Problem", "Batch", "Network", "CelesError", "default_options", "plan_preconditioner", "mie_coefficients", "translation_tables", "version",
@@ -120,7 +120,8 @@ class Problem:
 
     def set_solve_options(self, **kw):
         """Change solver settings (precision, tol, inner_tol, restart, maxiter,
-        max_refinements, verbose, solver, target_Nj, mem_cap_bytes, autotune)
+        max_refinements, verbose, solver, target_Nj, mem_cap_bytes, autotune,
+        translation)
         for the next solves, keeping geometry, incident field and
         preconditioner (celes_set_solve_options)."""
         opt = Options()

@@ -16,6 +16,7 @@ CELES_FP64, CELES_MIXED = 0, 1
 CELES_HANKEL_LUT, CELES_HANKEL_DIRECT = 0, 1
 CELES_SOLVER_GMRES, CELES_SOLVER_BICGSTAB = 0, 1
 CELES_CUBOID_AUTO = -1.0
+CELES_TRANSLATION_DIRECT, CELES_TRANSLATION_ROTATE = 0, 1
 
 
 class Options(C.Structure):
@@ -23,7 +24,7 @@ class Options(C.Structure):
                 ("inner_tol", C.c_double), ("restart", C.c_int), ("maxiter", C.c_int),
                 ("max_refinements", C.c_int), ("cuboid_edge", C.c_double), ("device", C.c_int),
                 ("verbose", C.c_int), ("solver", C.c_int), ("target_Nj", C.c_double),
-                ("mem_cap_bytes", C.c_double), ("autotune", C.c_int)]
+                ("mem_cap_bytes", C.c_double), ("autotune", C.c_int), ("translation", C.c_int)]
 
 
 class SolveInfo(C.Structure):

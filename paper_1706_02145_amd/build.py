@@ -37,6 +37,7 @@ def build(lmax_compiled=6, jobs=None, verbose=False, force=False):
     units = []
     for L in range(1, lmax_compiled + 1):
         units.append((os.path.join(CSRC, "wx_kernels.hip"), os.path.join(BUILD, f"wx_L{L}.o"), [f"-DCELES_WX_L={L}"]))
+        units.append((os.path.join(CSRC, "wx_rtr.hip"), os.path.join(BUILD, f"wx_rtr_L{L}.o"), [f"-DCELES_WX_L={L}"]))
     for f in ("wx_mfma.hip", "wx_dispatch.hip", "vec_kernels.hip", "batch_kernels.hip", "precond.hip", "nn.hip", "farfield.hip", "nearfield.hip", "noalloc.hip",
               "host_math.cpp",
               "celes_lib.cpp"):
@@ -79,6 +80,7 @@ def build(lmax_compiled=6, jobs=None, verbose=False, force=False):
             for L in range(lmax_compiled + 1, 7):
                 for T in ("double", "float"):
                     f.write(f"template <> void wx_run_L<{T}, {L}>(const WxArgs<{T}>&, int, int, hipStream_t) {{}}\n")
+                    f.write(f"template <> void wx_rtr_run_L<{T}, {L}>(const WxArgs<{T}>&, int, int, hipStream_t) {{}}\n")
                 f.write(f"template <> int wx_num_groups_L<{L}>() {{ return 1; }}\n")
                 for T in ("double", "float"):
                     f.write(f"template <> int wx_max_kb_L<{T}, {L}>() {{ return 1; }}\n")

@@ -369,8 +369,10 @@ template <typename T>
 static int matvec_valu(celes_handle* h, const cx<T>* x, cx<T>* y, int K, int epilogue, hipStream_t s, int target,
                        bool timed, void* ext, size_t ext_bytes) {
     const int64_t N = h->N;
-    const int kb = pick_kb<T>(h->L, K);
-    int64_t nbx = (N + celes::WX_BLOCK_SIZE - 1) / celes::WX_BLOCK_SIZE * celes::wx_num_groups(h->L) * (K / kb);
+    const bool rot = h->opt.translation == CELES_TRANSLATION_ROTATE;
+    const int kb = rot ? 1 : pick_kb<T>(h->L, K);
+    int64_t nbx = rot ? (N + celes::WX_RTR_BLOCK_SIZE - 1) / celes::WX_RTR_BLOCK_SIZE * 2 * K
+                      : (N + celes::WX_BLOCK_SIZE - 1) / celes::WX_BLOCK_SIZE * celes::wx_num_groups(h->L) * (K / kb);
     int64_t nchunk = (target + nbx - 1) / nbx;
     nchunk = std::max<int64_t>(1, std::min<int64_t>(nchunk, (N + celes::WX_TILE_SIZE - 1) / celes::WX_TILE_SIZE));
     const size_t vec_bytes = (size_t)K * N * h->nmax * sizeof(cx<T>);     // one [K][N][nmax] vector
@@ -409,7 +411,7 @@ static int matvec_valu(celes_handle* h, const cx<T>* x, cx<T>* y, int K, int epi
     a.sys0 = 0;
     const cx<T>* tq = (sizeof(T) == 8) ? (const cx<T>*)h->d_tq64.p : (const cx<T>*)h->d_tq32.p;
     int rc = celes::wx_launch<T>(a, h->L, h->opt.hankel == CELES_HANKEL_DIRECT ? 1 : 0, nchunk_eff, x, tq, y,
-                                 epilogue, s, timed ? timing_events(h) : nullptr);
+                                 epilogue, s, timed ? timing_events(h) : nullptr, rot ? 1 : 0);
     if (rc == -1) return fail(h, CELES_E_UNSUPPORTED, "lmax not compiled");
     if (rc != 0) return fail(h, CELES_E_DEVICE, "mat-vec launch failed");
     return CELES_OK;
@@ -823,6 +825,8 @@ static int celes_create_impl(celes_handle** out, int64_t N, const double* pos, c
     if (h->opt.restart < 1) h->opt.restart = 1;
     if (h->opt.solver != CELES_SOLVER_GMRES && h->opt.solver != CELES_SOLVER_BICGSTAB)
         return fail(nullptr, CELES_E_ARG, "unknown solver");
+    if (h->opt.translation != CELES_TRANSLATION_DIRECT && h->opt.translation != CELES_TRANSLATION_ROTATE)
+        return fail(nullptr, CELES_E_ARG, "unknown translation scheme");
     if (hipSetDevice(h->opt.device) != hipSuccess) return fail(nullptr, CELES_E_DEVICE, "hipSetDevice failed");
     h->N = N;
     h->L = lmax;
@@ -910,6 +914,8 @@ int celes_set_solve_options(celes_handle* h, const celes_options* opt) {
     if (opt->solver != CELES_SOLVER_GMRES && opt->solver != CELES_SOLVER_BICGSTAB)
         return fail(h, CELES_E_ARG, "unknown solver");
     if (opt->precision != CELES_FP64 && opt->precision != CELES_MIXED) return fail(h, CELES_E_ARG, "unknown precision");
+    if (opt->translation != CELES_TRANSLATION_DIRECT && opt->translation != CELES_TRANSLATION_ROTATE)
+        return fail(h, CELES_E_ARG, "unknown translation scheme");
     celes_options& o = h->opt;
     o.precision = opt->precision;
     o.tol = opt->tol;
@@ -922,6 +928,10 @@ int celes_set_solve_options(celes_handle* h, const celes_options* opt) {
     o.target_Nj = opt->target_Nj;
     o.mem_cap_bytes = opt->mem_cap_bytes;
     o.autotune = opt->autotune;
+    if (o.translation != opt->translation) {
+        o.translation = opt->translation;
+        h->tuned_blocks[0] = h->tuned_blocks[1] = 0;     // a tuned split belongs to one scheme
+    }
     return CELES_OK;
 }
 

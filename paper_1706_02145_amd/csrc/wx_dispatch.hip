@@ -109,20 +109,31 @@ template int wx_batch_run<float>(int, const WxArgs<float>*, const int*, const in
 
 template <typename T>
 int wx_launch(const WxArgs<T>& a, int L, int hmode, int nchunk, const cx<T>* x, const cx<T>* tq,
-              cx<T>* y, int epilogue, hipStream_t s, const hipEvent_t* ev) {
+              cx<T>* y, int epilogue, hipStream_t s, const hipEvent_t* ev, int scheme) {
     const int half = L * (L + 2);
     const int64_t tot = (int64_t)a.n * half * a.nrhs;
+    if (L < 1 || L > 6) return -1;
     hipLaunchKernelGGL(wx_prep_kernel<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, x,
                        const_cast<cx<T>*>(a.xsd), a.n, half, a.nrhs);
     if (ev) hipEventRecord(ev[0], s);
-    switch (L) {
-        case 1: wx_run_L<T, 1>(a, hmode, nchunk, s); break;
-        case 2: wx_run_L<T, 2>(a, hmode, nchunk, s); break;
-        case 3: wx_run_L<T, 3>(a, hmode, nchunk, s); break;
-        case 4: wx_run_L<T, 4>(a, hmode, nchunk, s); break;
-        case 5: wx_run_L<T, 5>(a, hmode, nchunk, s); break;
-        case 6: wx_run_L<T, 6>(a, hmode, nchunk, s); break;
-        default: return -1;
+    if (scheme == 1) {
+        switch (L) {
+            case 1: wx_rtr_run_L<T, 1>(a, hmode, nchunk, s); break;
+            case 2: wx_rtr_run_L<T, 2>(a, hmode, nchunk, s); break;
+            case 3: wx_rtr_run_L<T, 3>(a, hmode, nchunk, s); break;
+            case 4: wx_rtr_run_L<T, 4>(a, hmode, nchunk, s); break;
+            case 5: wx_rtr_run_L<T, 5>(a, hmode, nchunk, s); break;
+            case 6: wx_rtr_run_L<T, 6>(a, hmode, nchunk, s); break;
+        }
+    } else {
+        switch (L) {
+            case 1: wx_run_L<T, 1>(a, hmode, nchunk, s); break;
+            case 2: wx_run_L<T, 2>(a, hmode, nchunk, s); break;
+            case 3: wx_run_L<T, 3>(a, hmode, nchunk, s); break;
+            case 4: wx_run_L<T, 4>(a, hmode, nchunk, s); break;
+            case 5: wx_run_L<T, 5>(a, hmode, nchunk, s); break;
+            case 6: wx_run_L<T, 6>(a, hmode, nchunk, s); break;
+        }
     }
     if (ev) hipEventRecord(ev[1], s);
     hipLaunchKernelGGL(wx_finish_kernel<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, a.part, nchunk,
@@ -142,8 +153,8 @@ int wx_launch_mfma(const WxMfmaArgs& a, int L, int width, int hmode, int nchunk,
 }
 
 template int wx_launch<double>(const WxArgs<double>&, int, int, int, const cx<double>*, const cx<double>*,
-                               cx<double>*, int, hipStream_t, const hipEvent_t*);
+                               cx<double>*, int, hipStream_t, const hipEvent_t*, int);
 template int wx_launch<float>(const WxArgs<float>&, int, int, int, const cx<float>*, const cx<float>*,
-                              cx<float>*, int, hipStream_t, const hipEvent_t*);
+                              cx<float>*, int, hipStream_t, const hipEvent_t*, int);
 
 }  // namespace celes

@@ -36,6 +36,11 @@ struct WxArgs {
 // per-L pass launcher (defined in wx_kernels.hip, one translation unit per L)
 template <typename T, int L>
 void wx_run_L(const WxArgs<T>& a, int hmode, int nchunk, hipStream_t s);
+// rotation-translation-rotation launcher (defined in wx_rtr.hip, one unit per L):
+// grid (receiver tiles of 64, source chunks, 2 passes x right-hand sides)
+template <typename T, int L>
+void wx_rtr_run_L(const WxArgs<T>& a, int hmode, int nchunk, hipStream_t s);
+constexpr int WX_RTR_BLOCK_SIZE = 64;   // receivers per block of the rotation kernel
 // number of pass groups (third grid dimension) of cut-off L
 template <int L>
 int wx_num_groups_L();
@@ -60,8 +65,10 @@ constexpr int WX_TILE_SIZE = 16;    // sources per LDS tile
 // right-hand sides; x, y: [nrhs][N][nmax]; tq: [N][2][L] Mie coefficients.
 // ev[0], ev[1] (if ev is given) are recorded on s right before and after the
 // coupling kernel.  Returns 0 on success.
+// scheme 0: direct block evaluation (wx_fused_kernel); 1: rotation,
+// translation along z, rotation back (wx_rtr_kernel; a.kb must be 1)
 template <typename T>
 int wx_launch(const WxArgs<T>& a, int L, int hmode, int nchunk, const cx<T>* x, const cx<T>* tq,
-              cx<T>* y, int epilogue, hipStream_t s, const hipEvent_t* ev = nullptr);
+              cx<T>* y, int epilogue, hipStream_t s, const hipEvent_t* ev = nullptr, int scheme = 0);
 
 }  // namespace celes
