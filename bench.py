@@ -637,101 +637,105 @@ def scaling_mode(a):
 
 
 def warmstart_mode(a):
-    """Learned initial guess: train on solver output of several slabs
-    (lmax 3, N = a.train_n each), evaluate on a larger unseen slab: GMRES
-    iterations and time to residual 1e-6 from x0 = 0, x0 = T a_in, the
-    network's prediction and the solution of a central sub-ensemble (the
-    paper's custom initial condition, Section 4.2)."""
+    """Learned initial guess (the custom initial condition of Section 4.2):
+    train the network on solver output of a.train_slabs slabs (lmax 3,
+    N = a.train_n each, vf 0.3, 2 um thick), evaluate on an unseen slab of
+    a.eval_n spheres: GMRES iterations and time to residual 1e-6 from x0 = 0
+    and from the network's prediction (and optionally from x0 = T a_in and a
+    central sub-ensemble's solution), with and/or without the block-diagonal
+    preconditioner.  Precision and translation scheme of all solves are
+    options (default: mixed precision, rotation scheme)."""
     import numpy as np
     import torch
     import paper_1706_02145_amd as P
-    from celes_inputs import workload
     from concurrent.futures import ProcessPoolExecutor
     tw = time.perf_counter()
 
     def log(msg):
         print(f"[warmstart] {msg} ({time.perf_counter() - tw:.1f} s)", file=sys.stderr, flush=True)
 
+    prec = P.CELES_MIXED if a.ws_precision == "mixed" else P.CELES_FP64
+    tr = P.CELES_TRANSLATION_ROTATE if a.ws_translation == "rotate" else P.CELES_TRANSLATION_DIRECT
+    opts = dict(precision=prec, translation=tr, inner_tol=1e-3, hankel=P.CELES_HANKEL_LUT)
     net = P.Network(3, seed=11)
-    with ProcessPoolExecutor(min(16, os.cpu_count() or 1)) as ex:
-        geos = list(ex.map(_realisation, [(5001 + s, a.train_n) for s in range(a.train_slabs)]))
-    log(f"{len(geos)} training geometries")
+    ex = ProcessPoolExecutor(min(16, os.cpu_count() or 1))
+    eval_geo = ex.submit(_realisation, (5000, a.eval_n))       # generated while the training data is solved
     t0 = time.perf_counter()
-    for gi, (pos, rad) in enumerate(geos):
-        q = P.Problem(pos, rad, 1.52, 1.0, 550.0, 3, tol=1e-6, hankel=P.CELES_HANKEL_LUT)
+    n_train = 0
+    for gi, (pos, rad) in enumerate(ex.map(_realisation, [(5001 + s, a.train_n) for s in range(a.train_slabs)])):
+        q = P.Problem(pos, rad, 1.52, 1.0, 550.0, 3, tol=1e-6, restart=100, maxiter=4000, **opts)
         q.set_plane_waves([0.0], [0.0], [2])
         q.solve()
         net.add_training_problem(q)
         q.close()
-        if gi % 5 == 4:
+        n_train += len(rad)
+        if gi % 10 == 9:
             log(f"solved {gi + 1} training slabs")
     t_data = time.perf_counter() - t0
     t0 = time.perf_counter()
     loss = net.train(epochs=a.epochs, batch=2048, lr=2e-3, seed=3)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
-    log(f"trained, loss {loss:.3e}")
-    pos, rad = _realisation((5000, a.eval_n))
-    log("evaluation geometry generated")
-    p = P.Problem(pos, rad, 1.52, 1.0, 550.0, 3, tol=1e-6, hankel=P.CELES_HANKEL_LUT, restart=100, maxiter=4000,
-                  verbose=1)
+    log(f"trained on {n_train} rows, loss {loss:.3e}")
+    pos, rad = eval_geo.result()
+    ex.shutdown()
+    log(f"evaluation geometry ready (N={len(rad)})")
+    p = P.Problem(pos, rad, 1.52, 1.0, 550.0, 3, tol=1e-6, restart=100, maxiter=6000, verbose=1, **opts)
     p.set_plane_waves([0.0], [0.0], [2])
-    a_in = p.incident()
-    # single-scattering guess T a_in (per-sphere Mie coefficients from the library)
-    tq = np.stack([P.mie_coefficients(3, 2 * np.pi / 550.0 * r, 1.52) for r in rad])   # [N][2][L]
-    ls = [l for t in (0, 1) for l in range(1, 4) for m in range(-l, l + 1)]
-    ts = [t for t in (0, 1) for l in range(1, 4) for m in range(-l, l + 1)]
-    tvec = tq[:, ts, [l - 1 for l in ls]]
-    rhs = tvec * a_in[0]
     t1 = time.perf_counter()
     x_net = net.predict(p)
     t_pred = time.perf_counter() - t1
-    # sub-ensemble guess (Section 4.2): the spheres within a.sub_radius of
-    # the slab's axis solved alone (block-diagonal preconditioner)
-    sub = np.nonzero(np.hypot(pos[:, 0], pos[:, 1]) < a.sub_radius)[0]
-    t1 = time.perf_counter()
-    x_sub, sub_info = p.subsystem_guess(sub, cuboid_edge=a.cuboid_edge)
-    t_sub = time.perf_counter() - t1
-    log(f"sub-ensemble guess: {sub.size} spheres, {sub_info['iterations']} iterations, {t_sub:.2f} s")
-    guesses = {"zero": None, "T_a_in": rhs[None], "network": x_net[None], "subsystem": x_sub}
-
-    def initial_residual(x0):
-        # || T a_in - M x0 || / || T a_in ||, M x0 by the FP64 mat-vec
-        if x0 is None:
-            return 1.0
-        xd = torch.from_numpy(np.ascontiguousarray(x0[0])).to("cuda")
-        yd = torch.empty_like(xd)
-        p.apply_M(xd, yd, P.CELES_FP64)
-        torch.cuda.synchronize()
-        return float(np.linalg.norm(rhs - yd.cpu().numpy()) / np.linalg.norm(rhs))
-
+    guesses = {"zero": None, "network": x_net[None]}
+    names = [g for g in a.ws_guesses.split(",") if g]
+    if "T_a_in" in names:
+        a_in = p.incident()
+        tq = np.stack([P.mie_coefficients(3, 2 * np.pi / 550.0 * r, 1.52) for r in rad])   # [N][2][L]
+        ls = [l for t in (0, 1) for l in range(1, 4) for m in range(-l, l + 1)]
+        ts = [t for t in (0, 1) for l in range(1, 4) for m in range(-l, l + 1)]
+        guesses["T_a_in"] = (tq[:, ts, [l - 1 for l in ls]] * a_in[0])[None]
+    if "subsystem" in names:
+        sub = np.nonzero(np.hypot(pos[:, 0], pos[:, 1]) < a.sub_radius)[0]
+        t1 = time.perf_counter()
+        x_sub, sub_info = p.subsystem_guess(sub, cuboid_edge=a.cuboid_edge)
+        log(f"sub-ensemble guess: {sub.size} spheres, {sub_info['iterations']} iterations")
+        guesses["subsystem"] = x_sub
     res = {}
-    for pre in (False, True):
+    for pre in [v == "1" for v in a.ws_precond.split(",")]:
         if pre:
-            p.build_preconditioner(a.cuboid_edge)
-            log("preconditioner built")
-        for name, x0 in guesses.items():
+            t1 = time.perf_counter()
+            info_pre = p.build_preconditioner(a.cuboid_edge)
+            log(f"preconditioner {info_pre} in {time.perf_counter() - t1:.1f} s")
+        else:
+            p.build_preconditioner(0.0)
+        for name in names:
+            x0 = guesses[name]
             torch.cuda.synchronize()
             t1 = time.perf_counter()
             _, info = p.solve(x0=x0)
             dt = time.perf_counter() - t1
             key = name + ("_preconditioned" if pre else "")
             res[key] = {"iterations": info["iterations"], "seconds": dt, "x0_used": info["x0_used"],
-                        "rel_residual": info["rel_residual"], "initial_rel_residual": initial_residual(x0)}
-            log(f"x0 = {key}: {info['iterations']} iterations, {dt:.2f} s, "
-                f"initial residual {res[key]['initial_rel_residual']:.3f}")
-    res["network"]["predict_seconds"] = t_pred
-    res["subsystem"].update({"guess_seconds": t_sub, "spheres": int(sub.size), "guess_iterations": sub_info["iterations"]})
+                        "initial_rel_residual": info["x0_residual"], "rel_residual": info["rel_residual"],
+                        "refinements": info["refinements"]}
+            log(f"x0 = {key}: {info['iterations']} iterations, {dt:.2f} s, initial residual "
+                f"{info['x0_residual']:.3f}")
+    gains = {}
+    for key in res:
+        if key.startswith("network"):
+            z = res[key.replace("network", "zero")]
+            gains[key] = {"iterations_saved": z["iterations"] - res[key]["iterations"],
+                          "fraction_saved": 1 - res[key]["iterations"] / z["iterations"],
+                          "time_ratio": res[key]["seconds"] / z["seconds"]}
     print(json.dumps({
         "metric": "GMRES iterations and time to residual 1e-6 with a learned initial guess",
-        "guess_comparators": "zero, T a_in (single scattering), sub-ensemble solution",
-        "value": res["network"]["seconds"], "unit": "s", "higher_is_better": False, "n_gpus": 1,
-        "dtype": "f64 solve, bf16/f32 network", "data": "synthetic",
+        "value": res[[k for k in res if k.startswith("network")][0]]["seconds"], "unit": "s",
+        "higher_is_better": False, "n_gpus": 1,
+        "dtype": f"{a.ws_precision} solve ({a.ws_translation} scheme), bf16/f32 network", "data": "synthetic",
         "config": {"workload": f"train {a.train_slabs} slabs N={a.train_n}, evaluate N={a.eval_n}, lmax 3, "
-                               f"vf 0.3, t=2 um, normal incidence x-pol, LUT 1 nm, restart 100; "
-                               f"without and with the block-diagonal preconditioner (edge {a.cuboid_edge:g} nm)"},
-        "results": res, "training_loss": loss, "training_rows": a.train_slabs * a.train_n,
-        "data_generation_seconds": t_data, "training_seconds": t_train}))
+                               f"vf 0.3, t=2 um, normal incidence x-pol, LUT 1 nm, restart 100, "
+                               f"preconditioner edge {a.cuboid_edge:g} nm where used"},
+        "results": res, "gains": gains, "training_loss": loss, "training_rows": n_train,
+        "predict_seconds": t_pred, "data_generation_seconds": t_data, "training_seconds": t_train}))
 
 
 def translation_mode(a):
@@ -811,14 +815,18 @@ def main():
     ap.add_argument("--batch-restart", type=int, default=150)
     ap.add_argument("--batch-precond", type=float, default=0.0,
                     help="batched mode: block-diagonal preconditioner cuboid edge (nm) for every problem, 0 = none")
-    ap.add_argument("--train-slabs", type=int, default=40)
-    ap.add_argument("--train-n", type=int, default=2000)
-    ap.add_argument("--eval-n", type=int, default=20000)
+    ap.add_argument("--train-slabs", type=int, default=200)
+    ap.add_argument("--train-n", type=int, default=5000)
+    ap.add_argument("--eval-n", type=int, default=100000)
     ap.add_argument("--epochs", type=int, default=40)
     ap.add_argument("--large-cuboid", type=int, default=50,
                     help="large mode: spheres per preconditioner cuboid (0: no preconditioned run)")
     ap.add_argument("--scaling-vfs", default="0.1,0.3,0.5", help="scaling mode: volume fractions")
     ap.add_argument("--sub-radius", type=float, default=5000.0, help="warmstart: sub-ensemble radius (nm)")
+    ap.add_argument("--ws-precision", choices=["mixed", "fp64"], default="mixed")
+    ap.add_argument("--ws-translation", choices=["rotate", "direct"], default="rotate")
+    ap.add_argument("--ws-guesses", default="zero,network", help="warmstart: zero,network,T_a_in,subsystem")
+    ap.add_argument("--ws-precond", default="0,1", help="warmstart: runs without (0) and with (1) preconditioner")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",

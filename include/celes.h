@@ -110,7 +110,10 @@ typedef struct celes_solve_info {
     double rel_residual;    /* final true relative residual, evaluated in FP64                 */
     double seconds;         /* wall time of the solve (excludes preconditioner set-up)         */
     double matvec_seconds;  /* part of `seconds` spent in the coupling mat-vec kernels         */
-    int x0_used;            /* 1 if the given initial guess was kept (its residual < ||rhs||)  */
+    int x0_used;            /* 1 if the given initial guess was used (see celes_solve)         */
+    double x0_residual;     /* relative residual ||T a_in - M x0|| / ||T a_in|| of the initial
+                             * iterate actually used (after its weighting; 1 for x0 = 0),
+                             * largest over the right-hand sides                              */
 } celes_solve_info;
 
 /* Fill *opt with defaults: FP64, LUT, lut_dr = 1, tol = 1e-8, inner_tol = 1e-4,
@@ -227,8 +230,11 @@ int celes_apply_preconditioner(celes_handle* h, int precision, const void* x_dev
  * maxiter counts BiCGSTAB iterations.  With CELES_MIXED the complex64
  * correction solves use the chosen solver.  x0 [K][N][nmax]
  * complex128 is the initial guess (NULL: zero; the custom initial condition
- * of Section 4.2): it is kept only if its relative residual is below 1,
- * otherwise the solve starts from zero (info->x0_used tells which).  b_out [K][N][nmax]
+ * of Section 4.2): per right-hand side it is multiplied by the complex weight
+ * alpha = (M x0)^H rhs / ||M x0||^2 that minimises the residual of alpha x0
+ * (one FP64 mat-vec; alpha = 1 when x0 is the solution) and used if that
+ * residual is below ||rhs||, otherwise the solve starts from zero
+ * (info->x0_used tells which, info->x0_residual the residual it starts from).  b_out [K][N][nmax]
  * receives the scattered-field coefficients (may be NULL: kept internally
  * for celes_cross_sections / celes_far_field).  info may be NULL.
  * Returns CELES_OK, CELES_E_NOCONV (b_out holds the best iterate),
@@ -438,7 +444,10 @@ int celes_batch_solve(celes_batch* b, celes_solve_info* infos, celes_solve_info*
  * position/lambda, R_j/lambda and a_in^j in sphere i's frame.
  * Layers: in_pad -> 128 -> 128 -> 128 -> out_pad, SiLU, bf16 weights and
  * activations with FP32 accumulation, FP32 master weights, Adam.  It is
- * trained on coefficients the solver produced.  Intended for training sets
+ * trained on coefficients the solver produced: its output is the
+ * multiple-scattering correction b^i - T^i a_in^i to the single-scattering
+ * response (in the sphere's frame), so an untrained or uninformed network
+ * falls back to single scattering.  Intended for training sets
  * and problems of one lmax; only the first right-hand side is used.
  * ------------------------------------------------------------------------- */
 typedef struct celes_nn celes_nn;
@@ -461,7 +470,8 @@ int celes_nn_get_params(const celes_nn* net, float* params);
 int celes_nn_set_params(celes_nn* net, const float* params);
 
 /* Features X [N][in_pad] (as the network sees them, bf16 values) and, if the
- * problem is solved, targets Y [N][out_pad] of a problem.  Either may be
+ * problem is solved, targets Y [N][out_pad] (b - T a_in in the sphere's
+ * frame, divided by ||a_in^i||) of a problem.  Either may be
  * NULL.  Errors: CELES_E_ARG, CELES_E_STATE. */
 int celes_nn_features(celes_nn* net, celes_handle* h, float* X, float* Y);
 
@@ -483,7 +493,8 @@ int celes_nn_add_training_problem(celes_nn* net, celes_handle* h);
 int celes_nn_train(celes_nn* net, int epochs, int batch, double lr, uint64_t seed, double* loss);
 
 /* Predicted scattered coefficients x0 [N][nmax] complex128 of a problem's
- * first right-hand side (pass to celes_solve as x0).  Errors: CELES_E_ARG,
+ * first right-hand side, T a_in plus the predicted correction (pass to
+ * celes_solve as x0).  Errors: CELES_E_ARG,
  * CELES_E_STATE, CELES_E_OOM, CELES_E_DEVICE. */
 int celes_nn_predict(celes_nn* net, celes_handle* h, double* x0);
 

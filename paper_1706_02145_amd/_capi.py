@@ -30,7 +30,7 @@ class Options(C.Structure):
 class SolveInfo(C.Structure):
     _fields_ = [("status", C.c_int), ("iterations", C.c_int), ("refinements", C.c_int), ("matvecs", C.c_int),
                 ("rel_residual", C.c_double), ("seconds", C.c_double), ("matvec_seconds", C.c_double),
-                ("x0_used", C.c_int)]
+                ("x0_used", C.c_int), ("x0_residual", C.c_double)]
 
 
 _dp = C.POINTER(C.c_double)

@@ -1251,19 +1251,40 @@ static int celes_solve_impl(celes_handle* h, const double* x0, double* b_out, ce
         HIPCHK(h, hipMemcpy(drhs, rhs.data(), n * sizeof(cx<double>), hipMemcpyHostToDevice));
         HIPCHK(h, hipMemcpy(dx, x.data(), n * sizeof(cx<double>), hipMemcpyHostToDevice));
         double final_res = 0;
+        double x0_res = 1.0;
         if (x0 && rn > 0) {
-            // an initial guess is only used if it beats x0 = 0 (residual below ||rhs||)
+            // The initial guess enters with the complex weight alpha that
+            // minimises ||rhs - alpha M x0|| (one FP64 mat-vec): alpha =
+            // (M x0)^H rhs / ||M x0||^2, residual^2 = ||rhs||^2 - |(M x0)^H
+            // rhs|^2 / ||M x0||^2 <= ||rhs||^2.  It is used if that beats
+            // x0 = 0; alpha = 1 for a guess that is already the solution.
             double mv = 0;
             int rc0 = CELES_OK;
-            const double r0 = residual64(h, drhs, dx, h->d_r.as<cx<double>>(), s, &rc0, &mv) / rn;
+            (void)residual64(h, drhs, dx, h->d_r.as<cx<double>>(), s, &rc0, &mv);   // d_w = M x0
             inf.matvecs++;
             if (rc0 != CELES_OK) return rc0;
-            if (!(r0 < 1.0)) {
-                HIPCHK(h, hipMemset(dx, 0, n * sizeof(cx<double>)));
-            } else {
+            cx<double> d1, d2;
+            const cx<double>* mx = h->d_w.as<cx<double>>();
+            celes::vec_dots<double>(mx, 0, 1, drhs, n, h->d_partial.as<cx<double>>(), h->d_h.as<cx<double>>(), s);
+            HIPCHK(h, hipMemcpyAsync(&d1, h->d_h.p, sizeof(d1), hipMemcpyDeviceToHost, s));
+            celes::vec_dots<double>(mx, 0, 1, mx, n, h->d_partial.as<cx<double>>(), h->d_h.as<cx<double>>(), s);
+            HIPCHK(h, hipMemcpyAsync(&d2, h->d_h.p, sizeof(d2), hipMemcpyDeviceToHost, s));
+            HIPCHK(h, hipStreamSynchronize(s));
+            const double proj = d2.re > 0 ? (d1.re * d1.re + d1.im * d1.im) / d2.re : 0.0;
+            if (std::isfinite(proj) && proj > 0) {
+                const cplx alpha = cplx(d1.re, d1.im) / d2.re;
+                for (auto& v : x) {
+                    const cplx z = alpha * cplx(v.re, v.im);
+                    v = {z.real(), z.imag()};
+                }
+                HIPCHK(h, hipMemcpy(dx, x.data(), n * sizeof(cx<double>), hipMemcpyHostToDevice));
                 inf.x0_used = 1;
+                x0_res = std::sqrt(std::max(0.0, rn * rn - proj)) / rn;
+            } else {
+                HIPCHK(h, hipMemset(dx, 0, n * sizeof(cx<double>)));
             }
         }
+        inf.x0_residual = std::max(inf.x0_residual, x0_res);
         if (rn == 0) {
             HIPCHK(h, hipMemset(dx, 0, n * sizeof(cx<double>)));
         } else if (!mixed) {
@@ -2484,6 +2505,7 @@ static int celes_batch_solve_impl(celes_batch* b, celes_solve_info* infos, celes
             infos[sy].iterations = its[sy];
             infos[sy].refinements = refinements;
             infos[sy].rel_residual = res[sy];
+            infos[sy].x0_residual = 1.0;        // batches start from zero
         }
     }
     if (summary) {
@@ -2493,6 +2515,7 @@ static int celes_batch_solve_impl(celes_batch* b, celes_solve_info* infos, celes
         summary->refinements = refinements;
         summary->matvecs = matvecs;
         summary->rel_residual = worst;
+        summary->x0_residual = 1.0;
         summary->seconds = std::chrono::duration<double>(t1 - t0).count();
     }
     if (status == CELES_E_NOCONV) b->err = "batched solve did not reach the tolerance";

@@ -428,6 +428,16 @@ double nn_backward(celes_nn* n, const unsigned short* X, const float* Y, int64_t
     return loss / ((double)Mvalid * n->out_dim);
 }
 
+// (T a_in)[e] of the first right-hand side: Mie coefficient Q_{tau l} of the
+// sphere times the incident coefficient, entry e = i nmax + tau half + c
+static celes::cplx single_scattering(const celes_handle* h, int64_t e) {
+    const int64_t i = e / h->nmax;
+    const int r = (int)(e % h->nmax), tau = r / h->half, c = r % h->half;
+    int l = 1;
+    while (l * (l + 2) < c + 1) ++l;
+    return h->tq[((size_t)i * 2 + tau) * h->L + (l - 1)] * h->a_in[e];
+}
+
 int nn_features(celes_nn* n, celes_handle* h, int64_t row0, unsigned short* X, float* Y, celes::DevBuf& frame,
                 celes::DevBuf& nbr, bool with_targets) {
     if (h->K < 1) return nn_fail(n, CELES_E_STATE, "problem without incident field");
@@ -454,8 +464,13 @@ int nn_features(celes_nn* n, celes_handle* h, int64_t row0, unsigned short* X, f
     hipMemcpy(dain.p, a.data(), a.size() * 16, hipMemcpyHostToDevice);
     hipMemcpy(drad.p, h->radius.data(), N * 8, hipMemcpyHostToDevice);
     if (with_targets) {
+        // the network learns the multiple-scattering correction b - T a_in
+        // to the single-scattering response (celes_nn_predict adds T a_in back)
         bb.resize(N * h->nmax);
-        for (int64_t i = 0; i < N * h->nmax; ++i) bb[i] = {h->b[i].real(), h->b[i].imag()};
+        for (int64_t i = 0; i < N * h->nmax; ++i) {
+            const celes::cplx v = h->b[i] - single_scattering(h, i);
+            bb[i] = {v.real(), v.imag()};
+        }
         if (!db.ensure(bb.size() * 16)) return nn_fail(n, CELES_E_OOM, "feature buffers");
         hipMemcpy(db.p, bb.data(), bb.size() * 16, hipMemcpyHostToDevice);
     }
@@ -730,6 +745,11 @@ static int celes_nn_predict_impl(celes_nn* n, celes_handle* h, double* x0_out) {
     hipLaunchKernelGGL(unframe, dim3(nb(N * h->nmax)), dim3(256), 0, 0, n->Z[NN_LAYERS - 1].as<float>(), n->out_pad,
                        fr.as<cx<double>>(), (int)N, h->nmax, x0.as<cx<double>>());
     if (hipMemcpy(x0_out, x0.p, N * h->nmax * 16, hipMemcpyDeviceToHost) != hipSuccess) return CELES_E_DEVICE;
+    for (int64_t e = 0; e < N * h->nmax; ++e) {      // predicted correction + single scattering
+        const celes::cplx t = single_scattering(h, e);
+        x0_out[2 * e] += t.real();
+        x0_out[2 * e + 1] += t.imag();
+    }
     return CELES_OK;
 }
 int celes_nn_predict(celes_nn* n, celes_handle* h, double* x0_out) {
