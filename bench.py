@@ -721,7 +721,7 @@ def warmstart_mode(a):
                 f"{info['x0_residual']:.3f}")
     gains = {}
     for key in res:
-        if key.startswith("network"):
+        if key.startswith("network") and key.replace("network", "zero") in res:
             z = res[key.replace("network", "zero")]
             gains[key] = {"iterations_saved": z["iterations"] - res[key]["iterations"],
                           "fraction_saved": 1 - res[key]["iterations"] / z["iterations"],

@@ -281,10 +281,14 @@ __global__ void __launch_bounds__(PA_ROWS) apply_tiles(const cx<TM>* __restrict_
     dst[r] = {(double)((re[0] + re[1]) + (re[2] + re[3])), (double)((im[0] + im[1]) + (im[2] + im[3]))};
 }
 
+// grid-stride: the inverses can hold more than 2^32 entries, more work-items
+// than one dispatch can address (its grid size is a 32-bit work-item count)
 __global__ void narrow_kernel(const cx<double>* __restrict__ a, cx<float>* __restrict__ b, int64_t n) {
-    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (t < n) b[t] = {(float)a[t].re, (float)a[t].im};
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += stride)
+        b[t] = {(float)a[t].re, (float)a[t].im};
 }
+constexpr unsigned NARROW_BLOCKS = 16384;   // 4M work-items per launch
 
 // out[perm[t / nmax] nmax + t % nmax] = sum_s part[s][t], t in permuted order
 template <typename T>
@@ -457,8 +461,8 @@ int BlockPrecond::build(int64_t N, int L, const double* pos, double k, const cpl
             *msg = "cannot allocate the complex64 preconditioner copy";
             rc = CELES_E_OOM_INTERNAL;
         } else {
-            hipLaunchKernelGGL(narrow_kernel, dim3((unsigned)((mat_elems_ + 255) / 256)), dim3(256), 0, 0, d_inv_,
-                               d_inv32_, (int64_t)mat_elems_);
+            const unsigned blocks = (unsigned)std::min<size_t>(NARROW_BLOCKS, (mat_elems_ + 255) / 256);
+            hipLaunchKernelGGL(narrow_kernel, dim3(blocks), dim3(256), 0, 0, d_inv_, d_inv32_, (int64_t)mat_elems_);
         }
     }
     hipDeviceSynchronize();

@@ -76,3 +76,27 @@ def test_single_cuboid_preconditioner_is_the_exact_inverse():
     from tests.gpu_helpers import oracle_incident
     bref = solve_dense(M, t * oracle_incident(w).reshape(-1)).reshape(w.N, -1)
     assert rel(b[0], bref) <= 1e-10
+
+
+@pytest.mark.timeout(400)
+def test_complex64_copy_beyond_2_to_32_entries():
+    # Regression: the complex64 copy of the inverses was written by a launch
+    # with one work-item per entry; above 2^32 entries that exceeds what one
+    # dispatch can address and most cuboids kept zero inverses.  The budgeted
+    # edge for 100 spheres per cuboid on the 20,000-sphere slab gives 5.4e9
+    # entries: every cuboid of the complex64 apply must match the FP64 apply.
+    w = workload("slab20000_l4")
+    p = make_problem(w, hankel=0, target_Nj=100.0)
+    edge, nb, by = p.build_preconditioner()
+    print(f"[precond] slab20000_l4 auto edge {edge:.0f} nm: {nb} cuboids, {by / 2**30:.1f} GiB", flush=True)
+    perm, off = partition(w.positions, edge)
+    sizes = np.diff(off).astype(np.float64)
+    assert float(np.sum((sizes * w.nmax) ** 2)) > 2.0 ** 32
+    x = random_coefficients(13, 1, w.N, w.nmax)[0]
+    y64 = _apply(p, x, P.CELES_FP64)
+    y32 = _apply(p, x, P.CELES_MIXED)
+    # per cuboid: the last cuboids are the ones a wrapped launch would miss
+    for j in (0, nb // 2, nb - 1):
+        sph = perm[off[j]:off[j + 1]]
+        assert rel(y32[sph], y64[sph]) <= 1e-5, j
+    assert rel(y32, y64) <= 1e-5
