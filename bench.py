@@ -801,6 +801,8 @@ def main():
                     help="preconditioner cuboid edge in nm (-1: budgeted automatic edge, 0: none)")
     ap.add_argument("--hankel", choices=["lut", "direct"], default="lut")
     ap.add_argument("--profile", action="store_true", help="mat-vec launches only (for rocprofv3)")
+    ap.add_argument("--profile-scheme", choices=["direct", "rotate"], default="direct",
+                    help="profile mode: translation scheme of the timed mat-vecs")
     ap.add_argument("--translation-lmax", default="1,2,3,4,5,6", help="translation mode: cut-offs")
     ap.add_argument("--mode", choices=["solve", "batched", "warmstart", "mixed", "paper", "scaling", "validation",
                                        "large", "translation"],
@@ -881,6 +883,8 @@ def main():
     t0 = time.perf_counter()
     p = problem(w, restart=100, maxiter=3000)
     t_setup = time.perf_counter() - t0
+    if a.profile and a.profile_scheme == "rotate":
+        p.set_solve_options(translation=P.CELES_TRANSLATION_ROTATE)
     stream = torch.cuda.current_stream()
     x = torch.from_numpy(random_coefficients(1, 1, N, nm)[0]).to("cuda")
     y = torch.empty_like(x)
