@@ -122,25 +122,26 @@ def _delta_pi2(l, k, m):
 def flops_per_pair_rotate(L, hankel_lut=True, executed=False):
     """Flops per sphere pair of the rotation-translation-rotation mat-vec
     (one right-hand side; counting as in flops_per_pair): geometry, Hankel
-    orders and the powers of q and e^{i theta} once, the axial A_z, B_z sums
-    once (executed: once per polarisation pass), and per pass the two
-    rotations (phases and two constant d(pi/2) products each way) and the
-    axial translation."""
+    orders and the powers of q and e^{i theta} once; the axial A_z, B_z sums
+    for m >= 0 once (executed: once per polarisation pass); per pass the two
+    rotations (phases, sum/difference pairs, the two constant d(pi/2)
+    products over m >= 0 or k >= 0) and the axial translation for +-m."""
     P = 2 * L
     f = 19 + ((4 + 24 + 1 + 5 * (P - 1)) if hankel_lut else (4 + 6 + 5 * (P - 1))) + 12 * (L - 1)
-    nz = {l: sum(1 for k in range(-l, l + 1) for m in range(-l, l + 1) if _delta_pi2(l, k, m) != 0)
-          for l in range(1, L + 1)}
+    # nonzero d(pi/2) entries over one half (the other half follows by symmetry)
+    nzh = {l: sum(1 for k in range(-l, l + 1) for m in range(0, l + 1) if _delta_pi2(l, k, m) != 0)
+           for l in range(1, L + 1)}
     sums = 0
     per_pass = 0
     for l in range(1, L + 1):
-        per_pass += 12 * l + 4 * nz[l] + 12 * l + 4 * nz[l]            # rotate in
-        per_pass += 4 * nz[l] + 12 * l + 4 * nz[l] + 2 + 16 * l         # rotate out + accumulate
-        for m in range(-l, l + 1):
-            for lp in range(max(1, abs(m)), L + 1):
+        rot = 8 * l + 4 * nzh[l] + 12 * l + 8 * l + 4 * nzh[l]          # S/D, Delta, phase, P/Q, Delta^T
+        per_pass += 12 * l + rot                                        # rotate in (source phases + rotation)
+        per_pass += rot + 2 + 16 * l                                    # rotate out + accumulate
+        for m in range(0, l + 1):
+            for lp in range(max(1, m), L + 1):
                 # A terms: |l-l'| <= p <= l+l', l+l'+p even; B terms: |l-l'|+1 <= p <= l+l'-1, odd
-                nt = (min(l, lp) + 1) + min(l, lp)
-                sums += 4 * nt
-                per_pass += 4 + 8                                       # A +- iB, multiply-accumulate
+                sums += 4 * ((min(l, lp) + 1) + min(l, lp))
+                per_pass += (4 + 8) * (2 if m > 0 else 1)               # A +- iB, multiply-accumulate
     return f + 2 * per_pass + (2 * sums if executed else sums)
 
 

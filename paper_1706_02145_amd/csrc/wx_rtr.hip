@@ -74,36 +74,61 @@ constexpr double zb(int lp, int l, int m, int p) { return cb5im(lp, m, l, m, p) 
 
 constexpr int off(int l, int m) { return l * (l + 1) + m - 1; }
 
-// g = Delta^l u (rows k, columns m), constant real matrix on complex vectors
+// g = Delta^l u (rows k, columns m), constant real matrix on complex
+// vectors.  Delta_{k,-m} = (-1)^{l+k} Delta_{k,m}, so with S_m = u_m + u_{-m}
+// and D_m = u_m - u_{-m} each output sums over m >= 0 only:
+//   g_k = Delta_{k0} u_0 + sum_{m>0} Delta_{km} (l+k even ? S_m : D_m)
 template <typename T, int l>
 __device__ __forceinline__ void delta_mul(const cx<T> (&u)[2 * l + 1], cx<T> (&g)[2 * l + 1]) {
+    cx<T> S[l + 1], D[l + 1];
+    sfor<1, l + 1>([&](auto M_) {
+        constexpr int m = decltype(M_)::value;
+        S[m] = {u[l + m].re + u[l - m].re, u[l + m].im + u[l - m].im};
+        D[m] = {u[l + m].re - u[l - m].re, u[l + m].im - u[l - m].im};
+    });
     sfor<-l, l + 1>([&](auto K_) {
         constexpr int k = decltype(K_)::value;
+        constexpr bool even = ((l + k) & 1) == 0;
         cx<T> acc = {0, 0};
-        sfor<-l, l + 1>([&](auto M_) {
+        constexpr double c0 = delta(l, k, 0);
+        if constexpr (c0 != 0.0) acc = {(T)c0 * u[l].re, (T)c0 * u[l].im};
+        sfor<1, l + 1>([&](auto M_) {
             constexpr int m = decltype(M_)::value;
             constexpr double c = delta(l, k, m);
             if constexpr (c != 0.0) {
-                acc.re = fma((T)c, u[m + l].re, acc.re);
-                acc.im = fma((T)c, u[m + l].im, acc.im);
+                const cx<T>& v = even ? S[m] : D[m];
+                acc.re = fma((T)c, v.re, acc.re);
+                acc.im = fma((T)c, v.im, acc.im);
             }
         });
         g[k + l] = acc;
     });
 }
 
-// w = Delta^T g
+// w = Delta^T g.  Delta_{-k,m} = (-1)^{l+m} Delta_{k,m}, so with
+// P_k = g_k + g_{-k} and Q_k = g_k - g_{-k}:
+//   w_m = Delta_{0m} g_0 + sum_{k>0} Delta_{km} (l+m even ? P_k : Q_k)
 template <typename T, int l>
 __device__ __forceinline__ void delta_tmul(const cx<T> (&g)[2 * l + 1], cx<T> (&w)[2 * l + 1]) {
+    cx<T> Pk[l + 1], Qk[l + 1];
+    sfor<1, l + 1>([&](auto K_) {
+        constexpr int k = decltype(K_)::value;
+        Pk[k] = {g[l + k].re + g[l - k].re, g[l + k].im + g[l - k].im};
+        Qk[k] = {g[l + k].re - g[l - k].re, g[l + k].im - g[l - k].im};
+    });
     sfor<-l, l + 1>([&](auto M_) {
         constexpr int m = decltype(M_)::value;
+        constexpr bool even = ((l + m) & 1) == 0;
         cx<T> acc = {0, 0};
-        sfor<-l, l + 1>([&](auto K_) {
+        constexpr double c0 = delta(l, 0, m);
+        if constexpr (c0 != 0.0) acc = {(T)c0 * g[l].re, (T)c0 * g[l].im};
+        sfor<1, l + 1>([&](auto K_) {
             constexpr int k = decltype(K_)::value;
             constexpr double c = delta(l, k, m);
             if constexpr (c != 0.0) {
-                acc.re = fma((T)c, g[k + l].re, acc.re);
-                acc.im = fma((T)c, g[k + l].im, acc.im);
+                const cx<T>& v = even ? Pk[k] : Qk[k];
+                acc.re = fma((T)c, v.re, acc.re);
+                acc.im = fma((T)c, v.im, acc.im);
             }
         });
         w[m + l] = acc;
@@ -169,11 +194,12 @@ __device__ __forceinline__ void rtr_pair(const cx<T>* __restrict__ v, const cx<T
     sfor<1, L + 1>([&](auto L_) {
         constexpr int l = decltype(L_)::value;
         cx<T> z[2 * l + 1], g[2 * l + 1], w[2 * l + 1];
-        sfor<-l, l + 1>([&](auto M_) {
+        // A_z is even and B_z odd under m -> -m (Appendix A.2 mirror
+        // symmetry): one pair of p sums serves m and -m
+        sfor<0, l + 1>([&](auto M_) {
             constexpr int m = decltype(M_)::value;
-            constexpr int am = m < 0 ? -m : m;
-            cx<T> acc = {0, 0};
-            sfor<(am > 1 ? am : 1), L + 1>([&](auto LQ_) {
+            cx<T> accp = {0, 0}, accm = {0, 0};
+            sfor<(m > 1 ? m : 1), L + 1>([&](auto LQ_) {
                 constexpr int lp = decltype(LQ_)::value;
                 // A_z and B_z entry (source (lp, m), receiver (l, m))
                 cx<T> A = {0, 0}, B = {0, 0};
@@ -189,13 +215,19 @@ __device__ __forceinline__ void rtr_pair(const cx<T>* __restrict__ v, const cx<T
                         B.im = fma((T)cb, h[p].im, B.im);
                     }
                 });
-                // coefficient A +- iB, with the (-1)^m of the two rotations' unit factors
-                constexpr T sg = (T)(SG * ((am & 1) ? -1 : 1));
-                constexpr T sa = (T)((am & 1) ? -1 : 1);
-                const cx<T> cf = {sa * A.re - sg * B.im, sa * A.im + sg * B.re};
-                cfma(acc, cf, t.get(off(lp, m)));
+                // coefficients (-1)^m (A +- iB) for +m and (-1)^m (A -+ iB) for -m:
+                // the (-1)^m is the two rotations' unit factors
+                constexpr T sa = (T)((m & 1) ? -1 : 1);
+                constexpr T sg = (T)SG * sa;
+                const cx<T> cp = {sa * A.re - sg * B.im, sa * A.im + sg * B.re};
+                cfma(accp, cp, t.get(off(lp, m)));
+                if constexpr (m > 0) {
+                    const cx<T> cm = {sa * A.re + sg * B.im, sa * A.im - sg * B.re};
+                    cfma(accm, cm, t.get(off(lp, -m)));
+                }
             });
-            z[m + l] = acc;
+            z[l + m] = accp;
+            if constexpr (m > 0) z[l - m] = accm;
         });
         delta_mul<T, l>(z, g);
         theta_phase<T, l, L>(g, ep);
