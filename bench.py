@@ -291,7 +291,12 @@ def batched_mode(a):
     big_ms = ev0.elapsed_time(ev1) / 3
     big_pairs = big.N * (big.N - 1)
     apply_flops = 4 * big.nmax ** 2 * big.num_rhs * big_pairs      # (A+-B) block products, all RHS
-    log(f"64-RHS slab W x: {big_ms:.1f} ms")
+    log(f"64-RHS slab W x: {big_ms:.1f} ms (kernel {big_kernel_ms:.1f} ms)")
+    if a.batch_no_solve:
+        print(json.dumps({"batched_matvec_ms": mv_ms, "big_matvec_ms": big_ms, "big_kernel_ms": big_kernel_ms,
+                          "big_kernel_tflops": apply_flops / (big_kernel_ms * 1e-3) / 1e12,
+                          "frac": apply_flops / (big_kernel_ms * 1e-3) / 1e12 / PEAK_FP32_MFMA_TFLOPS}))
+        return
     t1 = time.perf_counter()
     per, summ = bt.solve(check=False)
     log("solve done")
@@ -816,6 +821,7 @@ def main():
     ap.add_argument("--batch-tol", type=float, default=1e-6)
     ap.add_argument("--batch-maxiter", type=int, default=600)
     ap.add_argument("--batch-restart", type=int, default=150)
+    ap.add_argument("--batch-no-solve", action="store_true", help="batched mode: mat-vec timings only")
     ap.add_argument("--batch-precond", type=float, default=0.0,
                     help="batched mode: block-diagonal preconditioner cuboid edge (nm) for every problem, 0 = none")
     ap.add_argument("--train-slabs", type=int, default=200)

@@ -55,7 +55,10 @@ namespace celes {
 // (r / 16) 64 KS + (r % 16) KS + 16 KS (c % 4) + c / 4.
 void wx_mfma_records(int L, std::vector<float>* rec) {
     const int half = L * (L + 2), hs = 4 * L + 1, ta = L + 1, tb = L;
-    const int R = (2 * half + 15) / 16 * 16, KS = R / 4;
+    // lmax 3 uses the three-product form: complex order 15 padded to 16, one
+    // offset per entry (the same in the Re, Im and Re + Im matrices)
+    const bool g3 = L == 3;
+    const int R = g3 ? 16 : (2 * half + 15) / 16 * 16, KS = R / 4;
     rec->clear();
     auto F = [&](int r) { return (r / 16) * 64 * KS + (r % 16) * KS; };
     auto G = [&](int c) { return 16 * KS * (c % 4) + c / 4; };
@@ -65,6 +68,11 @@ void wx_mfma_records(int L, std::vector<float>* rec) {
         return f;
     };
     auto pos = [&](int n, int np, float* w) {
+        if (g3) {
+            w[0] = as_float(F(n) + G(np));
+            w[1] = as_float(0);
+            return;
+        }
         w[0] = as_float(F(n) + G(np) | (F(n + half) + G(np + half)) << 16);
         w[1] = as_float(F(n) + G(np + half) | (F(n + half) + G(np)) << 16);
     };

@@ -44,13 +44,23 @@ __device__ __forceinline__ void mfor(F&& f) {
     }
 }
 
+// Two operand forms.  Real form: the complex HALF x HALF block as one real
+// matrix [[Re, -Im], [Im, Re]] of order R = 2 HALF (padded to 16), one
+// product with [Re x; Im x].  Three-product form (Gauss), used where the
+// complex order pads to 16 with little waste (lmax 3: HALF = 15): the three
+// real products Re(P) Re(x), Im(P) Im(x) and (Re P + Im P)(Re x + Im x) of
+// order HALF padded to 16 give Re = T1 - T2 and Im = T3 - T1 - T2 with three
+// quarters of the real-form multiplies.
 template <int L>
 struct MShape {
     static constexpr int HALF = L * (L + 2);
-    static constexpr int R = (2 * HALF + 15) / 16 * 16;   // real-form order, padded to the MFMA tile
+    static constexpr bool G3 = L == 3;                     // three-product form
+    static constexpr int NMAT = G3 ? 3 : 1;                // operand matrices per half
+    static constexpr int R = G3 ? (HALF + 15) / 16 * 16 : (2 * HALF + 15) / 16 * 16;   // matrix order
     static constexpr int MT = R / 16;                      // 16-row tiles
     static constexpr int KS = R / 4;                       // k-steps of 4
     static constexpr int KQ = KS / 4;                      // float4 groups of k-steps
+    static constexpr int MSZ = MT * 64 * KS;               // floats of one operand matrix
     static constexpr int E = HALF * HALF;                  // reduced block entries
     static constexpr int P2 = 2 * L;
     static constexpr int HS = 4 * L + 1;                   // H row stride: p = 0..4L, zero above 2L
@@ -59,7 +69,7 @@ struct MShape {
     static constexpr int EC = (E + L * L) / 2;             // records: entry pairs under the mirror
     static_assert(KS % 4 == 0, "k-steps come in float4 groups");
     static_assert(5 + TA + TB <= WXM_REC, "record too short");
-    static_assert(2 * MT * 64 * KS <= 65536, "operand offsets must fit 16 bits");
+    static_assert(NMAT * MSZ <= 65536, "operand offsets must fit 16 bits");
 };
 
 // h_p(kd), p = 0..2L, in FP32 from the FP64 distance: h_0, h_1 from the
@@ -153,22 +163,41 @@ __device__ __forceinline__ void build_entry(const EntryRec<L>& e, const cx<float
         aQ[o2] = -vq.im;
         aQ[o3] = vq.im;
     };
-    put(e.w01, e.w23, cmul(ph, Y), cmul(ph, X));
-    if ((e.head >> 30) & 1) {
-        const cx<float> phc = {ph.re, -ph.im};
-        put(e.m01, e.m23, cmul(phc, X), cmul(phc, Y));
+    if constexpr (MShape<L>::G3) {
+        // three-product form: Re, Im and Re + Im at one offset of three matrices
+        constexpr int M1 = MShape<L>::MSZ;
+        auto put3 = [&](int o, cx<float> vp, cx<float> vq) {
+            aP[o] = vp.re;
+            aP[o + M1] = vp.im;
+            aP[o + 2 * M1] = vp.re + vp.im;
+            aQ[o] = vq.re;
+            aQ[o + M1] = vq.im;
+            aQ[o + 2 * M1] = vq.re + vq.im;
+        };
+        put3(e.w01, cmul(ph, Y), cmul(ph, X));
+        if ((e.head >> 30) & 1) {
+            const cx<float> phc = {ph.re, -ph.im};
+            put3(e.m01, cmul(phc, X), cmul(phc, Y));
+        }
+    } else {
+        put(e.w01, e.w23, cmul(ph, Y), cmul(ph, X));
+        if ((e.head >> 30) & 1) {
+            const cx<float> phc = {ph.re, -ph.im};
+            put(e.m01, e.m23, cmul(phc, X), cmul(phc, Y));
+        }
     }
 }
 
 template <int L, int NT, int HMODE>
 __global__ __launch_bounds__(256) void wx_mfma_kernel(WxMfmaArgs a) {
     using S = MShape<L>;
-    constexpr int HALF = S::HALF, MT = S::MT, KS = S::KS, KQ = S::KQ, P2 = S::P2;
+    constexpr int HALF = S::HALF, MT = S::MT, KS = S::KS, KQ = S::KQ, P2 = S::P2, NMAT = S::NMAT;
     constexpr int HS = S::HS, NPH = S::NPH, EC = S::EC;
     constexpr int KN = 16 * NT;                 // right-hand sides per block
     constexpr int TS = 2;                       // sources per tile: one per half-wave in the set-up
-    constexpr int AH = MT * 64 * KS;            // floats of one real-form block (R x R)
-    constexpr int XH = NT * 64 * KS;            // floats of one source half (R x KN)
+    constexpr int AH = NMAT * S::MSZ;           // floats of one block's operand matrices (R x R each)
+    constexpr int XM = NT * 64 * KS;            // floats of one source operand matrix (R x KN)
+    constexpr int XH = NMAT * XM;               // floats of one source half
     constexpr int EPL = (EC + 63) / 64;         // records per lane
     constexpr bool REGREC = EPL <= 2;           // records live in registers (lmax <= 3)
     constexpr int HT = (P2 + 1) * HS;           // complex H entries per source
@@ -234,11 +263,11 @@ __global__ __launch_bounds__(256) void wx_mfma_kernel(WxMfmaArgs a) {
     const double yi = active ? a.py[i] : 0.0;
     const double zi = active ? a.pz[i] : 0.0;
 
-    v4f acc[2][MT][NT];
+    v4f acc[2][NMAT * MT][NT];   // [half][operand matrix x row tile][column tile]
 #pragma unroll
     for (int h = 0; h < 2; ++h)
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt)
+        for (int mt = 0; mt < NMAT * MT; ++mt)
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) acc[h][mt][nt] = v4f{0.f, 0.f, 0.f, 0.f};
 
@@ -319,39 +348,43 @@ __global__ __launch_bounds__(256) void wx_mfma_kernel(WxMfmaArgs a) {
             }
             __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
             __builtin_amdgcn_wave_barrier();
-            // ---- block products on the matrix cores ----
+            // ---- block products on the matrix cores: operand matrix mm of
+            // the block against operand matrix mm of the source half ----
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
-                const float* ab = sa + h * AH + lane * KS;
-                float af[MT][KS];
 #pragma unroll
-                for (int mt = 0; mt < MT; ++mt)
+                for (int mm = 0; mm < NMAT; ++mm) {
+                    const float* ab = sa + h * AH + mm * S::MSZ + lane * KS;
+                    float af[MT][KS];
 #pragma unroll
-                    for (int q = 0; q < KQ; ++q) {
-                        const float4 v = *(const float4*)(ab + mt * 64 * KS + 4 * q);
-                        af[mt][4 * q] = v.x;
-                        af[mt][4 * q + 1] = v.y;
-                        af[mt][4 * q + 2] = v.z;
-                        af[mt][4 * q + 3] = v.w;
+                    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                        for (int q = 0; q < KQ; ++q) {
+                            const float4 v = *(const float4*)(ab + mt * 64 * KS + 4 * q);
+                            af[mt][4 * q] = v.x;
+                            af[mt][4 * q + 1] = v.y;
+                            af[mt][4 * q + 2] = v.z;
+                            af[mt][4 * q + 3] = v.w;
+                        }
+                    const float* xb = s_x + (jj * 2 + h) * XH + mm * XM + lane * KS;
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt) {
+                        float bf[KS];
+#pragma unroll
+                        for (int q = 0; q < KQ; ++q) {
+                            const float4 v = *(const float4*)(xb + nt * 64 * KS + 4 * q);
+                            bf[4 * q] = v.x;
+                            bf[4 * q + 1] = v.y;
+                            bf[4 * q + 2] = v.z;
+                            bf[4 * q + 3] = v.w;
+                        }
+#pragma unroll
+                        for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+                            for (int mt = 0; mt < MT; ++mt)
+                                acc[h][mm * MT + mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                                    af[mt][ks], bf[ks], acc[h][mm * MT + mt][nt], 0, 0, 0);
                     }
-                const float* xb = s_x + (jj * 2 + h) * XH + lane * KS;
-#pragma unroll
-                for (int nt = 0; nt < NT; ++nt) {
-                    float bf[KS];
-#pragma unroll
-                    for (int q = 0; q < KQ; ++q) {
-                        const float4 v = *(const float4*)(xb + nt * 64 * KS + 4 * q);
-                        bf[4 * q] = v.x;
-                        bf[4 * q + 1] = v.y;
-                        bf[4 * q + 2] = v.z;
-                        bf[4 * q + 3] = v.w;
-                    }
-#pragma unroll
-                    for (int ks = 0; ks < KS; ++ks)
-#pragma unroll
-                        for (int mt = 0; mt < MT; ++mt)
-                            acc[h][mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[mt][ks], bf[ks], acc[h][mt][nt],
-                                                                                  0, 0, 0);
                 }
             }
         }
@@ -360,6 +393,26 @@ __global__ __launch_bounds__(256) void wx_mfma_kernel(WxMfmaArgs a) {
     // lane holds C[16 mt + 4 (lane / 16) + t][16 nt + lane % 16]: real-form
     // row -> (half h, entry (l, m), real or imaginary part), column -> RHS
     float* pf = reinterpret_cast<float*>(a.part);
+    if constexpr (S::G3) {
+        // three-product form: row r = entry (l, m); Re = T1 - T2, Im = T3 - T1 - T2
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int e = 4 * (lane >> 4) + t;
+                    if (e < HALF) {
+                        const float t1 = acc[h][0][nt][t], t2 = acc[h][1][nt][t], t3 = acc[h][2][nt][t];
+                        const int col = 16 * nt + (lane & 15);
+                        const size_t o =
+                            (((size_t)chunk * a.nrhs + k0 + col) * (2 * HALF) + h * HALF + e) * a.ldp + i;
+                        pf[2 * o] = t1 - t2;
+                        pf[2 * o + 1] = t3 - t1 - t2;
+                    }
+                }
+        return;
+    }
 #pragma unroll
     for (int h = 0; h < 2; ++h)
 #pragma unroll
@@ -385,12 +438,14 @@ __global__ __launch_bounds__(256) void wx_mfma_kernel(WxMfmaArgs a) {
 // real-form row k (Re of entry k < HALF, Im of entry k - HALF below 2 HALF,
 // zero padding above) of right-hand side col = 16 nt + c sits at lane
 // (k % 4) 16 + c, k-step k / 4
+// (three-product form: xb [K / KN][N][2][3][NT][64][KS], operand matrices
+// Re, Im and Re + Im of the HALF entries, row k = entry k)
 template <int L, int NT>
 __global__ void wx_mfma_prep_kernel(const cx<float>* __restrict__ x0, const int* kstep, int kin, int64_t slot_stride,
                                     float* __restrict__ xb, int n, int K) {
     using S = MShape<L>;
-    constexpr int HALF = S::HALF, KS = S::KS, KN = 16 * NT;
-    constexpr int XH = NT * 64 * KS;
+    constexpr int HALF = S::HALF, KS = S::KS, KN = 16 * NT, NMAT = S::NMAT;
+    constexpr int XH = NMAT * NT * 64 * KS;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t total = (int64_t)(K / KN) * n * 2 * XH;
     if (t >= total) return;
@@ -401,6 +456,8 @@ __global__ void wx_mfma_prep_kernel(const cx<float>* __restrict__ x0, const int*
     r /= 64;
     const int nt = (int)(r % NT);
     r /= NT;
+    const int mm = (int)(r % NMAT);
+    r /= NMAT;
     const int h = (int)(r % 2);
     r /= 2;
     const int j = (int)(r % n);
@@ -408,12 +465,13 @@ __global__ void wx_mfma_prep_kernel(const cx<float>* __restrict__ x0, const int*
     const int k = 4 * ks + (ln >> 4);
     const int col = z * KN + 16 * nt + (ln & 15);
     float v = 0.f;
-    if (k < 2 * HALF) {
-        const int e = k < HALF ? k : k - HALF;
+    const int e = S::G3 ? k : (k < HALF ? k : k - HALF);
+    if (S::G3 ? k < HALF : k < 2 * HALF) {
         const cx<float>* xr = x + ((size_t)col * n + j) * 2 * HALF;
         const cx<float> x1 = xr[e], x2 = xr[HALF + e];
         const cx<float> sd = h == 0 ? cx<float>{x1.re + x2.re, x1.im + x2.im} : cx<float>{x1.re - x2.re, x1.im - x2.im};
-        v = k < HALF ? sd.re : sd.im;
+        if constexpr (S::G3) v = mm == 0 ? sd.re : (mm == 1 ? sd.im : sd.re + sd.im);
+        else v = k < HALF ? sd.re : sd.im;
     }
     xb[t] = v;
 }
@@ -421,7 +479,7 @@ __global__ void wx_mfma_prep_kernel(const cx<float>* __restrict__ x0, const int*
 template <int L, int NT>
 void launch_nt(const WxMfmaArgs& a, int hmode, int nchunk, hipStream_t s, const hipEvent_t* ev) {
     using S = MShape<L>;
-    const int64_t total = (int64_t)a.nrhs * a.n * 2 * S::KS * 64 / 16;
+    const int64_t total = (int64_t)(a.nrhs / (16 * NT)) * a.n * 2 * (S::NMAT * NT * 64 * S::KS);
     hipLaunchKernelGGL((wx_mfma_prep_kernel<L, NT>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, a.x,
                        a.kstep, a.kin, a.slot_stride, a.xb, a.n, a.nrhs);
     dim3 grid((unsigned)((a.n + 3) / 4), (unsigned)nchunk, (unsigned)(a.nrhs / (16 * NT)));
@@ -443,8 +501,9 @@ void launch_L(const WxMfmaArgs& a, int width, int hmode, int nchunk, hipStream_t
 }  // namespace
 
 size_t wx_mfma_xb_floats(int L, int64_t N, int K) {
-    const int R = (2 * L * (L + 2) + 15) / 16 * 16;
-    return (size_t)2 * K * N * R;
+    // per right-hand side and source half: R rows (real form) or 3 x 16 (three-product form, lmax 3)
+    const int rows = L == 3 ? 3 * 16 : (2 * L * (L + 2) + 15) / 16 * 16;
+    return (size_t)2 * K * N * rows;
 }
 
 int wx_mfma_block(int L, int K, bool any) {
