@@ -213,13 +213,16 @@ int celes_preconditioner_info(const celes_handle* h, double* edge, int64_t* nblo
 
 /* y = P^{-1} x for the block-diagonal preconditioner of the last
  * celes_build_preconditioner (Section 3.2.1): every cuboid's block of x is
- * multiplied by the inverse of M_j = I - T W_jj.  precision CELES_FP64:
- * x_dev, y_dev complex128 [N][nmax] (one right-hand side), FP64 inverses;
+ * multiplied by the inverse of M_j = I - T W_jj, for K right-hand sides.
+ * precision CELES_FP64: x_dev, y_dev complex128 [K][N][nmax], FP64 inverses;
  * CELES_MIXED: complex64 vectors and the complex64 copy of the inverses.
- * Enqueued on `stream` (NULL = default stream).  x_dev and y_dev must not
- * alias.  Errors: CELES_E_ARG, CELES_E_STATE (no preconditioner),
- * CELES_E_DEVICE. */
-int celes_apply_preconditioner(celes_handle* h, int precision, const void* x_dev, void* y_dev, void* stream);
+ * K = 1 splits each block's columns over work-groups (a fixed-order
+ * reduction of partial sums follows); K > 1 reads each inverse tile once per
+ * group of eight right-hand sides.  Enqueued on `stream` (NULL = default
+ * stream).  x_dev and y_dev must not alias.  Errors: CELES_E_ARG, CELES_E_STATE
+ * (no preconditioner), CELES_E_DEVICE. */
+int celes_apply_preconditioner(celes_handle* h, int precision, int K, const void* x_dev, void* y_dev,
+                               void* stream);
 
 /* Solve the master equation M b = T a_in (Section 2.2, eqs. masterequation
  * and M) for every right-hand side by right-preconditioned restarted GMRES

@@ -237,11 +237,12 @@ class Problem:
         _check(lib().celes_apply_M(self._h, precision, K, C.c_void_p(xp), C.c_void_p(yp), _stream_ptr(stream)),
                self._h)
 
-    def apply_preconditioner(self, x, y, precision=CELES_FP64, stream=None):
-        """y = P^{-1} x (block-diagonal preconditioner) on device buffers."""
+    def apply_preconditioner(self, x, y, precision=CELES_FP64, stream=None, K=1):
+        """y = P^{-1} x (block-diagonal preconditioner) for K right-hand sides
+        on device buffers."""
         xp = x.data_ptr() if hasattr(x, "data_ptr") else int(x)
         yp = y.data_ptr() if hasattr(y, "data_ptr") else int(y)
-        _check(lib().celes_apply_preconditioner(self._h, precision, C.c_void_p(xp), C.c_void_p(yp),
+        _check(lib().celes_apply_preconditioner(self._h, precision, int(K), C.c_void_p(xp), C.c_void_p(yp),
                                                 _stream_ptr(stream)), self._h)
 
     # ---- observables ------------------------------------------------------

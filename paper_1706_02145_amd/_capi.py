@@ -55,7 +55,7 @@ SIGNATURES = {
                                             C.POINTER(C.c_int64), _dp, C.POINTER(C.c_int64)]),
     "celes_preconditioner_info": (C.c_int, [_h, _dp, C.POINTER(C.c_int64), _dp]),
     "celes_solve": (C.c_int, [_h, _dp, _dp, C.POINTER(SolveInfo)]),
-    "celes_apply_preconditioner": (C.c_int, [_h, C.c_int, _vp, _vp, _vp]),
+    "celes_apply_preconditioner": (C.c_int, [_h, C.c_int, C.c_int, _vp, _vp, _vp]),
     "celes_s11": (C.c_int, [C.c_void_p, C.c_int, C.c_int64, _dp, C.c_int, _dp]),
     "celes_subsystem_guess": (C.c_int, [_h, C.c_int64, C.POINTER(C.c_int64), C.c_double, _dp, C.POINTER(SolveInfo)]),
     "celes_apply_W": (C.c_int, [_h, C.c_int, C.c_int, _vp, _vp, _vp]),

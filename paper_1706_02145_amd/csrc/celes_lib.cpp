@@ -1132,20 +1132,25 @@ int celes_apply_M(celes_handle* h, int precision, int K, const void* x_dev, void
 }
 
 
-static int celes_apply_preconditioner_impl(celes_handle* h, int precision, const void* x_dev, void* y_dev,
+static int celes_apply_preconditioner_impl(celes_handle* h, int precision, int K, const void* x_dev, void* y_dev,
                                            void* stream) {
     if (!h) return CELES_E_ARG;
-    if (!x_dev || !y_dev || x_dev == y_dev) return fail(h, CELES_E_ARG, "null or aliasing device pointer");
+    if (K < 1 || !x_dev || !y_dev || x_dev == y_dev) return fail(h, CELES_E_ARG, "K < 1, null or aliasing pointer");
     if (!h->pre) return fail(h, CELES_E_STATE, "no preconditioner built");
     hipStream_t s = (hipStream_t)stream;
+    const int64_t n = h->N * h->nmax;
     int rc;
-    if (precision == CELES_FP64) rc = h->pre->apply<double>((const cx<double>*)x_dev, (cx<double>*)y_dev, s);
-    else if (precision == CELES_MIXED) rc = h->pre->apply<float>((const cx<float>*)x_dev, (cx<float>*)y_dev, s);
+    if (precision == CELES_FP64)
+        rc = K == 1 ? h->pre->apply<double>((const cx<double>*)x_dev, (cx<double>*)y_dev, s)
+                    : h->pre->apply_multi<double>((const cx<double>*)x_dev, (cx<double>*)y_dev, K, n, nullptr, 0, s);
+    else if (precision == CELES_MIXED)
+        rc = K == 1 ? h->pre->apply<float>((const cx<float>*)x_dev, (cx<float>*)y_dev, s)
+                    : h->pre->apply_multi<float>((const cx<float>*)x_dev, (cx<float>*)y_dev, K, n, nullptr, 0, s);
     else return fail(h, CELES_E_ARG, "unknown precision");
     return rc == CELES_OK ? CELES_OK : fail(h, rc, "preconditioner apply failed");
 }
-int celes_apply_preconditioner(celes_handle* h, int precision, const void* x_dev, void* y_dev, void* stream) {
-    return celes_guard([&] { return celes_apply_preconditioner_impl(h, precision, x_dev, y_dev, stream); });
+int celes_apply_preconditioner(celes_handle* h, int precision, int K, const void* x_dev, void* y_dev, void* stream) {
+    return celes_guard([&] { return celes_apply_preconditioner_impl(h, precision, K, x_dev, y_dev, stream); });
 }
 
 static int celes_build_preconditioner_impl(celes_handle* h, double cuboid_edge) {
@@ -2052,18 +2057,20 @@ int batch_matvec(celes_batch* b, const cx<T>* V, const int* kstep, int kin, cx<T
 // preconditioner on each of its right-hand sides, the identity for problems
 // without one (flat layout, in and out must not alias)
 template <typename T>
-int batch_precond_apply(celes_batch* b, const cx<T>* in, cx<T>* out, hipStream_t s) {
+int batch_precond_apply(celes_batch* b, const cx<T>* in, cx<T>* out, hipStream_t s, bool skip_inactive) {
+    // one pass over a problem's inverses per group of eight of its systems;
+    // inside an Arnoldi step groups of converged systems are skipped (their
+    // slots are not read); the cycle-end update applies every system, since
+    // one that converged during the cycle still needs its last correction
     for (int p = 0; p < b->nprob; ++p) {
         celes_handle* h = b->probs[p];
-        const int64_t n = h->N * h->nmax;
-        for (int r = 0; r < h->K; ++r) {
-            const int64_t off = b->elem_off[p] + (int64_t)r * n;
-            if (h->pre) {
-                if (h->pre->apply<T>(in + off, out + off, s) != 0)
-                    return bfail(b, CELES_E_DEVICE, "batch preconditioner apply failed");
-            } else {
-                celes::vec_scale<T>(in + off, 1.0, out + off, n, s);
-            }
+        const int64_t n = h->N * h->nmax, off = b->elem_off[p];
+        if (h->pre) {
+            if (h->pre->apply_multi<T>(in + off, out + off, h->K, n, skip_inactive ? b->st.active : nullptr,
+                                       b->sys0[p], s) != 0)
+                return bfail(b, CELES_E_DEVICE, "batch preconditioner apply failed");
+        } else {
+            celes::vec_scale<T>(in + off, 1.0, out + off, (int64_t)h->K * n, s);
         }
     }
     return CELES_OK;
@@ -2078,7 +2085,7 @@ void record_arnoldi_step(celes_batch* b, cx<T>* V, double tol, hipStream_t s) {
         // buffers because the apply takes plain pointers and the step index
         // lives on the device
         celes::bk_slot_copy<T>(V, k, 0, b->d_pz.as<cx<T>>(), nullptr, 0, b->total, s);
-        batch_precond_apply<T>(b, b->d_pz.as<cx<T>>(), b->d_pw.as<cx<T>>(), s);
+        batch_precond_apply<T>(b, b->d_pz.as<cx<T>>(), b->d_pw.as<cx<T>>(), s, true);
         celes::bk_slot_copy<T>(b->d_pw.as<cx<T>>(), nullptr, 0, V, k, 1, b->total, s);
         batch_matvec<T>(b, V, k, 1, V, 1, 1, s);                              // in place on slot k+1
     } else {
@@ -2177,7 +2184,7 @@ int batch_gmres(celes_batch* b, const cx<T>* rhs, cx<T>* d, cx<T>* tmp, double t
             celes::bk_zero<T>(b->d_pz.as<cx<T>>(), b->total, s);
             celes::bk_gemv<T>(b->si, V, b->total, b->st.y, m + 1, nullptr, 0, b->st.used, nullptr,
                               b->d_pz.as<cx<T>>(), 0, 1.0, s);
-            if ((*rc_out = batch_precond_apply<T>(b, b->d_pz.as<cx<T>>(), b->d_pw.as<cx<T>>(), s)) != CELES_OK)
+            if ((*rc_out = batch_precond_apply<T>(b, b->d_pz.as<cx<T>>(), b->d_pw.as<cx<T>>(), s, false)) != CELES_OK)
                 return cycle;
             celes::bk_add<T>(d, b->d_pw.as<cx<T>>(), d, b->total, s);
         } else {

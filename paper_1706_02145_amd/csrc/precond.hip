@@ -498,4 +498,85 @@ int BlockPrecond::apply(const cx<T>* in, cx<T>* out, hipStream_t s) const {
 template int BlockPrecond::apply<double>(const cx<double>*, cx<double>*, hipStream_t) const;
 template int BlockPrecond::apply<float>(const cx<float>*, cx<float>*, hipStream_t) const;
 
+// Several right-hand sides: block (row tile, cuboid j, group g) owns rows
+// r0..r0+255 of M_j^{-1} and right-hand sides 8g..8g+7; it walks all column
+// tiles of the block (no split, so no partial sums), staging the group's x
+// entries of a column tile in LDS, so each matrix entry is loaded once for up
+// to eight right-hand sides.
+constexpr int PM_KB = 8;
+template <typename T, typename TM>
+__global__ void __launch_bounds__(PA_ROWS) apply_tiles_multi(const cx<TM>* __restrict__ inv,
+                                                             const int64_t* __restrict__ perm,
+                                                             const int64_t* __restrict__ boff,
+                                                             const int64_t* __restrict__ moff, int nmax, int nb,
+                                                             const cx<T>* __restrict__ in, cx<T>* __restrict__ out,
+                                                             int K, int64_t stride, const int* __restrict__ active,
+                                                             int sys0) {
+    const int j = blockIdx.z % nb, g = blockIdx.z / nb;
+    const int k0 = g * PM_KB, kn = min(PM_KB, K - k0);
+    if (active) {
+        int any = 0;
+        for (int q = 0; q < kn; ++q) any |= active[sys0 + k0 + q];
+        if (!any) return;
+    }
+    const int64_t o = boff[j], dim = (boff[j + 1] - o) * nmax;
+    const int64_t r0 = (int64_t)blockIdx.x * PA_ROWS;
+    if (r0 >= dim) return;
+    const int64_t r = r0 + threadIdx.x;
+    __shared__ cx<TM> xs[PA_COLS][PM_KB];
+    TM re[PM_KB], im[PM_KB];
+#pragma unroll
+    for (int q = 0; q < PM_KB; ++q) re[q] = im[q] = 0;
+    const cx<TM>* Mrow = inv + moff[j] + (r < dim ? r : 0);
+    for (int64_t c0 = 0; c0 < dim; c0 += PA_COLS) {
+        const int ncol = (int)(dim - c0 < PA_COLS ? dim - c0 : PA_COLS);
+        __syncthreads();
+        for (int e = threadIdx.x; e < ncol * PM_KB; e += PA_ROWS) {
+            const int c = e / PM_KB, q = e % PM_KB;
+            cx<TM> v = {0, 0};
+            if (q < kn) {
+                const int64_t cc = c0 + c;
+                const cx<T> w = in[(int64_t)(k0 + q) * stride + perm[o + cc / nmax] * nmax + cc % nmax];
+                v = {(TM)w.re, (TM)w.im};
+            }
+            xs[c][q] = v;
+        }
+        __syncthreads();
+        if (r < dim) {
+            for (int c = 0; c < ncol; ++c) {
+                const cx<TM> a = stream_load(Mrow + (c0 + c) * dim);
+#pragma unroll
+                for (int q = 0; q < PM_KB; ++q) {
+                    const cx<TM> x = xs[c][q];
+                    re[q] = fma(a.re, x.re, fma(-a.im, x.im, re[q]));
+                    im[q] = fma(a.re, x.im, fma(a.im, x.re, im[q]));
+                }
+            }
+        }
+    }
+    if (r >= dim) return;
+    const int64_t dst = perm[o + r / nmax] * nmax + r % nmax;
+    for (int q = 0; q < kn; ++q) out[(int64_t)(k0 + q) * stride + dst] = {(T)re[q], (T)im[q]};
+}
+
+template <typename T>
+int BlockPrecond::apply_multi(const cx<T>* in, cx<T>* out, int K, int64_t stride, const int* active, int sys0,
+                              hipStream_t s) const {
+    if (K < 1) return 0;
+    const int nb = (int)offsets_.size() - 1;
+    const int ng = (K + PM_KB - 1) / PM_KB;
+    dim3 grid((unsigned)((max_dim_ + PA_ROWS - 1) / PA_ROWS), 1, (unsigned)(nb * ng));
+    if constexpr (sizeof(T) == 4)
+        hipLaunchKernelGGL((apply_tiles_multi<T, float>), grid, dim3(PA_ROWS), 0, s, d_inv32_, d_perm_, d_boff_,
+                           d_moff_, nmax_, nb, in, out, K, stride, active, sys0);
+    else
+        hipLaunchKernelGGL((apply_tiles_multi<T, double>), grid, dim3(PA_ROWS), 0, s, d_inv_, d_perm_, d_boff_,
+                           d_moff_, nmax_, nb, in, out, K, stride, active, sys0);
+    return hipGetLastError() == hipSuccess ? 0 : CELES_E_DEVICE_INTERNAL;
+}
+template int BlockPrecond::apply_multi<double>(const cx<double>*, cx<double>*, int, int64_t, const int*, int,
+                                               hipStream_t) const;
+template int BlockPrecond::apply_multi<float>(const cx<float>*, cx<float>*, int, int64_t, const int*, int,
+                                              hipStream_t) const;
+
 }  // namespace celes

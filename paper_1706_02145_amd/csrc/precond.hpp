@@ -28,6 +28,14 @@ class BlockPrecond {
     // complex64 vectors use the complex64 copy of the inverses
     template <typename T>
     int apply(const cx<T>* in, cx<T>* out, hipStream_t s) const;
+    // out_k = P^{-1} in_k for K right-hand sides k at element stride `stride`
+    // (layout [K][N][nmax]): each inverse tile is read once per group of up to
+    // 8 right-hand sides; groups whose systems are all inactive
+    // (active[sys0 + k] == 0, active may be null) are skipped and their
+    // outputs left as they are.  Allocates nothing (graph-capture safe).
+    template <typename T>
+    int apply_multi(const cx<T>* in, cx<T>* out, int K, int64_t stride, const int* active, int sys0,
+                    hipStream_t s) const;
 
     int num_blocks() const { return (int)offsets_.size() - 1; }
     const std::vector<int64_t>& perm() const { return perm_; }

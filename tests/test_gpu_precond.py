@@ -100,3 +100,28 @@ def test_complex64_copy_beyond_2_to_32_entries():
         sph = perm[off[j]:off[j + 1]]
         assert rel(y32[sph], y64[sph]) <= 1e-5, j
     assert rel(y32, y64) <= 1e-5
+
+
+@pytest.mark.parametrize("K", [3, 8, 11])
+def test_apply_several_rhs_matches_oracle_and_single(K):
+    # K right-hand sides through the grouped apply (each inverse tile read once
+    # per group of eight): every column against the oracle's block LU solve and
+    # against the one-right-hand-side apply; a ragged last group (K = 3, 11)
+    w = workload("slab300_l3")
+    edge = 700.0
+    perm, off = partition(w.positions, edge)
+    M, W, t = master_matrix(w.positions, w.radii, w.n_sphere, w.n0, w.wavelength, w.lmax)
+    pre = BlockDiagonalPreconditioner(M, w.nmax, perm, off)
+    X = random_coefficients(30 + K, K, w.N, w.nmax)
+    p = make_problem(w, hankel=1)
+    p.build_preconditioner(edge)
+    for prec, dt, bar in ((P.CELES_FP64, torch.complex128, 1e-11), (P.CELES_MIXED, torch.complex64, 1e-5)):
+        xd = torch.from_numpy(X).to("cuda", dt)
+        yd = torch.empty_like(xd)
+        p.apply_preconditioner(xd, yd, prec, K=K)
+        torch.cuda.synchronize()
+        Y = yd.cpu().numpy().astype(np.complex128)
+        for k in range(K):
+            yref = pre(X[k].reshape(-1)).reshape(w.N, -1)
+            assert rel(Y[k], yref) <= bar, (prec, k)
+            assert rel(Y[k], _apply(p, X[k], prec)) <= (1e-13 if prec == P.CELES_FP64 else 1e-6)
