@@ -112,3 +112,20 @@ def test_switching_the_scheme_between_calls():
     assert rel(yr, yd) <= 1e-12
     with pytest.raises(P.CelesError):
         p.set_solve_options(translation=7)
+
+
+def test_rotated_matvec_full_size_sampled_rows():
+    # the 20,000-sphere benchmark slab (lmax 4, LUT), in the launch
+    # configuration the benchmark times: FP64 and complex64 rotation-scheme
+    # W x against the oracle's rows on sampled receivers
+    w = workload("slab20000_l4")
+    print("[rotation] slab20000_l4 sampled rows", flush=True)
+    x = random_coefficients(213, 1, w.N, w.nmax)[0]
+    p = make_problem(w, hankel=0, translation=ROT)
+    y = _gpu_W(p, x)
+    y32 = _gpu_W(p, x, precision=P.CELES_MIXED)
+    rows = [0, 4999, 12345, 19999]
+    ref = apply_W_rows(w.positions, x, k_of(w), w.lmax, rows, hankel=oracle_lut(w))
+    e, e32 = rel(y[rows], ref), rel(y32[rows], ref)
+    print(f"[rotation] slab20000 fp64 {e:.2e} fp32 {e32:.2e}", flush=True)
+    assert e <= 1e-11 and e32 <= 1e-4
