@@ -260,8 +260,14 @@ static int matvec_mfma(celes_handle* h, const cx<float>* x, cx<float>* y, int K,
     const int64_t N = h->N;
     const int64_t nbx = (N + 3) / 4 * (K / width);
     const char* env = std::getenv("CELES_WXM_TARGET_BLOCKS");
-    const int target = env ? std::max(1, std::atoi(env)) : 2048;
-    int64_t nchunk = std::max<int64_t>(1, std::min<int64_t>((target + nbx - 1) / nbx, (N + 1) / 2));
+    // about 20,000 blocks: at 80 KB of LDS two blocks fit a compute unit, so
+    // one chunk (N/4 blocks) leaves a partial last round; measured on the
+    // 10,000-sphere slab at lmax 3 with 64 right-hand sides, 8 chunks take
+    // 224.9 ms against 233.3 ms for one.  Chunks keep at least 64 sources
+    // (an explicit target may go down to 2, for tests of the chunk split).
+    const int target = env ? std::max(1, std::atoi(env)) : 20000;
+    const int64_t max_chunks = env ? (N + 1) / 2 : std::max<int64_t>(1, N / 64);
+    int64_t nchunk = std::max<int64_t>(1, std::min<int64_t>((target + nbx - 1) / nbx, max_chunks));
     int64_t chunk_len = (N + nchunk - 1) / nchunk;
     chunk_len += chunk_len & 1;
     const int nchunk_eff = (int)((N + chunk_len - 1) / chunk_len);
