@@ -99,6 +99,12 @@ typedef struct celes_options {
                              * celes_solve, celes_apply_W_noalloc) evaluates each pair's
                              * block; the matrix-core kernel, batches and the
                              * preconditioner assembly always use the direct form           */
+    int deterministic;      /* 1: bitwise the same results from run to run on one device:
+                             * no timing-based choice of the work split (autotune is
+                             * ignored; celes_batch_autotune fails with CELES_E_STATE), every
+                             * split follows from the sizes alone.  The reductions of the
+                             * mat-vec, dots and preconditioner apply are fixed-order in
+                             * either mode (no floating-point atomics)                        */
 } celes_options;
 
 typedef struct celes_solve_info {
@@ -119,7 +125,7 @@ typedef struct celes_solve_info {
 /* Fill *opt with defaults: FP64, LUT, lut_dr = 1, tol = 1e-8, inner_tol = 1e-4,
  * restart = 100, maxiter = 2000, max_refinements = 30, cuboid_edge = 0, device 0,
  * solver GMRES, target_Nj = 100, mem_cap_bytes = 0 (free device memory),
- * autotune = 0. */
+ * autotune = 0, translation = CELES_TRANSLATION_DIRECT, deterministic = 0. */
 void celes_default_options(celes_options* opt);
 
 /* Library version (CELES_VERSION). */
@@ -426,7 +432,8 @@ int celes_batch_apply_M(celes_batch* b, int precision, const void* x_dev, void* 
 /* Choose the batched mat-vec's source-chunk length and right-hand-side block
  * width by timing the candidates on this batch; the choice is kept by the
  * batch.  Outputs (may be NULL): the best time of one batched M x in ms, the
- * chunk length, the block width.  Errors: CELES_E_ARG. */
+ * chunk length, the block width.  Errors: CELES_E_ARG, CELES_E_STATE (the
+ * batch was created with opt.deterministic = 1). */
 int celes_batch_autotune(celes_batch* b, int precision, double* best_ms, int* best_chunk, int* best_kb);
 
 /* Solve every system from a zero initial guess to opt.tol; solutions are

@@ -121,7 +121,7 @@ class Problem:
     def set_solve_options(self, **kw):
         """Change solver settings (precision, tol, inner_tol, restart, maxiter,
         max_refinements, verbose, solver, target_Nj, mem_cap_bytes, autotune,
-        translation)
+        translation, deterministic)
         for the next solves, keeping geometry, incident field and
         preconditioner (celes_set_solve_options)."""
         opt = Options()

@@ -24,7 +24,8 @@ class Options(C.Structure):
                 ("inner_tol", C.c_double), ("restart", C.c_int), ("maxiter", C.c_int),
                 ("max_refinements", C.c_int), ("cuboid_edge", C.c_double), ("device", C.c_int),
                 ("verbose", C.c_int), ("solver", C.c_int), ("target_Nj", C.c_double),
-                ("mem_cap_bytes", C.c_double), ("autotune", C.c_int), ("translation", C.c_int)]
+                ("mem_cap_bytes", C.c_double), ("autotune", C.c_int), ("translation", C.c_int),
+                ("deterministic", C.c_int)]
 
 
 class SolveInfo(C.Structure):

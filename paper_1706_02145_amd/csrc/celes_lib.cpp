@@ -336,6 +336,7 @@ static int matvec_target(celes_handle* h, const cx<T>* x, cx<T>* y, int K, int e
     const char* env = std::getenv("CELES_WX_TARGET_BLOCKS");
     if (env) return std::max(1, std::atoi(env));
     if (h->target_blocks > 0) return h->target_blocks;
+    if (h->opt.deterministic) return 4096;
     int& tuned = h->tuned_blocks[sizeof(T) == 8 ? 0 : 1];
     if (tuned > 0 || !h->opt.autotune) return tuned > 0 ? tuned : 4096;
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
@@ -942,6 +943,7 @@ int celes_set_solve_options(celes_handle* h, const celes_options* opt) {
     o.target_Nj = opt->target_Nj;
     o.mem_cap_bytes = opt->mem_cap_bytes;
     o.autotune = opt->autotune;
+    o.deterministic = opt->deterministic;
     if (o.translation != opt->translation) {
         o.translation = opt->translation;
         h->tuned_blocks[0] = h->tuned_blocks[1] = 0;     // a tuned split belongs to one scheme
@@ -2347,6 +2349,7 @@ int celes_batch_apply_M(celes_batch* b, int precision, const void* x_dev, void* 
 
 static int celes_batch_autotune_impl(celes_batch* b, int precision, double* best_ms, int* best_chunk, int* best_kb) {
     if (!b) return CELES_E_ARG;
+    if (b->opt.deterministic) return bfail(b, CELES_E_STATE, "the batch was created deterministic: no timing-based split");
     const bool f64 = precision == CELES_FP64;
     const int mxkb = f64 ? celes::wx_max_kb<double>(b->L) : celes::wx_max_kb<float>(b->L);
     hipStream_t s = b->stream;

@@ -85,8 +85,24 @@ def test_default_options():
     assert o.precision == P.CELES_FP64 and o.hankel == P.CELES_HANKEL_LUT
     assert o.lut_dr == 1.0 and o.restart == 100
     assert o.solver == P.CELES_SOLVER_GMRES
+    assert o.autotune == 0 and o.deterministic == 0 and o.translation == P.CELES_TRANSLATION_DIRECT
     with pytest.raises(KeyError):
         P.default_options(nonsense=1)
+
+
+def test_options_layout_matches_the_library():
+    # celes_default_options writes the whole C struct: a binding struct
+    # shorter than the library's would be overrun, one with a field out of
+    # place would read back wrong defaults
+    import ctypes as C
+    from paper_1706_02145_amd._capi import Options, lib
+    n = C.sizeof(Options)
+    buf = (C.c_ubyte * (n + 64))(*([0xAB] * (n + 64)))
+    lib().celes_default_options(C.cast(buf, C.POINTER(Options)))
+    assert bytes(buf[n:]) == b"\xab" * 64
+    o = Options.from_buffer_copy(bytes(buf[:n]))
+    assert o.tol == 1e-8 and o.inner_tol == 1e-4 and o.max_refinements == 30
+    assert o.target_Nj == 100.0 and o.deterministic == 0
 
 
 def test_preconditioner_plan_respects_target_and_memory_cap():

@@ -193,3 +193,20 @@ def test_kernel_timing_counts_coupling_launches():
     assert n == 3 and 0 < ms < 1e3
     ms, n = p.kernel_timing(False)       # not running: nothing recorded
     assert n == 0 and ms == 0
+
+
+def test_deterministic_option_fixes_the_split():
+    # deterministic = 1 switches the timing-based split off: the split follows
+    # from the sizes, so an autotune-requesting handle gives a plain handle's
+    # bits on every call, and a batch created deterministic refuses to tune
+    w = workload("slab300_l3")
+    x = random_coefficients(108, 1, w.N, w.nmax)[0]
+    plain = make_problem(w, hankel=0)
+    det = make_problem(w, hankel=0, autotune=1, deterministic=1)
+    y0 = _gpu_W(plain, x)
+    for _ in range(2):
+        assert np.array_equal(_gpu_W(det, x), y0)
+        assert np.array_equal(_gpu_W(det, x, precision=P.CELES_MIXED), _gpu_W(plain, x, precision=P.CELES_MIXED))
+    bt = P.Batch([det], deterministic=1)
+    with pytest.raises(P.CelesError):
+        bt.autotune(P.CELES_FP64)
