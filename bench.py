@@ -329,7 +329,9 @@ def mixed_mode(a):
     """Mixed precision against all-FP64 on the 20,000-sphere slab (lmax 4,
     Gaussian beam, block-diagonal preconditioner, same seed): complex64 inner
     GMRES with FP64 residual refinement vs FP64 GMRES, each solved to 1e-8
-    (solutions compared) and to 1e-6 (time to residual)."""
+    (solutions compared) and to 1e-6 (time to residual), with the direct and
+    the rotation-translation-rotation mat-vec, on one handle and one
+    preconditioner (celes_set_solve_options switches between the runs)."""
     import numpy as np
     import torch
     import paper_1706_02145_amd as P
@@ -343,31 +345,37 @@ def mixed_mode(a):
     w = workload(a.mixed_workload)
     il = w.illumination
     log(f"{w.name} generated (N={w.N})")
+    p = P.Problem(w.positions, w.radii, w.n_sphere, w.n0, w.wavelength, w.lmax, hankel=P.CELES_HANKEL_LUT,
+                  lut_dr=w.lut_dr, restart=100, maxiter=3000, max_refinements=8, verbose=1)
+    p.set_gaussian_beam(il["waist"], il["focus"], il["alpha_G"], il["E0"])
+    t1 = time.perf_counter()
+    p.build_preconditioner(a.cuboid_edge)
+    torch.cuda.synchronize()
+    t_pre = time.perf_counter() - t1
+    log(f"preconditioner built in {t_pre:.1f} s")
+    schemes = (("", P.CELES_TRANSLATION_DIRECT), ("_rotate", P.CELES_TRANSLATION_ROTATE))
     results, sols = {}, {}
     for tol in (1e-8, 1e-6):
-        for name, prec in (("fp64", P.CELES_FP64), ("mixed", P.CELES_MIXED)):
-            p = P.Problem(w.positions, w.radii, w.n_sphere, w.n0, w.wavelength, w.lmax, hankel=P.CELES_HANKEL_LUT,
-                          lut_dr=w.lut_dr, precision=prec, tol=tol, restart=100, maxiter=3000,
-                          inner_tol=1e-4 if tol < 1e-7 else 1e-3, max_refinements=8, verbose=1)
-            p.set_gaussian_beam(il["waist"], il["focus"], il["alpha_G"], il["E0"])
-            t1 = time.perf_counter()
-            p.build_preconditioner(a.cuboid_edge)
-            torch.cuda.synchronize()
-            t_pre = time.perf_counter() - t1
-            log(f"{name} tol {tol:g}: preconditioner built in {t_pre:.1f} s")
-            t1 = time.perf_counter()
-            b, info = p.solve()
-            torch.cuda.synchronize()
-            t_sol = time.perf_counter() - t1
-            log(f"{name} tol {tol:g}: solved in {t_sol:.1f} s, {info['iterations']} iterations")
-            results[f"{name}_tol_{tol:g}"] = {"seconds": t_sol, "iterations": info["iterations"],
-                                              "refinements": info["refinements"], "matvecs": info["matvecs"],
-                                              "rel_residual": info["rel_residual"], "status": info["status"],
-                                              "preconditioner_setup_s": t_pre}
-            if tol < 1e-7:
-                sols[name] = b
-            p.close()
-    diff = float(np.linalg.norm(sols["mixed"] - sols["fp64"]) / np.linalg.norm(sols["fp64"]))
+        for suffix, scheme in schemes:
+            for name, prec in (("fp64", P.CELES_FP64), ("mixed", P.CELES_MIXED)):
+                key = name + suffix
+                p.set_solve_options(precision=prec, tol=tol, inner_tol=1e-4 if tol < 1e-7 else 1e-3,
+                                    translation=scheme)
+                t1 = time.perf_counter()
+                b, info = p.solve()
+                torch.cuda.synchronize()
+                t_sol = time.perf_counter() - t1
+                log(f"{key} tol {tol:g}: solved in {t_sol:.1f} s, {info['iterations']} iterations")
+                results[f"{key}_tol_{tol:g}"] = {"seconds": t_sol, "iterations": info["iterations"],
+                                                 "refinements": info["refinements"], "matvecs": info["matvecs"],
+                                                 "rel_residual": info["rel_residual"], "status": info["status"]}
+                if tol < 1e-7:
+                    sols[key] = b
+    p.close()
+
+    def diff(u, v):
+        return float(np.linalg.norm(sols[u] - sols[v]) / np.linalg.norm(sols[v]))
+
     t64, t32 = results["fp64_tol_1e-06"]["seconds"], results["mixed_tol_1e-06"]["seconds"]
     print(json.dumps({
         "metric": "time to residual 1e-6, mixed precision (complex64 inner GMRES, FP64 refinement) vs FP64",
@@ -377,9 +385,14 @@ def mixed_mode(a):
                                f"lmax={w.lmax}, Gaussian beam w=2 um, LUT 1 nm, block-diagonal preconditioner "
                                f"(cuboid edge {a.cuboid_edge:g} nm), restart 100",
                    "N": w.N, "lmax": w.lmax},
+        "preconditioner_setup_s": t_pre,
         "speedup_mixed_vs_fp64_1e-6": t64 / t32,
         "speedup_mixed_vs_fp64_1e-8": results["fp64_tol_1e-08"]["seconds"] / results["mixed_tol_1e-08"]["seconds"],
-        "solution_rel_diff_mixed_vs_fp64_at_1e-8": diff, "results": results}))
+        "speedup_mixed_rotate_vs_fp64_1e-6": t64 / results["mixed_rotate_tol_1e-06"]["seconds"],
+        "solution_rel_diff_mixed_vs_fp64_at_1e-8": diff("mixed", "fp64"),
+        "solution_rel_diff_rotate_vs_direct_fp64_at_1e-8": diff("fp64_rotate", "fp64"),
+        "solution_rel_diff_mixed_rotate_vs_fp64_at_1e-8": diff("mixed_rotate", "fp64"),
+        "results": results}))
 
 
 def _cyl_workload(args):
