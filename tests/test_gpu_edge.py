@@ -1,6 +1,7 @@
 """Degenerate and boundary cases of the GPU path: one sphere (W = 0, the
 solve reduces to Mie scattering), two spheres on the z axis (only m = m'
-couplings), the largest compiled cut-offs lmax 5 and 6, and argument errors
+couplings), both with the direct and the rotation-translation-rotation
+mat-vec, the largest compiled cut-offs lmax 5 and 6, and argument errors
 raised before any kernel runs."""
 import math
 
@@ -31,13 +32,17 @@ def _W(p, x, precision=P.CELES_FP64, K_rhs=1):
     return yd.cpu().numpy().astype(np.complex128)
 
 
+TRANSLATIONS = [P.CELES_TRANSLATION_DIRECT, P.CELES_TRANSLATION_ROTATE]
+
+
+@pytest.mark.parametrize("translation", TRANSLATIONS)
 @pytest.mark.parametrize("hankel", [0, 1])
-def test_single_sphere_is_mie(hankel):
+def test_single_sphere_is_mie(hankel, translation):
     pos = np.array([[10.0, -20.0, 30.0]])
     rad = np.array([150.0])
     n = 1.5 + 0.01j
     L = 4
-    p = P.Problem(pos, rad, n, 1.0, LAM, L, hankel=hankel, tol=1e-12)
+    p = P.Problem(pos, rad, n, 1.0, LAM, L, hankel=hankel, tol=1e-12, translation=translation)
     nm = 2 * L * (L + 2)
     # W = 0 for N = 1, on the VALU path and on the matrix-core path
     assert np.abs(_W(p, random_coefficients(1, 1, 1, nm)[0])).max() == 0.0
@@ -52,23 +57,27 @@ def test_single_sphere_is_mie(hankel):
     assert abs(ce[0] - extinction(K, a, t * a)) <= 1e-10 * abs(ce[0])
 
 
-def test_two_spheres_on_z_axis_couple_only_equal_m():
+@pytest.mark.parametrize("translation", TRANSLATIONS)
+def test_two_spheres_on_z_axis_couple_only_equal_m(translation):
+    # the rotation scheme meets theta = pi (source above the receiver) and
+    # theta = 0 (source below)
     pos = np.array([[0.0, 0.0, 0.0], [0.0, 0.0, 700.0]])
     rad = np.array([150.0, 150.0])
     L = 3
-    p = P.Problem(pos, rad, 1.52, 1.0, LAM, L, hankel=1)
+    p = P.Problem(pos, rad, 1.52, 1.0, LAM, L, hankel=1, translation=translation)
     idx = [(t, l, m) for t in (1, 2) for l in range(1, L + 1) for m in range(-l, l + 1)]
     nm = len(idx)
-    for src in (0, 5, 13, 20):       # unit source multipoles on sphere 1
-        x = np.zeros((2, nm), complex)
-        x[1, src] = 1.0
-        y = _W(p, x)
-        mp = idx[src][2]
-        off = [c for c, (t, l, m) in enumerate(idx) if m != mp]
-        assert np.abs(y[0, off]).max() <= 1e-14 * np.abs(y[0]).max()
-        assert np.abs(y[0]).max() > 0
-        ref = apply_W_rows(pos, x, K, L, [0])
-        assert rel(y[0], ref[0]) <= 1e-12
+    for s_sph, r_sph in ((1, 0), (0, 1)):
+        for src in (0, 5, 13, 20):       # unit source multipoles
+            x = np.zeros((2, nm), complex)
+            x[s_sph, src] = 1.0
+            y = _W(p, x)
+            mp = idx[src][2]
+            off = [c for c, (t, l, m) in enumerate(idx) if m != mp]
+            assert np.abs(y[r_sph, off]).max() <= 1e-14 * np.abs(y[r_sph]).max()
+            assert np.abs(y[r_sph]).max() > 0 and np.abs(y[s_sph]).max() == 0.0
+            ref = apply_W_rows(pos, x, K, L, [r_sph])
+            assert rel(y[r_sph], ref[0]) <= 1e-12
 
 
 @pytest.mark.parametrize("L", [5, 6])
