@@ -258,8 +258,9 @@ def batched_mode(a):
             f"in {t_pre:.1f} s")
     updates = sum(q.N * (q.N - 1) * q.nmax ** 2 * q.num_rhs for q in probs)
     log(f"{len(probs)} problems set up, {updates:.3e} updates per batched mat-vec")
+    scheme = P.CELES_TRANSLATION_ROTATE if a.batch_translation == "rotate" else P.CELES_TRANSLATION_DIRECT
     bt = P.Batch(probs, precision=P.CELES_MIXED, tol=a.batch_tol, inner_tol=1e-3, restart=a.batch_restart,
-                 maxiter=a.batch_maxiter, max_refinements=4, verbose=1)
+                 maxiter=a.batch_maxiter, max_refinements=4, verbose=1, translation=scheme)
     tune = bt.autotune(P.CELES_MIXED)
     log(f"autotuned: {tune}")
     # one batched M x in complex64 over every system (HIP events on the caller's stream)
@@ -308,7 +309,8 @@ def batched_mode(a):
         "data": "synthetic",
         "config": {"workload": f"slab10000_l3 (N={w.N}, 64 RHS: 32 polar angles 0-60 deg x TE/TM) + "
                                f"{a.realisations} realisations N in [500,5000] x 2 RHS, lmax 3, LUT 1 nm",
-                   "realisation_sizes": sizes},
+                   "realisation_sizes": sizes,
+                   "valu_translation": a.batch_translation},
         "systems": bt.num_systems, "updates_per_batched_matvec": updates, "batched_matvec_ms": mv_ms,
         "roofline": {"kernel": "wx_mfma_kernel<3, 4, 0> (64-RHS slab alone)",
                      "bound": "mfma", "achieved": apply_flops / (big_kernel_ms * 1e-3) / 1e12,
@@ -835,6 +837,8 @@ def main():
     ap.add_argument("--batch-maxiter", type=int, default=600)
     ap.add_argument("--batch-restart", type=int, default=150)
     ap.add_argument("--batch-no-solve", action="store_true", help="batched mode: mat-vec timings only")
+    ap.add_argument("--batch-translation", choices=["rotate", "direct"], default="rotate",
+                    help="batched mode: translation scheme of the persistent VALU mat-vec (the realisations)")
     ap.add_argument("--batch-precond", type=float, default=0.0,
                     help="batched mode: block-diagonal preconditioner cuboid edge (nm) for every problem, 0 = none")
     ap.add_argument("--train-slabs", type=int, default=200)

@@ -95,10 +95,11 @@ typedef struct celes_options {
     int autotune;           /* 1: the first mat-vec of each precision on a handle times the
                              * candidate source-chunk splits and keeps the fastest             */
     int translation;        /* CELES_TRANSLATION_DIRECT (default) or CELES_TRANSLATION_ROTATE:
-                             * how the VALU mat-vec of single problems (celes_apply_W/M,
-                             * celes_solve, celes_apply_W_noalloc) evaluates each pair's
-                             * block; the matrix-core kernel, batches and the
-                             * preconditioner assembly always use the direct form           */
+                             * how the VALU mat-vec evaluates each pair's block, for single
+                             * problems (celes_apply_W/M, celes_solve,
+                             * celes_apply_W_noalloc) and for batches (celes_batch_create);
+                             * the matrix-core kernel and the preconditioner assembly
+                             * always use the direct form                                    */
     int deterministic;      /* 1: bitwise the same results from run to run on one device:
                              * no timing-based choice of the work split (autotune is
                              * ignored; celes_batch_autotune fails with CELES_E_STATE), every
@@ -409,7 +410,9 @@ typedef struct celes_batch celes_batch;
 /* Build a batch over nprob problems (all with the same lmax, each with its
  * incident field set).  The handles stay owned by the caller and must
  * outlive the batch; opt (precision, tol, inner_tol, restart, maxiter,
- * max_refinements, hankel) applies to the whole batch (NULL: defaults).
+ * max_refinements, hankel, translation, deterministic) applies to the whole
+ * batch (NULL: defaults); translation selects the scheme of the persistent
+ * VALU mat-vec (problems on the matrix cores use the direct form).
  * Batches are compiled for lmax <= 4.  Errors: CELES_E_ARG, CELES_E_STATE,
  * CELES_E_UNSUPPORTED, CELES_E_OOM, CELES_E_DEVICE. */
 int celes_batch_create(celes_batch** b, int nprob, celes_handle* const* probs, const celes_options* opt);

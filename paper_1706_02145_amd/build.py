@@ -81,6 +81,8 @@ def build(lmax_compiled=6, jobs=None, verbose=False, force=False):
                 for T in ("double", "float"):
                     f.write(f"template <> void wx_run_L<{T}, {L}>(const WxArgs<{T}>&, int, int, hipStream_t) {{}}\n")
                     f.write(f"template <> void wx_rtr_run_L<{T}, {L}>(const WxArgs<{T}>&, int, int, hipStream_t) {{}}\n")
+                    f.write(f"template <> void wx_rtr_batch_run_L<{T}, {L}>(const WxArgs<{T}>*, const int*, const int*, "
+                            f"const int*, int, int*, int, int, hipStream_t) {{}}\n")
                 f.write(f"template <> int wx_num_groups_L<{L}>() {{ return 1; }}\n")
                 for T in ("double", "float"):
                     f.write(f"template <> int wx_max_kb_L<{T}, {L}>() {{ return 1; }}\n")

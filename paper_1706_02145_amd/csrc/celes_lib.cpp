@@ -1860,6 +1860,8 @@ struct celes_batch {
     std::vector<int> sys0;           // [nprob+1]
     std::vector<int> sys_prob;       // [nsys]
     // mat-vec configuration (set by celes_batch_autotune or defaults)
+    // (persistent blocks of 256 threads; the rotation scheme launches twice
+    // as many blocks of 64)
     int chunk_len = 256, kb32 = 1, kb64 = 1, persist_blocks = 2048;
     // complex64 mat-vec of problems whose right-hand sides fill matrix-core blocks
     std::vector<int> mf_prob, mf_width, mf_nch;
@@ -1908,6 +1910,8 @@ bool upload(DevBuf& d, const std::vector<T>& v) {
 // chunk length / right-hand-side blocks
 int batch_configure(celes_batch* b) {
     const int G = celes::wx_num_groups(b->L);
+    const bool rot = b->opt.translation == CELES_TRANSLATION_ROTATE;
+    const int rblock = rot ? celes::WX_RTR_BLOCK_SIZE : celes::WX_BLOCK_SIZE;
     std::vector<int> nbx(b->nprob), nch(b->nprob), item32(b->nprob + 1, 0), item64(b->nprob + 1, 0);
     std::vector<int64_t> part_off(b->nprob);
     std::vector<celes::WxArgs<float>> a32(b->nprob);
@@ -1917,15 +1921,18 @@ int batch_configure(celes_batch* b) {
         celes_handle* h = b->probs[p];
         const int K = b->sys0[p + 1] - b->sys0[p];
         const int64_t N = h->N;
-        nbx[p] = (int)((N + celes::WX_BLOCK_SIZE - 1) / celes::WX_BLOCK_SIZE);
+        nbx[p] = (int)((N + rblock - 1) / rblock);
         int64_t cl = std::max<int64_t>(celes::WX_TILE_SIZE, (int64_t)b->chunk_len);
         cl = (cl + celes::WX_TILE_SIZE - 1) / celes::WX_TILE_SIZE * celes::WX_TILE_SIZE;
         nch[p] = (int)((N + cl - 1) / cl);
         part_off[p] = poff;
         poff += (int64_t)nch[p] * K * b->nmax * N;
         const int mw = mfma_width(h, K);
-        item32[p + 1] = item32[p] + (mw > 0 ? 0 : nbx[p] * nch[p] * G * (K / b->kb32));
-        item64[p + 1] = item64[p] + nbx[p] * nch[p] * G * (K / b->kb64);
+        // per (receiver tile, chunk): pass groups x right-hand-side blocks
+        // (direct) or the two polarisation passes x right-hand sides (rotation)
+        const int z32 = rot ? 2 * K : G * (K / b->kb32), z64 = rot ? 2 * K : G * (K / b->kb64);
+        item32[p + 1] = item32[p] + (mw > 0 ? 0 : nbx[p] * nch[p] * z32);
+        item64[p + 1] = item64[p] + nbx[p] * nch[p] * z64;
         auto fill = [&](auto& a) {
             a.px = h->d_px.as<double>();
             a.py = h->d_py.as<double>();
@@ -2041,10 +2048,14 @@ int batch_matvec(celes_batch* b, const cx<T>* V, const int* kstep, int kin, cx<T
     celes::bk_zero_int(b->d_counter.as<int>(), 1, s);
     celes::bk_prep<T>(g, V, b->total, kstep, kin, (cx<T>*)b->d_xsd.p, s);
     const int* item_off = (const int*)b->d_item_off.p + (f64 ? b->nprob + 1 : 0);
-    int rc = celes::wx_batch_run<T>(b->L, (const celes::WxArgs<T>*)(f64 ? b->d_args64.p : b->d_args32.p), item_off,
-                                    b->d_nbx.as<int>(), b->d_nch.as<int>(), b->nprob, b->d_counter.as<int>(),
-                                    b->persist_blocks, f64 ? b->kb64 : b->kb32,
-                                    b->opt.hankel == CELES_HANKEL_DIRECT ? 1 : 0, s);
+    const celes::WxArgs<T>* args = (const celes::WxArgs<T>*)(f64 ? b->d_args64.p : b->d_args32.p);
+    const int hmode = b->opt.hankel == CELES_HANKEL_DIRECT ? 1 : 0;
+    int rc = b->opt.translation == CELES_TRANSLATION_ROTATE
+                 ? celes::wx_rtr_batch_run<T>(b->L, args, item_off, b->d_nbx.as<int>(), b->d_nch.as<int>(), b->nprob,
+                                              b->d_counter.as<int>(), 2 * b->persist_blocks, hmode, s)
+                 : celes::wx_batch_run<T>(b->L, args, item_off, b->d_nbx.as<int>(), b->d_nch.as<int>(), b->nprob,
+                                          b->d_counter.as<int>(), b->persist_blocks, f64 ? b->kb64 : b->kb32, hmode,
+                                          s);
     if (rc != 0) return bfail(b, CELES_E_DEVICE, "batch mat-vec launch failed");
     if constexpr (sizeof(T) == 4) {
         for (size_t q = 0; q < b->mf_prob.size(); ++q) {
@@ -2231,6 +2242,8 @@ static int celes_batch_create_impl(celes_batch** out, int nprob, celes_handle* c
     b->L = probs[0]->L;
     if (b->L > 4) return bfail(nullptr, CELES_E_UNSUPPORTED, "batches are compiled for lmax <= 4");
     if (b->opt.solver != CELES_SOLVER_GMRES) return bfail(nullptr, CELES_E_UNSUPPORTED, "batches run GMRES only");
+    if (b->opt.translation != CELES_TRANSLATION_DIRECT && b->opt.translation != CELES_TRANSLATION_ROTATE)
+        return bfail(nullptr, CELES_E_ARG, "unknown translation scheme");
     b->nmax = probs[0]->nmax;
     b->half = probs[0]->half;
     b->m = std::max(1, b->opt.restart);
@@ -2361,7 +2374,9 @@ static int celes_batch_autotune_impl(celes_batch* b, int precision, double* best
     hipEventCreate(&e0);
     hipEventCreate(&e1);
     const int chunks[] = {128, 256, 512, 1024};
-    for (int kb = 1; kb <= mxkb; kb *= 2) {
+    // the rotation scheme takes one right-hand side per work item
+    const int kb_max = b->opt.translation == CELES_TRANSLATION_ROTATE ? 1 : mxkb;
+    for (int kb = 1; kb <= kb_max; kb *= 2) {
         bool divides = true;
         for (int p = 0; p < b->nprob; ++p) divides = divides && ((b->sys0[p + 1] - b->sys0[p]) % kb == 0);
         if (!divides) continue;

@@ -108,6 +108,23 @@ template int wx_batch_run<float>(int, const WxArgs<float>*, const int*, const in
                                  int, hipStream_t);
 
 template <typename T>
+int wx_rtr_batch_run(int L, const WxArgs<T>* args, const int* item_off, const int* nbx, const int* nchunk, int nprob,
+                     int* counter, int nblocks, int hmode, hipStream_t s) {
+    switch (L) {
+        case 1: wx_rtr_batch_run_L<T, 1>(args, item_off, nbx, nchunk, nprob, counter, nblocks, hmode, s); break;
+        case 2: wx_rtr_batch_run_L<T, 2>(args, item_off, nbx, nchunk, nprob, counter, nblocks, hmode, s); break;
+        case 3: wx_rtr_batch_run_L<T, 3>(args, item_off, nbx, nchunk, nprob, counter, nblocks, hmode, s); break;
+        case 4: wx_rtr_batch_run_L<T, 4>(args, item_off, nbx, nchunk, nprob, counter, nblocks, hmode, s); break;
+        default: return -1;
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+template int wx_rtr_batch_run<double>(int, const WxArgs<double>*, const int*, const int*, const int*, int, int*, int,
+                                      int, hipStream_t);
+template int wx_rtr_batch_run<float>(int, const WxArgs<float>*, const int*, const int*, const int*, int, int*, int,
+                                     int, hipStream_t);
+
+template <typename T>
 int wx_launch(const WxArgs<T>& a, int L, int hmode, int nchunk, const cx<T>* x, const cx<T>* tq,
               cx<T>* y, int epilogue, hipStream_t s, const hipEvent_t* ev, int scheme) {
     const int half = L * (L + 2);

@@ -52,6 +52,15 @@ void wx_batch_run_L(const WxArgs<T>* args, const int* item_off, const int* nbx, 
 template <typename T>
 int wx_batch_run(int L, const WxArgs<T>* args, const int* item_off, const int* nbx, const int* nchunk, int nprob,
                  int* counter, int nblocks, int kb, int hmode, hipStream_t s);
+// persistent multi-problem launcher of the rotation scheme (defined in
+// wx_rtr.hip): work items (problem, receiver tile of 64, source chunk,
+// pass x right-hand side), compiled for L <= 4 like the direct one
+template <typename T, int L>
+void wx_rtr_batch_run_L(const WxArgs<T>* args, const int* item_off, const int* nbx, const int* nchunk, int nprob,
+                        int* counter, int nblocks, int hmode, hipStream_t s);
+template <typename T>
+int wx_rtr_batch_run(int L, const WxArgs<T>* args, const int* item_off, const int* nbx, const int* nchunk, int nprob,
+                     int* counter, int nblocks, int hmode, hipStream_t s);
 // largest compiled right-hand-side block of cut-off L
 template <typename T, int L>
 int wx_max_kb_L();

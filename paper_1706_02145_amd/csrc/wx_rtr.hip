@@ -361,7 +361,66 @@ __global__ __launch_bounds__(BLOCK) void wx_rtr_kernel(WxArgs<T> a) {
         rtr_block<T, L, HMODE, -1>(a, tile, slots, blockIdx.x, blockIdx.y, k);
 }
 
+// Persistent multi-problem variant (batches): as the direct scheme's batch
+// kernel, every block repeatedly claims the next work item (problem p,
+// receiver tile, source chunk, pass x right-hand side) from a counter that
+// must be zero at launch; items of problem p are numbered
+// [item_off[p], item_off[p+1]).  Items of converged systems are skipped.
+// Every block exits once the counter passes the last item.
+template <typename T, int L, int HMODE>
+__global__ __launch_bounds__(BLOCK) void wx_rtr_batch_kernel(const WxArgs<T>* __restrict__ args,
+                                                             const int* __restrict__ item_off,
+                                                             const int* __restrict__ nbx,
+                                                             const int* __restrict__ nchunk, int nprob,
+                                                             int* __restrict__ counter) {
+    constexpr int HALF = L * (L + 2);
+    __shared__ cx<T> tile[TILE * HALF];
+    __shared__ cx<T> slots[t_in_lds<T, L>() ? HALF * BLOCK : 1];
+    __shared__ int s_item;
+    const int total = item_off[nprob];
+    while (true) {
+        __syncthreads();
+        if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
+        __syncthreads();
+        const int item = s_item;
+        if (item >= total) break;
+        int p = 0;
+        while (item_off[p + 1] <= item) ++p;
+        const int local = item - item_off[p];
+        const int bxn = nbx[p], chn = nchunk[p];
+        const int bx = local % bxn;
+        const int chunk = (local / bxn) % chn;
+        const int z = local / (bxn * chn);
+        const int k = z >> 1;
+        const WxArgs<T> a = args[p];
+        if (a.active && a.active[a.sys0 + k] == 0) continue;
+        if ((z & 1) == 0)
+            rtr_block<T, L, HMODE, 1>(a, tile, slots, bx, chunk, k);
+        else
+            rtr_block<T, L, HMODE, -1>(a, tile, slots, bx, chunk, k);
+    }
+}
+
 }  // namespace rtr
+
+template <typename T, int L>
+void wx_rtr_batch_run_L(const WxArgs<T>* args, const int* item_off, const int* nbx, const int* nchunk, int nprob,
+                        int* counter, int nblocks, int hmode, hipStream_t s) {
+    if constexpr (L > 4) {
+        return;       // batches are compiled for cut-offs up to 4
+    } else {
+        if (hmode == 0)
+            hipLaunchKernelGGL((rtr::wx_rtr_batch_kernel<T, L, 0>), dim3(nblocks), dim3(rtr::BLOCK), 0, s, args,
+                               item_off, nbx, nchunk, nprob, counter);
+        else
+            hipLaunchKernelGGL((rtr::wx_rtr_batch_kernel<T, L, 1>), dim3(nblocks), dim3(rtr::BLOCK), 0, s, args,
+                               item_off, nbx, nchunk, nprob, counter);
+    }
+}
+template void wx_rtr_batch_run_L<double, CELES_WX_L>(const WxArgs<double>*, const int*, const int*, const int*, int,
+                                                     int*, int, int, hipStream_t);
+template void wx_rtr_batch_run_L<float, CELES_WX_L>(const WxArgs<float>*, const int*, const int*, const int*, int,
+                                                    int*, int, int, hipStream_t);
 
 template <typename T, int L>
 void wx_rtr_run_L(const WxArgs<T>& a, int hmode, int nchunk, hipStream_t s) {

@@ -30,10 +30,16 @@ def _problems(names, **opts):
     return out
 
 
-def test_batch_apply_M_matches_single_problem_launches():
-    probs = _problems(["slab300_l3", "slab64_l3", "cube8_l3"])
-    print("[batch] apply_M 3 problems", flush=True)
-    bt = P.Batch([p for _, p in probs], hankel=1)     # the problems' Hankel mode
+TRANSLATIONS = [P.CELES_TRANSLATION_DIRECT, P.CELES_TRANSLATION_ROTATE]
+
+
+@pytest.mark.parametrize("translation", TRANSLATIONS)
+def test_batch_apply_M_matches_single_problem_launches(translation):
+    # the persistent kernel of either translation scheme against the
+    # single-problem launches of the same scheme
+    probs = _problems(["slab300_l3", "slab64_l3", "cube8_l3"], translation=translation)
+    print(f"[batch] apply_M 3 problems, translation {translation}", flush=True)
+    bt = P.Batch([p for _, p in probs], hankel=1, translation=translation)     # the problems' Hankel mode
     assert bt.num_systems == 8
     xs = [random_coefficients(20 + i, p.num_rhs, w.N, w.nmax) for i, (w, p) in enumerate(probs)]
     flat = np.concatenate([x.reshape(-1) for x in xs])
@@ -55,12 +61,14 @@ def test_batch_apply_M_matches_single_problem_launches():
             off += ref.size
 
 
+@pytest.mark.parametrize("translation", TRANSLATIONS)
 @pytest.mark.parametrize("precision", [P.CELES_MIXED, P.CELES_FP64])
-def test_batch_solve_matches_individual_and_dense(precision):
+def test_batch_solve_matches_individual_and_dense(precision, translation):
     names = ["slab300_l3", "slab64_l3", "cube8_l3"]
     probs = _problems(names, tol=1e-10)
-    print(f"[batch] solve precision={precision}", flush=True)
-    bt = P.Batch([p for _, p in probs], tol=1e-10, precision=precision, inner_tol=1e-4, restart=60, hankel=1)
+    print(f"[batch] solve precision={precision} translation={translation}", flush=True)
+    bt = P.Batch([p for _, p in probs], tol=1e-10, precision=precision, inner_tol=1e-4, restart=60, hankel=1,
+                 translation=translation)
     per, summ = bt.solve()
     assert summ["status"] == 0 and summ["rel_residual"] <= 1e-10
     assert all(i["rel_residual"] <= 1e-10 for i in per)
