@@ -56,6 +56,8 @@ struct MShape {
     static constexpr int HALF = L * (L + 2);
     static constexpr bool G3 = L == 3;                     // three-product form
     static constexpr int NMAT = G3 ? 3 : 1;                // operand matrices per half
+    static constexpr int NMX = G3 ? 2 : 1;                 // source matrices staged per half (Re + Im
+                                                           // of the three-product form is formed in registers)
     static constexpr int R = G3 ? (HALF + 15) / 16 * 16 : (2 * HALF + 15) / 16 * 16;   // matrix order
     static constexpr int MT = R / 16;                      // 16-row tiles
     static constexpr int KS = R / 4;                       // k-steps of 4
@@ -194,10 +196,14 @@ __global__ __launch_bounds__(256) void wx_mfma_kernel(WxMfmaArgs a) {
     constexpr int HALF = S::HALF, MT = S::MT, KS = S::KS, KQ = S::KQ, P2 = S::P2, NMAT = S::NMAT;
     constexpr int HS = S::HS, NPH = S::NPH, EC = S::EC;
     constexpr int KN = 16 * NT;                 // right-hand sides per block
-    constexpr int TS = 2;                       // sources per tile: one per half-wave in the set-up
+    constexpr int TS = 2;                       // sources per staged tile of B operands
+    // sources per set-up tile: one per lane group of GW lanes, which needs
+    // 2L + 1 Legendre-column lanes and 2L + 1 phase lanes
+    constexpr int TSU = 2 * (P2 + 1) <= 16 ? 4 : 2;
+    constexpr int GW = 64 / TSU;
     constexpr int AH = NMAT * S::MSZ;           // floats of one block's operand matrices (R x R each)
     constexpr int XM = NT * 64 * KS;            // floats of one source operand matrix (R x KN)
-    constexpr int XH = NMAT * XM;               // floats of one source half
+    constexpr int XH = S::NMX * XM;             // floats of one staged source half
     constexpr int EPL = (EC + 63) / 64;         // records per lane
     constexpr bool REGREC = EPL <= 2;           // records live in registers (lmax <= 3)
     constexpr int HT = (P2 + 1) * HS;           // complex H entries per source
@@ -205,9 +211,9 @@ __global__ __launch_bounds__(256) void wx_mfma_kernel(WxMfmaArgs a) {
     __shared__ __attribute__((aligned(16))) float s_rec[REGREC ? 4 : EC * WXM_REC];
     __shared__ __attribute__((aligned(16))) float s_x[TS * 2 * XH];
     __shared__ __attribute__((aligned(16))) float s_a[4 * 2 * AH];
-    __shared__ cx<float> s_h[4 * TS * HT];
-    __shared__ cx<float> s_ph[4 * TS * NPH];
-    __shared__ double s_pos[TS * 3];
+    __shared__ cx<float> s_h[4 * TSU * HT];
+    __shared__ cx<float> s_ph[4 * TSU * NPH];
+    __shared__ double s_pos[TSU * 3];
 
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int i = blockIdx.x * 4 + wv;
@@ -224,11 +230,11 @@ __global__ __launch_bounds__(256) void wx_mfma_kernel(WxMfmaArgs a) {
     if constexpr (!REGREC)
         for (int e = tid; e < EC * WXM_REC; e += 256) s_rec[e] = a.rec[e];
     for (int e = tid; e < 4 * 2 * AH; e += 256) s_a[e] = 0.f;          // padding rows / columns stay zero
-    for (int e = tid; e < 4 * TS * HT; e += 256) s_h[e] = {0.f, 0.f};  // p > 2L stays zero
+    for (int e = tid; e < 4 * TSU * HT; e += 256) s_h[e] = {0.f, 0.f};  // p > 2L stays zero
 
     float* const sa = s_a + wv * 2 * AH;
-    cx<float>* const shw = s_h + wv * TS * HT;
-    cx<float>* const spw = s_ph + wv * TS * NPH;
+    cx<float>* const shw = s_h + wv * TSU * HT;
+    cx<float>* const spw = s_ph + wv * TSU * NPH;
 
     // records of this lane (lmax <= 3): loaded once
     EntryRec<L> rr[REGREC ? EPL : 1];
@@ -241,10 +247,10 @@ __global__ __launch_bounds__(256) void wx_mfma_kernel(WxMfmaArgs a) {
         }
     }
 
-    // set-up lanes: half-wave g = lane / 32 serves source t0 + g of a tile;
-    // within it, lane gl = lane % 32 computes Legendre column mu = gl
-    // (gl <= 2L) or the phase e^{ik phi}, k = gl - 4L - 1 (2L < gl <= 6L + 1)
-    const int g = lane >> 5, gl = lane & 31;
+    // set-up lanes: lane group g = lane / GW serves source t0 + g of a set-up
+    // tile; within it, lane gl = lane % GW computes Legendre column mu = gl
+    // (gl <= 2L) or the phases e^{+-ik phi}, k = gl - 2L - 1 (2L < gl <= 4L + 1)
+    const int g = lane / GW, gl = lane % GW;
     float dg = 0.70710678118654752440f;
     for (int v = 1; v <= gl && v <= P2; ++v) dg *= sqrtf((2.f * v + 1.f) / (2.f * v));
     float la[P2 + 1], lb[P2 + 1];
@@ -257,7 +263,7 @@ __global__ __launch_bounds__(256) void wx_mfma_kernel(WxMfmaArgs a) {
                                    ((2.f * pf - 3.f) * (pf * pf - mf * mf)))
                            : 0.f;
     }
-    const int kph = gl - (P2 + 1) - 2 * L;
+    const int kph = gl - (P2 + 1);
 
     const double xi = active ? a.px[i] : 0.0;
     const double yi = active ? a.py[i] : 0.0;
@@ -273,23 +279,17 @@ __global__ __launch_bounds__(256) void wx_mfma_kernel(WxMfmaArgs a) {
 
     const int j0 = chunk * a.chunk_len;
     const int j1 = min(a.n, j0 + a.chunk_len);
-    for (int t0 = j0; t0 < j1; t0 += TS) {
-        const int ntile = min(TS, j1 - t0);
+    for (int t0 = j0; t0 < j1; t0 += TSU) {
+        const int nsu = min(TSU, j1 - t0);
         __syncthreads();
-        // B operands of the tile (a contiguous copy of the operand-ordered
-        // records of the prep kernel) and the tile's centres
-        {
-            const float4* src = reinterpret_cast<const float4*>(a.xb + ((size_t)blockIdx.z * a.n + t0) * 2 * XH);
-            float4* dst = reinterpret_cast<float4*>(s_x);
-            for (int idx = tid; idx < ntile * 2 * XH / 4; idx += 256) dst[idx] = src[idx];
-            if (tid < 3 * ntile) {
-                const int jj = tid / 3, c = tid % 3;
-                s_pos[tid] = (c == 0 ? a.px : c == 1 ? a.py : a.pz)[t0 + jj];
-            }
+        // centres of the set-up tile
+        if (tid < 3 * nsu) {
+            const int jj = tid / 3, c = tid % 3;
+            s_pos[tid] = (c == 0 ? a.px : c == 1 ? a.py : a.pz)[t0 + jj];
         }
         __syncthreads();
         // ---- set-up of the tile's pairs: geometry, h_p, H_p^mu = h_p P_p^mu, e^{ik phi} ----
-        if (active && g < ntile && t0 + g != i) {
+        if (active && g < nsu && t0 + g != i) {
             const double dx = xi - s_pos[3 * g], dy = yi - s_pos[3 * g + 1], dz = zi - s_pos[3 * g + 2];
             const double rho2 = dx * dx + dy * dy;
             const double r = sqrt(rho2 + dz * dz);
@@ -316,22 +316,35 @@ __global__ __launch_bounds__(256) void wx_mfma_kernel(WxMfmaArgs a) {
                 p1 = v;
                 if (gl <= P2) sh[gl * HS + p] = {hv[p].re * v, hv[p].im * v};
             }
-            const int ak = kph < 0 ? -kph : kph;
             cx<float> ep = {1.f, 0.f};
             const cx<float> e1 = {cph, sph};
 #pragma unroll
             for (int q = 1; q <= P2; ++q)
-                if (q <= ak) ep = cmul(ep, e1);
-            if (kph >= -2 * L && kph <= 2 * L)
-                spw[g * NPH + kph + 2 * L] = kph < 0 ? cx<float>{ep.re, -ep.im} : ep;
+                if (q <= kph) ep = cmul(ep, e1);
+            if (kph >= 0 && kph <= 2 * L) {
+                spw[g * NPH + 2 * L + kph] = ep;
+                if (kph > 0) spw[g * NPH + 2 * L - kph] = {ep.re, -ep.im};
+            }
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         __builtin_amdgcn_wave_barrier();
+      for (int u0 = 0; u0 < nsu; u0 += TS) {
+        const int ntile = min(TS, nsu - u0);
+        __syncthreads();
+        // B operands of the staged tile: a contiguous copy of the
+        // operand-ordered records of the prep kernel
+        {
+            const float4* src =
+                reinterpret_cast<const float4*>(a.xb + ((size_t)blockIdx.z * a.n + t0 + u0) * 2 * XH);
+            float4* dst = reinterpret_cast<float4*>(s_x);
+            for (int idx = tid; idx < ntile * 2 * XH / 4; idx += 256) dst[idx] = src[idx];
+        }
+        __syncthreads();
         for (int jj = 0; jj < ntile; ++jj) {
-            const int j = t0 + jj;
+            const int j = t0 + u0 + jj;
             if (!active || j == i) continue;
-            const cx<float>* sh = shw + jj * HT;
-            const cx<float>* sp = spw + jj * NPH;
+            const cx<float>* sh = shw + (u0 + jj) * HT;
+            const cx<float>* sp = spw + (u0 + jj) * NPH;
             // ---- reduced block entries (record pairs), lane-parallel, into the real-form operands ----
 #pragma unroll
             for (int t = 0; t < EPL; ++t) {
@@ -352,6 +365,47 @@ __global__ __launch_bounds__(256) void wx_mfma_kernel(WxMfmaArgs a) {
             // the block against operand matrix mm of the source half ----
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
+                if constexpr (S::G3) {
+                    // Re P . Re x, Im P . Im x and (Re P + Im P)(Re x + Im x):
+                    // the third source matrix is the sum of the two staged ones
+                    float af[3][KS];
+#pragma unroll
+                    for (int mm = 0; mm < 3; ++mm)
+#pragma unroll
+                        for (int q = 0; q < KQ; ++q) {
+                            const float4 v = *(const float4*)(sa + h * AH + mm * S::MSZ + lane * KS + 4 * q);
+                            af[mm][4 * q] = v.x;
+                            af[mm][4 * q + 1] = v.y;
+                            af[mm][4 * q + 2] = v.z;
+                            af[mm][4 * q + 3] = v.w;
+                        }
+                    const float* xb = s_x + (jj * 2 + h) * XH + lane * KS;
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt) {
+                        float b0[KS], b1[KS];
+#pragma unroll
+                        for (int q = 0; q < KQ; ++q) {
+                            const float4 u = *(const float4*)(xb + nt * 64 * KS + 4 * q);
+                            const float4 v = *(const float4*)(xb + XM + nt * 64 * KS + 4 * q);
+                            b0[4 * q] = u.x;
+                            b0[4 * q + 1] = u.y;
+                            b0[4 * q + 2] = u.z;
+                            b0[4 * q + 3] = u.w;
+                            b1[4 * q] = v.x;
+                            b1[4 * q + 1] = v.y;
+                            b1[4 * q + 2] = v.z;
+                            b1[4 * q + 3] = v.w;
+                        }
+#pragma unroll
+                        for (int ks = 0; ks < KS; ++ks) {
+                            acc[h][0][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[0][ks], b0[ks], acc[h][0][nt], 0, 0, 0);
+                            acc[h][1][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[1][ks], b1[ks], acc[h][1][nt], 0, 0, 0);
+                            acc[h][2][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[2][ks], b0[ks] + b1[ks],
+                                                                                 acc[h][2][nt], 0, 0, 0);
+                        }
+                    }
+                    continue;
+                }
 #pragma unroll
                 for (int mm = 0; mm < NMAT; ++mm) {
                     const float* ab = sa + h * AH + mm * S::MSZ + lane * KS;
@@ -388,6 +442,7 @@ __global__ __launch_bounds__(256) void wx_mfma_kernel(WxMfmaArgs a) {
                 }
             }
         }
+      }
     }
     if (!active) return;
     // lane holds C[16 mt + 4 (lane / 16) + t][16 nt + lane % 16]: real-form
@@ -438,14 +493,14 @@ __global__ __launch_bounds__(256) void wx_mfma_kernel(WxMfmaArgs a) {
 // real-form row k (Re of entry k < HALF, Im of entry k - HALF below 2 HALF,
 // zero padding above) of right-hand side col = 16 nt + c sits at lane
 // (k % 4) 16 + c, k-step k / 4
-// (three-product form: xb [K / KN][N][2][3][NT][64][KS], operand matrices
-// Re, Im and Re + Im of the HALF entries, row k = entry k)
+// (three-product form: xb [K / KN][N][2][2][NT][64][KS], operand matrices
+// Re and Im of the HALF entries, row k = entry k; the kernel forms Re + Im)
 template <int L, int NT>
 __global__ void wx_mfma_prep_kernel(const cx<float>* __restrict__ x0, const int* kstep, int kin, int64_t slot_stride,
                                     float* __restrict__ xb, int n, int K) {
     using S = MShape<L>;
-    constexpr int HALF = S::HALF, KS = S::KS, KN = 16 * NT, NMAT = S::NMAT;
-    constexpr int XH = NMAT * NT * 64 * KS;
+    constexpr int HALF = S::HALF, KS = S::KS, KN = 16 * NT, NMX = S::NMX;
+    constexpr int XH = NMX * NT * 64 * KS;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t total = (int64_t)(K / KN) * n * 2 * XH;
     if (t >= total) return;
@@ -456,8 +511,8 @@ __global__ void wx_mfma_prep_kernel(const cx<float>* __restrict__ x0, const int*
     r /= 64;
     const int nt = (int)(r % NT);
     r /= NT;
-    const int mm = (int)(r % NMAT);
-    r /= NMAT;
+    const int mm = (int)(r % NMX);
+    r /= NMX;
     const int h = (int)(r % 2);
     r /= 2;
     const int j = (int)(r % n);
@@ -470,7 +525,7 @@ __global__ void wx_mfma_prep_kernel(const cx<float>* __restrict__ x0, const int*
         const cx<float>* xr = x + ((size_t)col * n + j) * 2 * HALF;
         const cx<float> x1 = xr[e], x2 = xr[HALF + e];
         const cx<float> sd = h == 0 ? cx<float>{x1.re + x2.re, x1.im + x2.im} : cx<float>{x1.re - x2.re, x1.im - x2.im};
-        if constexpr (S::G3) v = mm == 0 ? sd.re : (mm == 1 ? sd.im : sd.re + sd.im);
+        if constexpr (S::G3) v = mm == 0 ? sd.re : sd.im;
         else v = k < HALF ? sd.re : sd.im;
     }
     xb[t] = v;
@@ -479,7 +534,7 @@ __global__ void wx_mfma_prep_kernel(const cx<float>* __restrict__ x0, const int*
 template <int L, int NT>
 void launch_nt(const WxMfmaArgs& a, int hmode, int nchunk, hipStream_t s, const hipEvent_t* ev) {
     using S = MShape<L>;
-    const int64_t total = (int64_t)(a.nrhs / (16 * NT)) * a.n * 2 * (S::NMAT * NT * 64 * S::KS);
+    const int64_t total = (int64_t)(a.nrhs / (16 * NT)) * a.n * 2 * (S::NMX * NT * 64 * S::KS);
     hipLaunchKernelGGL((wx_mfma_prep_kernel<L, NT>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, a.x,
                        a.kstep, a.kin, a.slot_stride, a.xb, a.n, a.nrhs);
     dim3 grid((unsigned)((a.n + 3) / 4), (unsigned)nchunk, (unsigned)(a.nrhs / (16 * NT)));
@@ -501,8 +556,9 @@ void launch_L(const WxMfmaArgs& a, int width, int hmode, int nchunk, hipStream_t
 }  // namespace
 
 size_t wx_mfma_xb_floats(int L, int64_t N, int K) {
-    // per right-hand side and source half: R rows (real form) or 3 x 16 (three-product form, lmax 3)
-    const int rows = L == 3 ? 3 * 16 : (2 * L * (L + 2) + 15) / 16 * 16;
+    // per right-hand side and source half: R rows (real form) or 2 x 16 (three-product form, lmax 3:
+    // Re and Im; the kernel forms Re + Im)
+    const int rows = L == 3 ? 2 * 16 : (2 * L * (L + 2) + 15) / 16 * 16;
     return (size_t)2 * K * N * rows;
 }
 
