@@ -54,7 +54,7 @@ namespace celes {
 // form, R = 2 HALF rounded up to 16, KS = R / 4, sits at
 // (r / 16) 64 KS + (r % 16) KS + 16 KS (c % 4) + c / 4.
 void wx_mfma_records(int L, std::vector<float>* rec) {
-    const int half = L * (L + 2), hs = 4 * L + 1, ta = L + 1, tb = L;
+    const int half = L * (L + 2), hs = celes::wxm_h_stride(L), ta = L + 1, tb = L;
     // lmax 3 uses the three-product form: complex order 15 padded to 16, one
     // offset per entry (the same in the Re, Im and Re + Im matrices)
     const bool g3 = L == 3;

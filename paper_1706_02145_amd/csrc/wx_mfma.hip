@@ -65,7 +65,7 @@ struct MShape {
     static constexpr int MSZ = MT * 64 * KS;               // floats of one operand matrix
     static constexpr int E = HALF * HALF;                  // reduced block entries
     static constexpr int P2 = 2 * L;
-    static constexpr int HS = 4 * L + 1;                   // H row stride: p = 0..4L, zero above 2L
+    static constexpr int HS = wxm_h_stride(L);             // H row stride: p = 0..2L
     static constexpr int NPH = 4 * L + 1;                  // e^{ik phi}, k = -2L..2L
     static constexpr int TA = L + 1, TB = L;               // padded term counts of A~ and B~
     static constexpr int EC = (E + L * L) / 2;             // records: entry pairs under the mirror
@@ -197,21 +197,23 @@ __global__ __launch_bounds__(256) void wx_mfma_kernel(WxMfmaArgs a) {
     constexpr int HS = S::HS, NPH = S::NPH, EC = S::EC;
     constexpr int KN = 16 * NT;                 // right-hand sides per block
     constexpr int TS = 2;                       // sources per staged tile of B operands
-    // sources per set-up tile: one per lane group of GW lanes, which needs
-    // 2L + 1 Legendre-column lanes and 2L + 1 phase lanes
-    constexpr int TSU = 2 * (P2 + 1) <= 16 ? 4 : 2;
+    // sources per set-up tile: one per lane group of GW = 64 / TSU >= 2L + 1
+    // lanes; 4 for the narrower blocks, whose occupancy larger tables would cut
+    constexpr int TSU = NT == 4 && P2 + 1 <= 8 ? 8 : 4;
     constexpr int GW = 64 / TSU;
+    static_assert(GW >= P2 + 1, "a lane group holds the 2L + 1 set-up lanes");
     constexpr int AH = NMAT * S::MSZ;           // floats of one block's operand matrices (R x R each)
     constexpr int XM = NT * 64 * KS;            // floats of one source operand matrix (R x KN)
     constexpr int XH = S::NMX * XM;             // floats of one staged source half
     constexpr int EPL = (EC + 63) / 64;         // records per lane
     constexpr bool REGREC = EPL <= 2;           // records live in registers (lmax <= 3)
     constexpr int HT = (P2 + 1) * HS;           // complex H entries per source
+    constexpr int HTAIL = P2 + 1;               // zeroed entries after the last table (reads past a row)
 
     __shared__ __attribute__((aligned(16))) float s_rec[REGREC ? 4 : EC * WXM_REC];
     __shared__ __attribute__((aligned(16))) float s_x[TS * 2 * XH];
     __shared__ __attribute__((aligned(16))) float s_a[4 * 2 * AH];
-    __shared__ cx<float> s_h[4 * TSU * HT];
+    __shared__ cx<float> s_h[4 * TSU * HT + HTAIL];
     __shared__ cx<float> s_ph[4 * TSU * NPH];
     __shared__ double s_pos[TSU * 3];
 
@@ -230,7 +232,7 @@ __global__ __launch_bounds__(256) void wx_mfma_kernel(WxMfmaArgs a) {
     if constexpr (!REGREC)
         for (int e = tid; e < EC * WXM_REC; e += 256) s_rec[e] = a.rec[e];
     for (int e = tid; e < 4 * 2 * AH; e += 256) s_a[e] = 0.f;          // padding rows / columns stay zero
-    for (int e = tid; e < 4 * TSU * HT; e += 256) s_h[e] = {0.f, 0.f};  // p > 2L stays zero
+    for (int e = tid; e < 4 * TSU * HT + HTAIL; e += 256) s_h[e] = {0.f, 0.f};
 
     float* const sa = s_a + wv * 2 * AH;
     cx<float>* const shw = s_h + wv * TSU * HT;
@@ -248,8 +250,8 @@ __global__ __launch_bounds__(256) void wx_mfma_kernel(WxMfmaArgs a) {
     }
 
     // set-up lanes: lane group g = lane / GW serves source t0 + g of a set-up
-    // tile; within it, lane gl = lane % GW computes Legendre column mu = gl
-    // (gl <= 2L) or the phases e^{+-ik phi}, k = gl - 2L - 1 (2L < gl <= 4L + 1)
+    // tile; within it, lane gl = lane % GW <= 2L computes Legendre column
+    // mu = gl and the phases e^{+-i gl phi}
     const int g = lane / GW, gl = lane % GW;
     float dg = 0.70710678118654752440f;
     for (int v = 1; v <= gl && v <= P2; ++v) dg *= sqrtf((2.f * v + 1.f) / (2.f * v));
@@ -263,7 +265,6 @@ __global__ __launch_bounds__(256) void wx_mfma_kernel(WxMfmaArgs a) {
                                    ((2.f * pf - 3.f) * (pf * pf - mf * mf)))
                            : 0.f;
     }
-    const int kph = gl - (P2 + 1);
 
     const double xi = active ? a.px[i] : 0.0;
     const double yi = active ? a.py[i] : 0.0;
@@ -289,7 +290,7 @@ __global__ __launch_bounds__(256) void wx_mfma_kernel(WxMfmaArgs a) {
         }
         __syncthreads();
         // ---- set-up of the tile's pairs: geometry, h_p, H_p^mu = h_p P_p^mu, e^{ik phi} ----
-        if (active && g < nsu && t0 + g != i) {
+        if (active && g < nsu && t0 + g != i && gl <= P2) {
             const double dx = xi - s_pos[3 * g], dy = yi - s_pos[3 * g + 1], dz = zi - s_pos[3 * g + 2];
             const double rho2 = dx * dx + dy * dy;
             const double r = sqrt(rho2 + dz * dz);
@@ -314,17 +315,15 @@ __global__ __launch_bounds__(256) void wx_mfma_kernel(WxMfmaArgs a) {
                 const float v = p == gl ? dg * pw : la[p] * ct * p1 - lb[p] * p2;
                 p2 = p1;
                 p1 = v;
-                if (gl <= P2) sh[gl * HS + p] = {hv[p].re * v, hv[p].im * v};
+                sh[gl * HS + p] = {hv[p].re * v, hv[p].im * v};
             }
             cx<float> ep = {1.f, 0.f};
             const cx<float> e1 = {cph, sph};
 #pragma unroll
             for (int q = 1; q <= P2; ++q)
-                if (q <= kph) ep = cmul(ep, e1);
-            if (kph >= 0 && kph <= 2 * L) {
-                spw[g * NPH + 2 * L + kph] = ep;
-                if (kph > 0) spw[g * NPH + 2 * L - kph] = {ep.re, -ep.im};
-            }
+                if (q <= gl) ep = cmul(ep, e1);
+            spw[g * NPH + 2 * L + gl] = ep;
+            if (gl > 0) spw[g * NPH + 2 * L - gl] = {ep.re, -ep.im};
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         __builtin_amdgcn_wave_barrier();

@@ -11,6 +11,11 @@ namespace celes {
 
 constexpr int WXM_MAX_L = 4;
 constexpr int WXM_REC = 16;   // floats per block-entry record
+// row stride of a pair's H_p^mu table (p = 0..2L).  A record reads a fixed
+// number of terms from its first H offset; the terms past a row carry zero
+// coefficients and land on the next row, the next source's table or a zeroed
+// tail of at most 2L entries, all finite.
+constexpr int wxm_h_stride(int L) { return 2 * L + 1; }
 
 struct WxMfmaArgs {
     const double* px;          // sphere centres, SoA, FP64
