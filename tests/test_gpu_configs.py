@@ -136,8 +136,10 @@ def test_slab10000_64rhs_plus_realisations_batched_mixed_to_1e6():
         probs.append(pr)
     for pr in probs:
         pr.build_preconditioner(1500.0)
+    # as the batched benchmark runs it: the realisations on the persistent
+    # rotation-scheme kernel, the 64-RHS slab on the matrix cores
     bt = P.Batch(probs, precision=P.CELES_MIXED, tol=1e-6, inner_tol=1e-3, restart=150, maxiter=600,
-                 max_refinements=4)
+                 max_refinements=4, translation=P.CELES_TRANSLATION_ROTATE)
     per, summ = bt.solve()
     print(f"[configs] batch: status {summ['status']}, worst residual {summ['rel_residual']:.2e}, "
           f"{summ['seconds']:.1f} s", flush=True)
