@@ -464,6 +464,13 @@ int gmres_device(celes_handle* h, const cx<T>* rhs, cx<T>* x, double tol, int ma
     hipEvent_t e0, e1;
     hipEventCreate(&e0);
     hipEventCreate(&e1);
+    // a failed copy or synchronisation ends the solve with CELES_E_DEVICE
+    // (the host would otherwise go on with stale values)
+    bool dev_err = false;
+    auto dev_ok = [&](hipError_t e) {
+        if (e != hipSuccess) dev_err = true;
+        return e == hipSuccess;
+    };
     bool pending = false;
     auto collect = [&]() {
         if (!pending) return;
@@ -474,8 +481,8 @@ int gmres_device(celes_handle* h, const cx<T>* rhs, cx<T>* x, double tol, int ma
     auto norm2 = [&](const cx<T>* v) -> double {
         celes::vec_dots<T>(v, 0, 1, v, n, dpart, dh, s);
         cx<double> r;
-        hipMemcpyAsync(&r, dh, sizeof(r), hipMemcpyDeviceToHost, s);
-        hipStreamSynchronize(s);
+        if (!dev_ok(hipMemcpyAsync(&r, dh, sizeof(r), hipMemcpyDeviceToHost, s)) || !dev_ok(hipStreamSynchronize(s)))
+            return std::numeric_limits<double>::quiet_NaN();
         collect();
         return std::sqrt(std::max(0.0, r.re));
     };
@@ -494,6 +501,7 @@ int gmres_device(celes_handle* h, const cx<T>* rhs, cx<T>* x, double tol, int ma
         celes::vec_sub<T>(rhs, w, V, n, s);
         double beta = norm2(V);
         out->est = beta / rhs_norm;
+        if (dev_err) break;
         if (!std::isfinite(beta)) {
             out->breakdown = true;
             break;
@@ -515,14 +523,15 @@ int gmres_device(celes_handle* h, const cx<T>* rhs, cx<T>* x, double tol, int ma
             // CGS2
             celes::vec_dots<T>(V, n, kk + 1, vk1, n, dpart, dh, s);
             celes::vec_gemv_sub<T>(V, n, kk + 1, dh, vk1, n, s);
-            hipMemcpyAsync(hh.data(), dh, (kk + 1) * sizeof(cx<double>), hipMemcpyDeviceToHost, s);
+            dev_ok(hipMemcpyAsync(hh.data(), dh, (kk + 1) * sizeof(cx<double>), hipMemcpyDeviceToHost, s));
             celes::vec_dots<T>(V, n, kk + 1, vk1, n, dpart, dh, s);
             celes::vec_gemv_sub<T>(V, n, kk + 1, dh, vk1, n, s);
-            hipMemcpyAsync(hh2.data(), dh, (kk + 1) * sizeof(cx<double>), hipMemcpyDeviceToHost, s);
+            dev_ok(hipMemcpyAsync(hh2.data(), dh, (kk + 1) * sizeof(cx<double>), hipMemcpyDeviceToHost, s));
             double hn = norm2(vk1);
             for (int i = 0; i <= kk; ++i)
                 H[(size_t)i * m + kk] = cplx(hh[i].re + hh2[i].re, hh[i].im + hh2[i].im);
             H[(size_t)(kk + 1) * m + kk] = hn;
+            if (dev_err) break;
             if (!std::isfinite(hn)) {
                 out->breakdown = true;
                 break;
@@ -548,7 +557,7 @@ int gmres_device(celes_handle* h, const cx<T>* rhs, cx<T>* x, double tol, int ma
             out->est = est;
             if (hn == 0 || est <= tol || out->iterations >= maxiter) break;
         }
-        if (rc != CELES_OK || out->breakdown) break;
+        if (rc != CELES_OK || out->breakdown || dev_err) break;
         // y = H^{-1} g (upper triangular), u = V y, x += P^{-1} u
         std::vector<cplx> y(used);
         for (int i = used - 1; i >= 0; --i) {
@@ -558,30 +567,32 @@ int gmres_device(celes_handle* h, const cx<T>* rhs, cx<T>* x, double tol, int ma
         }
         std::vector<cx<double>> yd(used);
         for (int i = 0; i < used; ++i) yd[i] = {y[i].real(), y[i].imag()};
-        hipMemcpyAsync(dh, yd.data(), used * sizeof(cx<double>), hipMemcpyHostToDevice, s);
+        dev_ok(hipMemcpyAsync(dh, yd.data(), used * sizeof(cx<double>), hipMemcpyHostToDevice, s));
         if (use_pre) {
-            hipMemsetAsync(w, 0, n * sizeof(cx<T>), s);
+            dev_ok(hipMemsetAsync(w, 0, n * sizeof(cx<T>), s));
             celes::vec_gemv_add<T>(V, n, used, dh, w, n, s);
             if ((rc = apply_pre(w, z)) != CELES_OK) break;
             // x += z : reuse gemv_add with a single "basis vector" z and coefficient 1
             cx<double> one = {1.0, 0.0};
-            hipMemcpyAsync(dh, &one, sizeof(one), hipMemcpyHostToDevice, s);
+            dev_ok(hipMemcpyAsync(dh, &one, sizeof(one), hipMemcpyHostToDevice, s));
             celes::vec_gemv_add<T>(z, n, 1, dh, x, n, s);
         } else {
             celes::vec_gemv_add<T>(V, n, used, dh, x, n, s);
         }
-        hipStreamSynchronize(s);
+        if (!dev_ok(hipStreamSynchronize(s))) break;
         out->restarts++;
         if (h->opt.verbose)
             std::fprintf(stderr, "gmres (%s) cycle %d: %d iterations, estimate %.3e\n",
                          sizeof(T) == 8 ? "fp64" : "fp32", out->restarts, out->iterations, out->est);
     }
-    if (pending) {
+    if (pending && !dev_err) {
         hipEventSynchronize(e1);
         collect();
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
+    if (dev_err && rc == CELES_OK)
+        rc = fail(h, CELES_E_DEVICE, std::string("device error during GMRES: ") + hipGetErrorString(hipGetLastError()));
     return rc;
 }
 
@@ -611,11 +622,18 @@ int bicgstab_device(celes_handle* h, const cx<T>* rhs, cx<T>* x, double tol, int
     cx<double>* dpart = h->d_partial.as<cx<double>>();
     const bool use_pre = (bool)h->pre;
     cx<double> hv[2];
-    // out[c] = V[c]^H w for c < m, V[c] = V0 + c * ldv; copied to hv
+    // a failed copy or synchronisation ends the solve with CELES_E_DEVICE
+    bool dev_err = false;
+    // out[c] = V[c]^H w for c < m, V[c] = V0 + c * ldv; copied to hv (NaN
+    // after a device error)
     auto dots = [&](const cx<T>* V0, int64_t ldv, int m, const cx<T>* w) {
         celes::vec_dots<T>(V0, ldv, m, w, n, dpart, dh, s);
-        hipMemcpyAsync(hv, dh, m * sizeof(cx<double>), hipMemcpyDeviceToHost, s);
-        hipStreamSynchronize(s);
+        if (hipMemcpyAsync(hv, dh, m * sizeof(cx<double>), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) {
+            dev_err = true;
+            const double nan = std::numeric_limits<double>::quiet_NaN();
+            for (int c = 0; c < m; ++c) hv[c] = {nan, nan};
+        }
     };
     auto cplx_of = [](cx<double> a) { return cplx(a.re, a.im); };
     auto cxd = [](cplx a) { return cx<double>{a.real(), a.imag()}; };
@@ -711,9 +729,11 @@ int bicgstab_device(celes_handle* h, const cx<T>* rhs, cx<T>* x, double tol, int
                          sizeof(T) == 8 ? "fp64" : "fp32", out->restarts, out->iterations, out->est);
         if (run_its == 0) break;
     }
-    hipStreamSynchronize(s);
+    if (hipStreamSynchronize(s) != hipSuccess) dev_err = true;
     hipEventDestroy(e0);
     hipEventDestroy(e1);
+    if (dev_err && rc == CELES_OK)
+        rc = fail(h, CELES_E_DEVICE, std::string("device error during BiCGSTAB: ") + hipGetErrorString(hipGetLastError()));
     return rc;
 }
 
@@ -755,8 +775,15 @@ double residual64(celes_handle* h, const cx<double>* rhs, const cx<double>* x, c
     celes::vec_sub<double>(rhs, h->d_w.as<cx<double>>(), r, n, s);
     celes::vec_dots<double>(r, 0, 1, r, n, h->d_partial.as<cx<double>>(), h->d_h.as<cx<double>>(), s);
     cx<double> v;
-    hipMemcpyAsync(&v, h->d_h.p, sizeof(v), hipMemcpyDeviceToHost, s);
-    hipStreamSynchronize(s);
+    if (hipMemcpyAsync(&v, h->d_h.p, sizeof(v), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+        if (*rc == CELES_OK)
+            *rc = fail(h, CELES_E_DEVICE, std::string("device error in the FP64 residual: ") +
+                                              hipGetErrorString(hipGetLastError()));
+        hipEventDestroy(e0);
+        hipEventDestroy(e1);
+        return std::numeric_limits<double>::quiet_NaN();
+    }
     float ms = 0;
     hipEventElapsedTime(&ms, e0, e1);
     *mv_sec += ms * 1e-3;
@@ -1323,6 +1350,7 @@ static int celes_solve_impl(celes_handle* h, const double* x0, double* b_out, ce
             inf.matvec_seconds += gr.matvec_seconds;
             double mv = 0;
             double r = residual64(h, drhs, dx, h->d_r.as<cx<double>>(), s, &rc, &mv) / rn;
+            if (rc != CELES_OK) return rc;
             inf.matvecs++;
             inf.matvec_seconds += mv;
             final_res = r;
@@ -1333,6 +1361,7 @@ static int celes_solve_impl(celes_handle* h, const double* x0, double* b_out, ce
             int inner_left = h->opt.maxiter;
             double mv = 0;
             double r = residual64(h, drhs, dx, h->d_r.as<cx<double>>(), s, &rc, &mv) / rn;
+            if (rc != CELES_OK) return rc;
             inf.matvecs++;
             for (int it = 0; it < h->opt.max_refinements && r > h->opt.tol && inner_left > 0; ++it) {
                 // correction problem M d = r in complex64, from d = 0
@@ -1355,6 +1384,7 @@ static int celes_solve_impl(celes_handle* h, const double* x0, double* b_out, ce
                 inner_left -= std::max(1, gr.iterations);
                 celes::vec_acc32(h->d_x32.as<cx<float>>(), dx, n, s);
                 double rnew = residual64(h, drhs, dx, h->d_r.as<cx<double>>(), s, &rc, &mv) / rn;
+                if (rc != CELES_OK) return rc;
                 inf.matvecs++;
                 inf.refinements++;
                 if (h->opt.verbose) std::fprintf(stderr, "refinement %d: residual %.3e (inner its %d)\n", it, rnew, gr.iterations);
