@@ -318,16 +318,24 @@ template <typename T>
 static int matvec_valu(celes_handle* h, const cx<T>* x, cx<T>* y, int K, int epilogue, hipStream_t s, int target,
                        bool timed, void* ext = nullptr, size_t ext_bytes = 0);
 
+// default source-chunk split: about this many blocks (receiver tiles x
+// source chunks x passes), so that the last round of resident blocks is a
+// small part of a launch.  Measured on the 20,000-sphere slab at lmax 4
+// (kernel ms at 4,096 / 32,768 blocks): direct FP64 147.6 / 144.1,
+// complex64 77.7 / 75.1; rotation scheme (one wave per block) FP64 78.7 /
+// 67.1, complex64 40.0 / 30.4; flat from there to 262,144.
+constexpr int kDefaultTargetBlocks = 32768;
+
 // source-chunk split without tuning: the environment (tests), the handle's
-// forced value, or 4096 blocks
+// forced value, or kDefaultTargetBlocks
 static int matvec_target_fixed(const celes_handle* h) {
     const char* env = std::getenv("CELES_WX_TARGET_BLOCKS");
     if (env) return std::max(1, std::atoi(env));
-    return h->target_blocks > 0 ? h->target_blocks : 4096;
+    return h->target_blocks > 0 ? h->target_blocks : kDefaultTargetBlocks;
 }
 
 // source-chunk split of the VALU mat-vec: the environment (tests), the
-// handle's forced value, the autotuned value, or 4096 blocks.  With
+// handle's forced value, the autotuned value, or kDefaultTargetBlocks.  With
 // opt.autotune the first call of each precision times the candidate splits
 // on the caller's x and y (each candidate writes y completely) and keeps the
 // fastest; not while the stream is being captured.
@@ -336,20 +344,20 @@ static int matvec_target(celes_handle* h, const cx<T>* x, cx<T>* y, int K, int e
     const char* env = std::getenv("CELES_WX_TARGET_BLOCKS");
     if (env) return std::max(1, std::atoi(env));
     if (h->target_blocks > 0) return h->target_blocks;
-    if (h->opt.deterministic) return 4096;
+    if (h->opt.deterministic) return kDefaultTargetBlocks;
     int& tuned = h->tuned_blocks[sizeof(T) == 8 ? 0 : 1];
-    if (tuned > 0 || !h->opt.autotune) return tuned > 0 ? tuned : 4096;
+    if (tuned > 0 || !h->opt.autotune) return tuned > 0 ? tuned : kDefaultTargetBlocks;
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-    if (hipStreamIsCapturing(s, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone) return 4096;
+    if (hipStreamIsCapturing(s, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone) return kDefaultTargetBlocks;
     hipEvent_t e0, e1;
-    if (hipEventCreate(&e0) != hipSuccess) return 4096;
+    if (hipEventCreate(&e0) != hipSuccess) return kDefaultTargetBlocks;
     if (hipEventCreate(&e1) != hipSuccess) {
         hipEventDestroy(e0);
-        return 4096;
+        return kDefaultTargetBlocks;
     }
     float best = 1e30f;
-    int best_t = 4096;
-    for (int t : {1024, 2048, 4096, 8192, 16384}) {
+    int best_t = kDefaultTargetBlocks;
+    for (int t : {4096, 8192, 16384, 32768, 65536, 131072}) {
         if (matvec_valu<T>(h, x, y, K, epilogue, s, t, false) != CELES_OK) continue;   // warm
         hipEventRecord(e0, s);
         const int rc = matvec_valu<T>(h, x, y, K, epilogue, s, t, false);
