@@ -348,9 +348,17 @@ __device__ __forceinline__ void rtr_block(const WxArgs<T>& a, cx<T>* tile, cx<T>
     for (int c = 0; c < HALF; ++c) out[(size_t)(PASS * HALF + c) * a.ldp + i] = y[c];
 }
 
+// waves per SIMD the compiler must leave room for: three for the complex64
+// kernel at lmax 4 (168 VGPRs and 36 B of spill per lane instead of 240
+// VGPRs: 28.0 vs 29.2 ms per W x on the 20,000-sphere slab, same bits);
+// elsewhere no constraint (lmax 5-6 measured slower with it)
+template <typename T, int L>
+constexpr int rtr_min_waves() { return sizeof(T) == 4 && L == 4 ? 3 : 1; }
+
 // grid: (receiver tiles, source chunks, 2 passes x right-hand sides)
 template <typename T, int L, int HMODE>
-__global__ __launch_bounds__(BLOCK) void wx_rtr_kernel(WxArgs<T> a) {
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(rtr_min_waves<T, L>())))
+void wx_rtr_kernel(WxArgs<T> a) {
     constexpr int HALF = L * (L + 2);
     __shared__ cx<T> tile[TILE * HALF];
     __shared__ cx<T> slots[t_in_lds<T, L>() ? HALF * BLOCK : 1];
