@@ -400,6 +400,12 @@ static int matvec_valu(celes_handle* h, const cx<T>* x, cx<T>* y, int K, int epi
     nchunk = std::max<int64_t>(1, std::min<int64_t>(nchunk, (N + celes::WX_TILE_SIZE - 1) / celes::WX_TILE_SIZE));
     const size_t vec_bytes = (size_t)K * N * h->nmax * sizeof(cx<T>);     // one [K][N][nmax] vector
     const size_t xsd_bytes = (vec_bytes + 255) / 256 * 256;
+    // the partial sums hold nchunk vectors: at most 2 GiB of them, but never
+    // fewer chunks than a 4,096-block split would take (the partial sums of a
+    // split of T blocks come to about T x 256 x nmax x element bytes x (RHS
+    // per block) / (pass groups), whatever N and K)
+    const int64_t cap = std::max<int64_t>((4096 + nbx - 1) / nbx, (int64_t)(((size_t)2 << 30) / vec_bytes));
+    nchunk = std::max<int64_t>(1, std::min(nchunk, cap));
     if (ext) {
         const size_t fit = ext_bytes > xsd_bytes ? (ext_bytes - xsd_bytes) / vec_bytes : 0;
         if (fit < 1)
