@@ -272,8 +272,11 @@ int celes_subsystem_guess(celes_handle* h, int64_t n_sub, const int64_t* idx, do
  * W evaluated on the fly per sphere pair (Section 3.2.2).  precision
  * CELES_FP64: x_dev, y_dev are complex128 [K][N][nmax]; CELES_MIXED:
  * complex64.  Enqueued on `stream` (a hipStream_t; NULL = default stream),
- * asynchronous.  x_dev and y_dev must not alias.  Errors: CELES_E_ARG,
- * CELES_E_DEVICE, CELES_E_OOM (scratch). */
+ * asynchronous.  x_dev and y_dev must not alias.  The handle keeps a device
+ * scratch, allocated on first use and reused: one [K][N][nmax] vector of
+ * source sums/differences plus the source-chunk partial sums (at most 2 GiB
+ * on the VALU path, unless even a split of about 4,096 blocks needs more).
+ * Errors: CELES_E_ARG, CELES_E_DEVICE, CELES_E_OOM (scratch). */
 int celes_apply_W(celes_handle* h, int precision, int K, const void* x_dev, void* y_dev,
                   void* stream);
 
