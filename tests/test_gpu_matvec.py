@@ -210,3 +210,23 @@ def test_deterministic_option_fixes_the_split():
     bt = P.Batch([det], deterministic=1)
     with pytest.raises(P.CelesError):
         bt.autotune(P.CELES_FP64)
+
+
+@pytest.mark.parametrize("translation", [P.CELES_TRANSLATION_DIRECT, P.CELES_TRANSLATION_ROTATE])
+def test_autotuned_split_keeps_parity(translation):
+    # opt.autotune times the candidate splits on the first mat-vec of each
+    # precision (every candidate writes y completely); whichever split it
+    # keeps, W x equals a plain handle's up to summation order and the
+    # oracle's rows
+    w = workload("slab300_l3")
+    x = random_coefficients(109, 1, w.N, w.nmax)[0]
+    plain = make_problem(w, hankel=0, translation=translation)
+    tuned = make_problem(w, hankel=0, translation=translation, autotune=1)
+    y0 = _gpu_W(plain, x)
+    for _ in range(2):
+        y = _gpu_W(tuned, x)
+        assert rel(y, y0) <= 1e-13
+        assert rel(_gpu_W(tuned, x, precision=P.CELES_MIXED), y0) <= 1e-5
+    rows = [0, 150, 299]
+    ref = apply_W_rows(w.positions, x, k_of(w), w.lmax, rows, hankel=oracle_lut(w))
+    assert rel(y[rows], ref) <= 1e-12
