@@ -10,7 +10,7 @@ import math
 import numpy as np
 import scipy.linalg as sla
 
-from .translation import coupling_matrix, nmax_of
+from .translation import coupling_matrix
 from .mie import T_vector
 
 

@@ -13,8 +13,6 @@ and its incident coefficients.  Two bounds are applied to the sampled rows S:
     (rows where the right-hand side is large: the beam core for a Gaussian
     beam, any rows for a plane wave).
 """
-import math
-
 import numpy as np
 import pytest
 

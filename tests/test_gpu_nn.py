@@ -6,7 +6,7 @@ import pytest
 
 import paper_1706_02145_amd as P
 from celes_inputs import workload
-from oracle.mlp import forward_backward, unpack, dims
+from oracle.mlp import forward_backward, unpack
 from tests.gpu_helpers import rel
 
 pytestmark = pytest.mark.gpu

@@ -9,7 +9,7 @@ import math
 import numpy as np
 import pytest
 
-from oracle.rotation import basis_rotation, basis_rotation_l, pair_angles, translation_matrix_rtr, wigner_small_d
+from oracle.rotation import basis_rotation, basis_rotation_l, translation_matrix_rtr, wigner_small_d
 from oracle.special import legendre
 from oracle.svwf import svwf
 from oracle.translation import idx, multi_indices, translation_matrix

@@ -13,10 +13,8 @@ import math
 import numpy as np
 import pytest
 
-from oracle.special import legendre
 from oracle.svwf import svwf
-from oracle.translation import (a5, b5, coupling_matrix, idx, multi_indices, translation_matrix,
-                                translation_blocks)
+from oracle.translation import a5, b5, coupling_matrix, idx, multi_indices, translation_matrix
 from oracle.lut import HankelLUT, lut_grid
 from oracle.special import sph_h1
 from scipy.special import spherical_jn, spherical_yn
