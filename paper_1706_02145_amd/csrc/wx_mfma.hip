@@ -280,6 +280,22 @@ __global__ __launch_bounds__(256) void wx_mfma_kernel(WxMfmaArgs a) {
 
     const int j0 = chunk * a.chunk_len;
     const int j1 = min(a.n, j0 + a.chunk_len);
+    // B operands of a staged tile (TS sources, a contiguous run of the
+    // prep kernel's operand-ordered records).  For 64-wide blocks they pass
+    // through registers: the next tile's are loaded while the current
+    // tile's products run (the narrower blocks would lose a wave of
+    // occupancy to the registers and copy directly)
+    constexpr bool PREFETCH = NT == 4;
+    constexpr int XQ = TS * 2 * XH / 4;         // float4 of a full staged tile
+    constexpr int QPT = PREFETCH ? (XQ + 255) / 256 : 1;
+    static_assert((2 * XH) % 4 == 0, "a source's operands are whole float4");
+    float4 pre[QPT];
+    if (PREFETCH && j0 < j1) {
+        const int nq = min(TS, j1 - j0) * 2 * XH / 4;
+        const float4* src = reinterpret_cast<const float4*>(a.xb + ((size_t)blockIdx.z * a.n + j0) * 2 * XH);
+#pragma unroll
+        for (int q = 0; q < QPT; ++q) pre[q] = tid + 256 * q < nq ? src[tid + 256 * q] : float4{0.f, 0.f, 0.f, 0.f};
+    }
     for (int t0 = j0; t0 < j1; t0 += TSU) {
         const int nsu = min(TSU, j1 - t0);
         __syncthreads();
@@ -330,15 +346,31 @@ __global__ __launch_bounds__(256) void wx_mfma_kernel(WxMfmaArgs a) {
       for (int u0 = 0; u0 < nsu; u0 += TS) {
         const int ntile = min(TS, nsu - u0);
         __syncthreads();
-        // B operands of the staged tile: a contiguous copy of the
-        // operand-ordered records of the prep kernel
+        // B operands of the staged tile (fetched during the previous tile)
         {
-            const float4* src =
-                reinterpret_cast<const float4*>(a.xb + ((size_t)blockIdx.z * a.n + t0 + u0) * 2 * XH);
             float4* dst = reinterpret_cast<float4*>(s_x);
-            for (int idx = tid; idx < ntile * 2 * XH / 4; idx += 256) dst[idx] = src[idx];
+            const int nq = ntile * 2 * XH / 4;
+            if constexpr (PREFETCH) {
+#pragma unroll
+                for (int q = 0; q < QPT; ++q) {
+                    const int idx = tid + 256 * q;
+                    if (idx < nq) dst[idx] = pre[q];
+                }
+            } else {
+                const float4* src =
+                    reinterpret_cast<const float4*>(a.xb + ((size_t)blockIdx.z * a.n + t0 + u0) * 2 * XH);
+                for (int idx = tid; idx < nq; idx += 256) dst[idx] = src[idx];
+            }
         }
         __syncthreads();
+        if (PREFETCH && t0 + u0 + TS < j1) {
+            const int s0 = t0 + u0 + TS;
+            const int nq = min(TS, j1 - s0) * 2 * XH / 4;
+            const float4* src = reinterpret_cast<const float4*>(a.xb + ((size_t)blockIdx.z * a.n + s0) * 2 * XH);
+#pragma unroll
+            for (int q = 0; q < QPT; ++q)
+                pre[q] = tid + 256 * q < nq ? src[tid + 256 * q] : float4{0.f, 0.f, 0.f, 0.f};
+        }
         for (int jj = 0; jj < ntile; ++jj) {
             const int j = t0 + u0 + jj;
             if (!active || j == i) continue;
